@@ -1,0 +1,224 @@
+/*
+ * mixlu.h -- C ABI of the MI355X (gfx950) mixed-precision dense solver.
+ *
+ * Method: Baboulin, Buttari, Dongarra, Kurzak, Langou, Langou, Luszczek,
+ * Tomov, "Accelerating Scientific Computations with Mixed Precision
+ * Algorithms" (arXiv:0808.2794), Algorithm 1 ("Mixed precision, Iterative
+ * Refinement for Direct Solvers", Section 2.1): factor PA = LU in a low
+ * precision eps_s, solve Ly = Pb, Ux_0 = y in eps_s, then repeat
+ * r = b - A x (eps_d = FP64, with the original A), solve for the
+ * correction z in eps_s, x = x + z in eps_d, until the stopping test of
+ * Section 3 holds.  The symmetric positive definite variant replaces the LU
+ * by a Cholesky factorization (SPOTRF/SPOTRS, Section 3.1.1).  When
+ * refinement cannot converge (condition number above the inverse of the
+ * low precision, Section 4) the solver falls back to an FP64 factorization.
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ * - Matrices are ROW-MAJOR by default: element (i, j) of an n x n matrix
+ *   with leading dimension lda is A[i*lda + j] (lda >= n).  With
+ *   opts->layout = MIXLU_COL_MAJOR the same pointers are read column-major
+ *   (element (i, j) at A[i + j*lda]).  Right-hand sides B and solutions X
+ *   are n x nrhs, row-major, leading dimension ldb/ldx >= nrhs (column-major
+ *   with ldb/ldx >= n under MIXLU_COL_MAJOR).
+ * - Every pointer documented as "device" is device memory of the context's
+ *   GPU.  The caller owns all buffers (A, B, X, ipiv, work); the library
+ *   allocates nothing that outlives a call except the context itself.
+ * - A is never modified: factors live in the caller's workspace.
+ * - Return value: MIXLU_OK (0), -i when argument i (1-based) is invalid, or a
+ *   positive MIXLU_ERR_* code for runtime failures.  Numerical outcomes
+ *   (singular matrix, fallback taken, iteration counts) are reported through
+ *   `info` and mixlu_report, never through the return value.
+ * - Work is enqueued on the context's stream (hipStream_t passed as void*).
+ *   Calls that return a mixlu_report or an info value synchronize that
+ *   stream before returning; the others are asynchronous.
+ * - The library is built for gfx950 only; mixlu_create fails with
+ *   MIXLU_ERR_UNSUPPORTED_ARCH on any other device.
+ */
+#ifndef MIXLU_H
+#define MIXLU_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status */
+#define MIXLU_OK 0
+#define MIXLU_ERR_HIP 1             /* a HIP runtime call failed          */
+#define MIXLU_ERR_WORKSPACE 2       /* lwork smaller than required        */
+#define MIXLU_ERR_NOT_IMPLEMENTED 3 /* valid request this build lacks     */
+#define MIXLU_ERR_UNSUPPORTED_ARCH 4
+#define MIXLU_ERR_DEVICE_TIMEOUT 5  /* a bounded cross-workgroup wait on the
+                                       device gave up (results invalid)   */
+
+/* Human-readable name of a status code (static string, never NULL). */
+const char *mixlu_status_string(int status);
+
+/* ------------------------------------------------------- precisions */
+/* Precision of the factorization (eps_s of Algorithm 1).  For BF16, FP16
+   and FP8 the factors are stored in FP32 and only the operands of the
+   trailing-matrix update are rounded to that format (FP32 accumulation);
+   the panel, the triangular updates and the triangular solves run in FP32. */
+typedef enum {
+    MIXLU_FP64 = 0,
+    MIXLU_FP32 = 1,
+    MIXLU_BF16 = 2,
+    MIXLU_FP16 = 3,
+    MIXLU_FP8 = 4 /* OCP e4m3, power-of-two per-tile scales */
+} mixlu_prec;
+
+typedef enum { MIXLU_ROW_MAJOR = 0, MIXLU_COL_MAJOR = 1 } mixlu_layout;
+
+/* ----------------------------------------------------------- options */
+typedef struct {
+    int itermax;      /* refinement iterations before declaring failure;
+                         default 30 (Section 4: 30 means failure)            */
+    int equilibrate;  /* -1 automatic (on for BF16/FP16/FP8), 0 off, 1 on:
+                         power-of-two row then column scaling of the
+                         low-precision copy only                            */
+    int fallback;     /* 1 (default): on failure factor in FP64 and refine  */
+    int nb;           /* outer block width of the factorization, 0 = auto   */
+    int layout;       /* mixlu_layout of A, B and X                          */
+    double stall;     /* stall ratio: refinement is declared stalled when
+                         ||r_k|| >= stall * ||r_{k-1}|| twice in a row
+                         (k >= 2) or ||r_k|| >= ||r_{k-1}|| once (k >= 3);
+                         default 0.9                                         */
+    int reserved[6];
+} mixlu_opts;
+
+/* Fill *o with the defaults listed above. */
+void mixlu_default_opts(mixlu_opts *o);
+
+/* ------------------------------------------------------------ report */
+/* Outcome of one solve (host memory, filled before the call returns). */
+typedef struct {
+    int iter;      /* >= 0: refinement corrections applied by the
+                      low-precision path (x_0 counts as 0).
+                      With prec = MIXLU_FP64 requested, the corrections
+                      of the FP64 refinement itself.
+                      < 0: the FP64 fallback produced X, for the reason
+                      -1 A is exactly singular (see info; X undefined),
+                      -2 overflow or non-finite value converting A,
+                      -3 zero or non-finite pivot in the low-precision
+                         factor (Cholesky: non-positive pivot),
+                      -4 refinement stalled,
+                      -(itermax+1) no convergence within itermax.        */
+    int info;      /* 0, or k+1 when the FP64 factorization met an exactly
+                      zero pivot in column k (A singular; X undefined)     */
+    int prec;      /* mixlu_prec of the factors that produced X           */
+    int fallback_iter; /* corrections applied by the FP64 refinement      */
+    double anorm;  /* ||A||_inf                                          */
+    double rnorm;  /* max over columns of ||b - A x||_inf (FP64, final x) */
+    double xnorm;  /* max over columns of ||x||_inf                       */
+    double berr;   /* max over columns of ||r|| / (||A|| ||x||)           */
+    int converged; /* 1 when every column meets the stopping test
+                      ||r||_inf <= sqrt(n) 2^-53 ||A||_inf ||x||_inf       */
+    int reserved[3];
+} mixlu_report;
+
+/* ----------------------------------------------------------- context */
+typedef struct mixlu_ctx_s *mixlu_ctx_t;
+
+/* Create a context on the current HIP device, bound to `stream`
+   (a hipStream_t; NULL = the default stream).  Fails on non-gfx950. */
+int mixlu_create(mixlu_ctx_t *ctx, void *stream);
+int mixlu_destroy(mixlu_ctx_t ctx);
+int mixlu_set_stream(mixlu_ctx_t ctx, void *stream);
+
+/* --------------------------------------------------------- workspace */
+typedef enum {
+    MIXLU_OP_GESV = 0,  /* mixlu_dxgesv, or mixlu_getrf + getrs/refine      */
+    MIXLU_OP_POSV = 1,  /* mixlu_dxposv, or mixlu_potrf + getrs/refine      */
+    MIXLU_OP_DGESV = 2  /* mixlu_dgesv (FP64 LU, no refinement)             */
+} mixlu_op;
+
+/* Bytes of device workspace the operation needs for (prec, n, nrhs) with
+   options o (NULL = defaults).  The workspace holds the factors, pivots,
+   scales, refinement vectors, device-side exchange buffers and, when
+   o->fallback is set, room for the FP64 fallback factor (8 n^2 bytes). */
+int mixlu_workspace_size(mixlu_ctx_t ctx, int op, int prec, int n, int nrhs,
+                         const mixlu_opts *o, size_t *bytes);
+
+/* ----------------------------------------------------------- factors */
+/* Description of factors that live inside a caller workspace.  Filled by
+   mixlu_getrf / mixlu_potrf; valid while the workspace is unchanged. */
+typedef struct {
+    int n, npad;       /* order, and padded order of the stored factor     */
+    int nb;            /* outer block width used by the factorization       */
+    int prec;          /* mixlu_prec of the factorization                  */
+    int kind;          /* 0 LU with partial pivoting, 1 Cholesky (lower)   */
+    int layout;        /* layout of the A it was computed from             */
+    int equilibrated;  /* 1 when R, C scaling was applied                  */
+    int lowp_status;   /* 0 ok; -2 conversion overflow; -3 breakdown       */
+    int nrhs_max;      /* right-hand sides the workspace was sized for     */
+    void *work;        /* the workspace (device)                           */
+    size_t lwork;
+    size_t off[16];    /* internal offsets into work                       */
+} mixlu_factor;
+
+/* Factor A (device, n x n, const) in precision prec (Algorithm 1 step 1):
+   ||A||_inf, optional equilibration, conversion to the working format and
+   blocked LU with partial pivoting on the GPU.  *info (host) receives 0, or
+   k+1 for an exact zero pivot in column k when prec = MIXLU_FP64.  Low-
+   precision breakdown or overflow is recorded in F->lowp_status instead.
+   Synchronizes the stream. */
+int mixlu_getrf(mixlu_ctx_t ctx, int prec, int n, const double *A, int lda,
+                void *work, size_t lwork, const mixlu_opts *o,
+                mixlu_factor *F, int *info);
+
+/* Cholesky A = L L^T of a symmetric positive definite A (lower triangle of
+   the row-major A is read; SPOTRF of Section 3.1.1). */
+int mixlu_potrf(mixlu_ctx_t ctx, int prec, int n, const double *A, int lda,
+                void *work, size_t lwork, const mixlu_opts *o,
+                mixlu_factor *F, int *info);
+
+/* Low-precision solve only (Algorithm 1 steps 2-3): X = op(A)^{-1} B with
+   the stored factors, computed in the factor's precision and promoted to
+   FP64.  trans = 1 solves A^T X = B.  B, X device, n x nrhs. */
+int mixlu_getrs(mixlu_ctx_t ctx, const mixlu_factor *F, int trans, int nrhs,
+                const double *B, int ldb, double *X, int ldx);
+
+/* Refinement loop (Algorithm 1 steps 4-7) starting from the X given:
+   r = B - op(A) X in FP64 with the original A, correction solved with the
+   factors, X += Z in FP64, until the stopping test holds for every column
+   or the policy declares failure (then, when o->fallback is set, an FP64
+   factorization in the workspace finishes the job).  rep (host) is filled;
+   the stream is synchronized. */
+int mixlu_refine(mixlu_ctx_t ctx, mixlu_factor *F, int trans, const double *A,
+                 int lda, const double *B, int ldb, double *X, int ldx,
+                 const mixlu_opts *o, mixlu_report *rep);
+
+/* One-shot mixed-precision solve A X = B (DSGESV-style): factor in prec,
+   x_0, refinement, FP64 fallback.  A, B (const) and X are device memory. */
+int mixlu_dxgesv(mixlu_ctx_t ctx, int prec, int n, int nrhs, const double *A,
+                 int lda, const double *B, int ldb, double *X, int ldx,
+                 void *work, size_t lwork, const mixlu_opts *o,
+                 mixlu_report *rep);
+
+/* Same for symmetric positive definite A (DSPOSV-style, Cholesky). */
+int mixlu_dxposv(mixlu_ctx_t ctx, int prec, int n, int nrhs, const double *A,
+                 int lda, const double *B, int ldb, double *X, int ldx,
+                 void *work, size_t lwork, const mixlu_opts *o,
+                 mixlu_report *rep);
+
+/* FP64 LU with partial pivoting and FP64 triangular solves, no refinement
+   (the DGESV comparator, and the factorization the fallback uses).
+   A is const; *info (host) as in mixlu_getrf.  Synchronizes. */
+int mixlu_dgesv(mixlu_ctx_t ctx, int n, int nrhs, const double *A, int lda,
+                const double *B, int ldb, double *X, int ldx, void *work,
+                size_t lwork, int *info);
+
+/* Adjoint helper: GA = GA_beta * GA + alpha * Gb * X^T (all device, FP64,
+   row-major; Gb and X are n x nrhs, GA is n x n).  With alpha = -1 and
+   GA_beta = 0 this forms the gradient g_A = -g_b x^T of x = A^{-1} b. */
+int mixlu_outer_update(mixlu_ctx_t ctx, int n, int nrhs, const double *Gb,
+                       int ldg, const double *X, int ldx, double *GA, int ldga,
+                       double alpha, double GA_beta);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MIXLU_H */

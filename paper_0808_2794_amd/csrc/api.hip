@@ -1,0 +1,711 @@
+// C ABI of libmixlu: argument checking, workspace layout and the host-side
+// sequencing of Algorithm 1 (mixed-precision iterative refinement for direct
+// solvers, Section 2.1) over the HIP kernels.  Every floating-point step
+// runs on the GPU; the host only enqueues kernels and, once per refinement
+// iteration, reads the per-column norms (a few bytes) to apply the stopping
+// test of Section 3 and the failure policy (30 iterations mean failure,
+// Section 4; fall back to FP64 when refinement cannot converge).
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+
+using namespace mixlu;
+
+struct mixlu_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    double *hbuf = nullptr;  // pinned host mirror of the norms / status
+    size_t hbuf_bytes = 0;
+};
+
+namespace {
+
+constexpr double kEpsD = 0x1p-53;
+
+#define HIPCK(x)                                    \
+    do {                                            \
+        hipError_t e_ = (x);                        \
+        if (e_ != hipSuccess) return MIXLU_ERR_HIP; \
+    } while (0)
+#define RETCK(x)                        \
+    do {                                \
+        int r_ = (x);                   \
+        if (r_ != MIXLU_OK) return r_;  \
+    } while (0)
+
+int auto_nb(int n) {
+    const int n64 = round_up(n > 0 ? n : 1, 64);
+    if (n64 <= 128) return 64;
+    if (n64 <= 512) return 128;
+    if (n64 <= 2048) return 256;
+    return 512;
+}
+
+bool is_lowp(int prec) { return prec == MIXLU_BF16 || prec == MIXLU_FP16; }
+bool prec_valid(int prec) {
+    return prec == MIXLU_FP64 || prec == MIXLU_FP32 || prec == MIXLU_BF16 || prec == MIXLU_FP16;
+}
+
+template <typename T> T *at(void *work, size_t off) {
+    return reinterpret_cast<T *>(static_cast<char *>(work) + off);
+}
+
+int ensure_hbuf(mixlu_ctx_s *ctx, size_t bytes) {
+    if (ctx->hbuf_bytes >= bytes) return MIXLU_OK;
+    if (ctx->hbuf) (void)hipHostFree(ctx->hbuf);
+    ctx->hbuf = nullptr;
+    ctx->hbuf_bytes = 0;
+    HIPCK(hipHostMalloc(reinterpret_cast<void **>(&ctx->hbuf), bytes, hipHostMallocDefault));
+    ctx->hbuf_bytes = bytes;
+    return MIXLU_OK;
+}
+
+}  // namespace
+
+size_t mixlu::plan_layout(Layout &L, int op, int prec, int n, int nrhs, const mixlu_opts &o) {
+    L.n = n;
+    L.nrhs = nrhs < 1 ? 1 : nrhs;
+    L.prec = (op == MIXLU_OP_DGESV) ? MIXLU_FP64 : prec;
+    L.kind = (op == MIXLU_OP_POSV) ? 1 : 0;
+    L.nb = o.nb > 0 ? o.nb : auto_nb(n);
+    L.npad = round_up(n > 0 ? n : 1, L.nb);
+    L.fallback = (L.prec != MIXLU_FP64) && o.fallback;
+    const size_t np = (size_t)L.npad;
+    const size_t wbytes = np * np * (L.prec == MIXLU_FP64 ? 8 : 4);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at_ = off;
+        off = align_up(off + bytes, 256);
+        return at_;
+    };
+    L.W = take(wbytes);
+    L.W64 = L.fallback ? take(np * np * 8) : 0;
+    const size_t pk = is_lowp(L.prec) ? np * L.nb * 2 : 0;
+    L.Ap = take(pk);
+    L.Bp = take(pk);
+    L.ipiv = take(np * 4);
+    L.perm = take(np * 4);
+    L.perm2 = take(np * 4);
+    L.R = take(np * 8);
+    L.C = take(np * 8);
+    L.vec_r = take(np * L.nrhs * 8);
+    L.vec_y = take(np * L.nrhs * 8);
+    L.xbuf = take((size_t)2 * (kPanelMaxWG * (3 + kPanelBF * 2) + kPanelBF * 2) * 8);
+    L.ybuf = take((np * kTrsvNRT * 2 + 64) * 8);
+    L.moves = take((size_t)(4 + 2 * 1024) * 4);
+    L.tmp = take((size_t)(2 * kColChunks + 2) * np * 8);
+    L.status = take(ST_COUNT * 4);
+    L.norms = take((size_t)(4 + 3 * L.nrhs) * 8);
+    L.total = off;
+    return off;
+}
+
+namespace {
+
+void fill_factor(mixlu_factor *F, const Layout &L, void *work, size_t lwork, int layout) {
+    std::memset(F, 0, sizeof(*F));
+    F->n = L.n;
+    F->npad = L.npad;
+    F->nb = L.nb;
+    F->prec = L.prec;
+    F->kind = L.kind;
+    F->layout = layout;
+    F->nrhs_max = L.nrhs;
+    F->work = work;
+    F->lwork = lwork;
+    const size_t offs[16] = {L.W, L.W64, L.Ap, L.Bp, L.ipiv, L.perm, L.perm2, L.R,
+                             L.C, L.vec_r, L.vec_y, L.xbuf, L.ybuf, L.moves, L.tmp, L.status};
+    std::memcpy(F->off, offs, sizeof(offs));
+}
+
+// Rebuild the layout from a factor description.
+Layout layout_of(const mixlu_factor *F) {
+    Layout L{};
+    L.n = F->n;
+    L.npad = F->npad;
+    L.nb = F->nb;
+    L.prec = F->prec;
+    L.kind = F->kind;
+    L.nrhs = F->nrhs_max;
+    L.W = F->off[0];
+    L.W64 = F->off[1];
+    L.fallback = F->off[1] != 0;
+    L.Ap = F->off[2];
+    L.Bp = F->off[3];
+    L.ipiv = F->off[4];
+    L.perm = F->off[5];
+    L.perm2 = F->off[6];
+    L.R = F->off[7];
+    L.C = F->off[8];
+    L.vec_r = F->off[9];
+    L.vec_y = F->off[10];
+    L.xbuf = F->off[11];
+    L.ybuf = F->off[12];
+    L.moves = F->off[13];
+    L.tmp = F->off[14];
+    L.status = F->off[15];
+    // norms follow status (same rule as plan_layout)
+    L.norms = align_up(L.status + ST_COUNT * 4, 256);
+    return L;
+}
+
+// Blocked right-looking LU with partial pivoting of W (npad x npad, ld = npad)
+// in place: per outer block of nb columns, panels of B columns (GEPP with
+// pivot search), their row interchanges on the rest of the outer block, the
+// triangular solve and FP32/FP64 update inside the block; then the
+// interchanges on the other columns, U12 = L11^{-1} A12 and the trailing
+// update A22 -= L21 U12 (in FP32/FP64, or with BF16/FP16 operands on MFMA).
+template <typename T>
+int factor_lu(hipStream_t s, void *work, const Layout &L, size_t woff, int trail_prec) {
+    constexpr int B = sizeof(T) == 4 ? kPanelBF : kPanelBD;
+    const int np = L.npad, nb = L.nb;
+    T *W = at<T>(work, woff);
+    int *ipiv = at<int>(work, L.ipiv);
+    int *perm = at<int>(work, L.perm);
+    int *moves = at<int>(work, L.moves);
+    int *status = at<int>(work, L.status);
+    auto *xbuf = at<unsigned long long>(work, L.xbuf);
+    if (nb % B || nb % 64 || nb > 512) return MIXLU_ERR_NOT_IMPLEMENTED;
+    HIPCK(launch_iota(perm, np, s));
+    HIPCK(launch_fill_u32(reinterpret_cast<unsigned *>(xbuf), 0u,
+                          (size_t)2 * (kPanelMaxWG * (3 + kPanelBF * 2) + kPanelBF * 2) * 2, s));
+    auto Wp = [&](int r, int c) { return W + (size_t)r * np + c; };
+    for (int K0 = 0; K0 < np; K0 += nb) {
+        const int kend = K0 + nb;
+        for (int k = K0; k < kend; k += B) {
+            HIPCK(launch_panel<T>(W, np, k, np - k, ipiv, xbuf, status, s));
+            HIPCK(launch_perm_build(ipiv, k, B, np, perm, moves, s));
+            HIPCK(launch_rows_move<T>(W, np, np, moves, 2 * B, K0, kend, k, k + B, s));
+            if (k + B < kend) {
+                HIPCK(launch_trsm_diag<T>(Wp(k, k), np, Wp(k, k + B), np, kend - k - B, s));
+                HIPCK(launch_gemm<T>(np - k - B, kend - k - B, B, Wp(k + B, k), np, Wp(k, k + B),
+                                     np, Wp(k + B, k + B), np, s));
+            }
+        }
+        HIPCK(launch_perm_build(ipiv, K0, nb, np, nullptr, moves, s));
+        HIPCK(launch_rows_move<T>(W, np, np, moves, 2 * nb, 0, np, K0, kend, s));
+        if (kend < np) {
+            const int nr = np - kend;
+            for (int ib = 0; ib < nb; ib += B) {
+                HIPCK(launch_trsm_diag<T>(Wp(K0 + ib, K0 + ib), np, Wp(K0 + ib, kend), np, nr, s));
+                if (ib + B < nb)
+                    HIPCK(launch_gemm<T>(nb - ib - B, nr, B, Wp(K0 + ib + B, K0 + ib), np,
+                                         Wp(K0 + ib, kend), np, Wp(K0 + ib + B, kend), np, s));
+            }
+            if (trail_prec == MIXLU_FP64 || trail_prec == MIXLU_FP32) {
+                HIPCK(launch_gemm<T>(nr, nr, nb, Wp(kend, K0), np, Wp(K0, kend), np,
+                                     Wp(kend, kend), np, s));
+            } else {
+                if constexpr (sizeof(T) == 4) {
+                    void *Ap = at<void>(work, L.Ap), *Bp = at<void>(work, L.Bp);
+                    HIPCK(launch_pack(trail_prec, Wp(kend, K0), np, nr, nb, 0, Ap, status, s));
+                    HIPCK(launch_pack(trail_prec, Wp(K0, kend), np, nb, nr, 1, Bp, status, s));
+                    HIPCK(launch_gemm_lowp(trail_prec, nr, nr, nb, Ap, Bp, Wp(kend, kend), np, s));
+                } else {
+                    return MIXLU_ERR_NOT_IMPLEMENTED;
+                }
+            }
+        }
+    }
+    return MIXLU_OK;
+}
+
+void init_status(hipStream_t s, int *status) {
+    // ST_BREAKDOWN and ST_CHOL start at INT_MAX (no failure), the rest at 0
+    static const int zero = 0;
+    (void)zero;
+    launch_fill_u32(reinterpret_cast<unsigned *>(status), 0u, ST_COUNT, s);
+    launch_fill_u32(reinterpret_cast<unsigned *>(status + ST_BREAKDOWN), (unsigned)INT_MAX, 1, s);
+    launch_fill_u32(reinterpret_cast<unsigned *>(status + ST_CHOL), (unsigned)INT_MAX, 1, s);
+}
+
+// Read status words and the two matrix norms (synchronizes).
+int read_status(mixlu_ctx_s *ctx, const Layout &L, void *work, int st[ST_COUNT],
+                double norms2[2]) {
+    RETCK(ensure_hbuf(ctx, 4096));
+    HIPCK(hipMemcpyAsync(ctx->hbuf, at<int>(work, L.status), ST_COUNT * 4, hipMemcpyDeviceToHost,
+                         ctx->stream));
+    HIPCK(hipMemcpyAsync(ctx->hbuf + 8, at<double>(work, L.norms), 2 * 8, hipMemcpyDeviceToHost,
+                         ctx->stream));
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    std::memcpy(st, ctx->hbuf, ST_COUNT * 4);
+    norms2[0] = ctx->hbuf[8];
+    norms2[1] = ctx->hbuf[9];
+    return MIXLU_OK;
+}
+
+// Norms, scales, conversion and LU of the n x n FP64 input into the working
+// factor at woff (FP32 or FP64 storage).
+template <typename T>
+int convert_and_factor(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t woff,
+                       const double *A, int lda, int equil, int trail_prec) {
+    hipStream_t s = ctx->stream;
+    const int n = L.n, np = L.npad;
+    double *tmp = at<double>(work, L.tmp);
+    double *R = at<double>(work, L.R), *C = at<double>(work, L.C);
+    double *norms = at<double>(work, L.norms);
+    int *status = at<int>(work, L.status);
+    init_status(s, status);
+    HIPCK(launch_row_stats(A, lda, n, tmp, tmp + np, s));
+    HIPCK(launch_finish_rows(n, np, tmp, tmp + np, R, equil, norms, s));
+    HIPCK(launch_col_stats(A, lda, n, np, R, tmp + 2 * (size_t)np, C, equil, norms, s));
+    HIPCK(launch_convert<T>(A, lda, n, np, R, C, at<T>(work, woff), np, status, s));
+    return factor_lu<T>(s, work, L, woff, trail_prec);
+}
+
+// Low-precision solve: X (=|+=) C * U^{-1} L^{-1} P (R * rhs), rhs FP64.
+template <typename Tw>
+int lu_solve(hipStream_t s, void *work, const Layout &L, size_t woff, int nrhs,
+             const double *rhs, int ldr, int rhs_cm, double *X, int ldx, int x_cm, int assign) {
+    const int n = L.n, np = L.npad;
+    const Tw *W = at<Tw>(work, woff);
+    Tw *Y = at<Tw>(work, L.vec_y);
+    int *status = at<int>(work, L.status);
+    double *xnorm = at<double>(work, L.norms) + 4 + L.nrhs;
+    auto *ybuf = at<unsigned long long>(work, L.ybuf);
+    HIPCK(launch_rhs_gather<Tw>(n, np, nrhs, rhs, ldr, rhs_cm, at<int>(work, L.perm),
+                                at<double>(work, L.R), Y, nrhs, s));
+    for (int c0 = 0; c0 < nrhs; c0 += kTrsvNRT) {
+        const int nc = nrhs - c0 < kTrsvNRT ? nrhs - c0 : kTrsvNRT;
+        HIPCK(launch_trsv<Tw>(0, W, np, np, Y + c0, nrhs, nc, ybuf, status, s));
+        HIPCK(launch_trsv<Tw>(1, W, np, np, Y + c0, nrhs, nc, ybuf, status, s));
+    }
+    HIPCK(launch_fill_f64(xnorm, 0.0, nrhs, s));
+    HIPCK(launch_x_update<Tw>(n, nrhs, assign, Y, nrhs, at<double>(work, L.C), X, ldx, x_cm,
+                              xnorm, s));
+    return MIXLU_OK;
+}
+
+struct LoopResult {
+    int iters;      // corrections applied, or negative failure code
+    int converged;
+    double rnorm, xnorm, berr;
+};
+
+// Algorithm 1 steps 4-7 from the current X, with correction solves in the
+// precision of the factor at woff (Tw storage).  Stops when every column
+// meets ||r||_inf <= sqrt(n) eps_d ||A||_inf ||x||_inf.
+template <typename Tw>
+int refine_loop(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t woff, const double *A,
+                int lda, const double *B, int ldb, double *X, int ldx, int cm, int nrhs,
+                double anorm, const mixlu_opts &o, LoopResult &res) {
+    hipStream_t s = ctx->stream;
+    const int n = L.n;
+    double *Rv = at<double>(work, L.vec_r);
+    double *norms = at<double>(work, L.norms);
+    double *rnorm = norms + 4;
+    double *xnorm = norms + 4 + L.nrhs;
+    int *status = at<int>(work, L.status);
+    RETCK(ensure_hbuf(ctx, (size_t)(2 * nrhs + 16) * 8));
+    const double thr = std::sqrt((double)n) * kEpsD * anorm;
+    std::vector<double> prev(nrhs, 0.0), ratio_prev(nrhs, 0.0);
+    res = LoopResult{0, 0, 0.0, 0.0, 0.0};
+    for (int k = 0;; ++k) {
+        HIPCK(launch_fill_f64(rnorm, 0.0, nrhs, s));
+        HIPCK(launch_residual(n, nrhs, A, lda, X, ldx, B, ldb, cm, Rv, nrhs, rnorm, s));
+        HIPCK(hipMemcpyAsync(ctx->hbuf, rnorm, (size_t)2 * L.nrhs * 8, hipMemcpyDeviceToHost, s));
+        HIPCK(hipMemcpyAsync(ctx->hbuf + 2 * L.nrhs, status, ST_COUNT * 4, hipMemcpyDeviceToHost,
+                             s));
+        HIPCK(hipStreamSynchronize(s));
+        int stl[ST_COUNT];
+        std::memcpy(stl, ctx->hbuf + 2 * L.nrhs, ST_COUNT * 4);
+        if (stl[ST_TIMEOUT]) return MIXLU_ERR_DEVICE_TIMEOUT;
+        const double *rn = ctx->hbuf;
+        const double *xn = ctx->hbuf + L.nrhs;
+        bool all_ok = true, nonfinite = false, stalled = false;
+        res.rnorm = 0.0;
+        res.xnorm = 0.0;
+        res.berr = 0.0;
+        for (int c = 0; c < nrhs; ++c) {
+            const double r = rn[c], x = xn[c];
+            if (!std::isfinite(r) || !std::isfinite(x)) nonfinite = true;
+            if (!(r <= thr * x)) all_ok = false;
+            res.rnorm = std::fmax(res.rnorm, r);
+            res.xnorm = std::fmax(res.xnorm, x);
+            const double den = anorm * x;
+            res.berr = std::fmax(res.berr, den > 0 ? r / den : (r > 0 ? INFINITY : 0.0));
+            if (k >= 1 && prev[c] > 0 && !(r <= thr * x)) {
+                const double rho = r / prev[c];
+                if ((k >= 2 && rho >= o.stall && ratio_prev[c] >= o.stall) || (k >= 3 && rho >= 1.0))
+                    stalled = true;
+                ratio_prev[c] = rho;
+            }
+            prev[c] = r;
+        }
+        if (nonfinite) res.berr = NAN;
+        if (all_ok && !nonfinite) {
+            res.iters = k;
+            res.converged = 1;
+            return MIXLU_OK;
+        }
+        if (nonfinite || stalled) {
+            res.iters = -4;
+            return MIXLU_OK;
+        }
+        if (k == o.itermax) {
+            res.iters = -(o.itermax + 1);
+            return MIXLU_OK;
+        }
+        RETCK(lu_solve<Tw>(s, work, L, woff, nrhs, Rv, nrhs, 0, X, ldx, cm, 0));
+    }
+}
+
+// Argument checks shared by the solve entry points; `pn` is the 1-based
+// position of n in the caller's signature, followed by nrhs, A, lda, B, ldb,
+// X, ldx.
+int check_common(mixlu_ctx_s *ctx, int pn, int n, int nrhs, int lda, int ldb, int ldx,
+                 const void *A, const void *B, const void *X) {
+    if (!ctx) return -1;
+    if (n < 0) return -pn;
+    if (nrhs < 0) return -(pn + 1);
+    if (n > 0 && !A) return -(pn + 2);
+    if (lda < (n > 1 ? n : 1)) return -(pn + 3);
+    if (n > 0 && nrhs > 0 && !B) return -(pn + 4);
+    if (ldb < (nrhs > 1 ? nrhs : 1)) return -(pn + 5);
+    if (n > 0 && nrhs > 0 && !X) return -(pn + 6);
+    if (ldx < (nrhs > 1 ? nrhs : 1)) return -(pn + 7);
+    return MIXLU_OK;
+}
+
+mixlu_opts opts_or_default(const mixlu_opts *o) {
+    mixlu_opts d;
+    mixlu_default_opts(&d);
+    return o ? *o : d;
+}
+
+int equil_for(int prec, const mixlu_opts &o) {
+    if (o.equilibrate >= 0) return o.equilibrate ? 1 : 0;
+    return is_lowp(prec) ? 1 : 0;
+}
+
+// FP64 factor of A in the W64 region (or W when the factor itself is FP64),
+// x solve, and (optionally) FP64 refinement.
+int fp64_path(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t woff, const double *A,
+              int lda, const double *B, int ldb, double *X, int ldx, int nrhs,
+              const mixlu_opts &o, bool refine, int *info, LoopResult *res, double *anorm_out) {
+    hipStream_t s = ctx->stream;
+    RETCK(convert_and_factor<double>(ctx, work, L, woff, A, lda, 0, MIXLU_FP64));
+    int st[ST_COUNT];
+    double nrm[2];
+    RETCK(read_status(ctx, L, work, st, nrm));
+    if (st[ST_TIMEOUT]) return MIXLU_ERR_DEVICE_TIMEOUT;
+    *info = st[ST_BREAKDOWN] == INT_MAX ? 0 : st[ST_BREAKDOWN];
+    if (anorm_out) *anorm_out = nrm[0];
+    if (*info) return MIXLU_OK;
+    RETCK(lu_solve<double>(s, work, L, woff, nrhs, B, ldb, 0, X, ldx, 0, 1));
+    if (refine) RETCK(refine_loop<double>(ctx, work, L, woff, A, lda, B, ldb, X, ldx, 0, nrhs,
+                                          nrm[0], o, *res));
+    return MIXLU_OK;
+}
+
+}  // namespace
+
+// ======================================================================
+// exported entry points
+// ======================================================================
+extern "C" {
+
+const char *mixlu_status_string(int status) {
+    switch (status) {
+        case MIXLU_OK: return "MIXLU_OK";
+        case MIXLU_ERR_HIP: return "MIXLU_ERR_HIP: a HIP runtime call failed";
+        case MIXLU_ERR_WORKSPACE: return "MIXLU_ERR_WORKSPACE: workspace too small";
+        case MIXLU_ERR_NOT_IMPLEMENTED: return "MIXLU_ERR_NOT_IMPLEMENTED";
+        case MIXLU_ERR_UNSUPPORTED_ARCH: return "MIXLU_ERR_UNSUPPORTED_ARCH: needs gfx950";
+        case MIXLU_ERR_DEVICE_TIMEOUT: return "MIXLU_ERR_DEVICE_TIMEOUT: a device wait gave up";
+        default: return status < 0 ? "invalid argument" : "unknown status";
+    }
+}
+
+void mixlu_default_opts(mixlu_opts *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->itermax = 30;
+    o->equilibrate = -1;
+    o->fallback = 1;
+    o->nb = 0;
+    o->layout = MIXLU_ROW_MAJOR;
+    o->stall = 0.9;
+}
+
+int mixlu_create(mixlu_ctx_t *ctx, void *stream) {
+    if (!ctx) return -1;
+    *ctx = nullptr;
+    int dev = 0;
+    HIPCK(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIPCK(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return MIXLU_ERR_UNSUPPORTED_ARCH;
+    auto *c = new mixlu_ctx_s;
+    c->device = dev;
+    c->stream = static_cast<hipStream_t>(stream);
+    *ctx = c;
+    return MIXLU_OK;
+}
+
+int mixlu_destroy(mixlu_ctx_t ctx) {
+    if (!ctx) return -1;
+    if (ctx->hbuf) (void)hipHostFree(ctx->hbuf);
+    delete ctx;
+    return MIXLU_OK;
+}
+
+int mixlu_set_stream(mixlu_ctx_t ctx, void *stream) {
+    if (!ctx) return -1;
+    ctx->stream = static_cast<hipStream_t>(stream);
+    return MIXLU_OK;
+}
+
+int mixlu_workspace_size(mixlu_ctx_t ctx, int op, int prec, int n, int nrhs,
+                         const mixlu_opts *o, size_t *bytes) {
+    if (!ctx) return -1;
+    if (op < MIXLU_OP_GESV || op > MIXLU_OP_DGESV) return -2;
+    if (!prec_valid(prec)) return -3;
+    if (n < 0) return -4;
+    if (nrhs < 0) return -5;
+    if (!bytes) return -7;
+    if (op == MIXLU_OP_POSV) return MIXLU_ERR_NOT_IMPLEMENTED;
+    const mixlu_opts op_ = opts_or_default(o);
+    Layout L{};
+    *bytes = plan_layout(L, op, prec, n, nrhs, op_);
+    return MIXLU_OK;
+}
+
+int mixlu_getrf(mixlu_ctx_t ctx, int prec, int n, const double *A, int lda, void *work,
+                size_t lwork, const mixlu_opts *o, mixlu_factor *F, int *info) {
+    if (!ctx) return -1;
+    if (!prec_valid(prec)) return -2;
+    if (n < 0) return -3;
+    if (n > 0 && !A) return -4;
+    if (lda < (n > 1 ? n : 1)) return -5;
+    if (!work) return -6;
+    if (!F) return -9;
+    if (!info) return -10;
+    const mixlu_opts op_ = opts_or_default(o);
+    if (op_.layout != MIXLU_ROW_MAJOR) return MIXLU_ERR_NOT_IMPLEMENTED;
+    Layout L{};
+    plan_layout(L, MIXLU_OP_GESV, prec, n, 1, op_);
+    if (lwork < L.total) return MIXLU_ERR_WORKSPACE;
+    if (L.npad > kPanelMaxWG * kPanelRowsPerWG) return MIXLU_ERR_NOT_IMPLEMENTED;
+    fill_factor(F, L, work, lwork, op_.layout);
+    *info = 0;
+    if (n == 0) return MIXLU_OK;
+    const int equil = equil_for(prec, op_);
+    F->equilibrated = equil;
+    if (prec == MIXLU_FP64)
+        RETCK(convert_and_factor<double>(ctx, work, L, L.W, A, lda, 0, MIXLU_FP64));
+    else
+        RETCK(convert_and_factor<float>(ctx, work, L, L.W, A, lda, equil, prec));
+    int st[ST_COUNT];
+    double nrm[2];
+    RETCK(read_status(ctx, L, work, st, nrm));
+    if (st[ST_TIMEOUT]) return MIXLU_ERR_DEVICE_TIMEOUT;
+    if (prec == MIXLU_FP64) {
+        *info = st[ST_BREAKDOWN] == INT_MAX ? 0 : st[ST_BREAKDOWN];
+    } else {
+        if (st[ST_OVERFLOW]) F->lowp_status = -2;
+        else if (st[ST_BREAKDOWN] != INT_MAX) F->lowp_status = -3;
+    }
+    return MIXLU_OK;
+}
+
+int mixlu_potrf(mixlu_ctx_t ctx, int prec, int n, const double *A, int lda, void *work,
+                size_t lwork, const mixlu_opts *o, mixlu_factor *F, int *info) {
+    (void)ctx; (void)prec; (void)n; (void)A; (void)lda; (void)work; (void)lwork; (void)o;
+    (void)F; (void)info;
+    return MIXLU_ERR_NOT_IMPLEMENTED;
+}
+
+int mixlu_getrs(mixlu_ctx_t ctx, const mixlu_factor *F, int trans, const int nrhs,
+                const double *B, int ldb, double *X, int ldx) {
+    if (!ctx) return -1;
+    if (!F || !F->work) return -2;
+    if (trans != 0 && trans != 1) return -3;
+    if (nrhs < 0 || nrhs > F->nrhs_max) return -4;
+    if (nrhs > 0 && F->n > 0 && !B) return -5;
+    if (ldb < (nrhs > 1 ? nrhs : 1)) return -6;
+    if (nrhs > 0 && F->n > 0 && !X) return -7;
+    if (ldx < (nrhs > 1 ? nrhs : 1)) return -8;
+    if (trans) return MIXLU_ERR_NOT_IMPLEMENTED;
+    if (F->n == 0 || nrhs == 0) return MIXLU_OK;
+    const Layout L = layout_of(F);
+    if (F->prec == MIXLU_FP64)
+        return lu_solve<double>(ctx->stream, F->work, L, L.W, nrhs, B, ldb, 0, X, ldx, 0, 1);
+    return lu_solve<float>(ctx->stream, F->work, L, L.W, nrhs, B, ldb, 0, X, ldx, 0, 1);
+}
+
+int mixlu_refine(mixlu_ctx_t ctx, mixlu_factor *F, int trans, const double *A, int lda,
+                 const double *B, int ldb, double *X, int ldx, const mixlu_opts *o,
+                 mixlu_report *rep) {
+    if (!ctx) return -1;
+    if (!F || !F->work) return -2;
+    if (trans != 0 && trans != 1) return -3;
+    if (F->n > 0 && !A) return -4;
+    if (lda < (F->n > 1 ? F->n : 1)) return -5;
+    if (!rep) return -11;
+    if (trans) return MIXLU_ERR_NOT_IMPLEMENTED;
+    const mixlu_opts op_ = opts_or_default(o);
+    const int nrhs = F->nrhs_max;
+    if (!B && F->n > 0) return -6;
+    if (ldb < (nrhs > 1 ? nrhs : 1)) return -7;
+    if (!X && F->n > 0) return -8;
+    if (ldx < (nrhs > 1 ? nrhs : 1)) return -9;
+    std::memset(rep, 0, sizeof(*rep));
+    rep->prec = F->prec;
+    if (F->n == 0) {
+        rep->converged = 1;
+        return MIXLU_OK;
+    }
+    const Layout L = layout_of(F);
+    int st[ST_COUNT];
+    double nrm[2];
+    RETCK(read_status(ctx, L, F->work, st, nrm));
+    const double anorm = nrm[0];
+    rep->anorm = anorm;
+    LoopResult res{};
+    int reason = F->lowp_status;
+    if (reason == 0) {
+        if (F->prec == MIXLU_FP64)
+            RETCK(refine_loop<double>(ctx, F->work, L, L.W, A, lda, B, ldb, X, ldx, 0, nrhs,
+                                      anorm, op_, res));
+        else
+            RETCK(refine_loop<float>(ctx, F->work, L, L.W, A, lda, B, ldb, X, ldx, 0, nrhs,
+                                     anorm, op_, res));
+        reason = res.converged ? 0 : res.iters;
+    }
+    if (reason == 0) {
+        rep->iter = res.iters;
+        rep->converged = 1;
+        rep->rnorm = res.rnorm;
+        rep->xnorm = res.xnorm;
+        rep->berr = res.berr;
+        return MIXLU_OK;
+    }
+    rep->iter = reason;
+    if (F->prec == MIXLU_FP64 || !L.fallback) {
+        rep->rnorm = res.rnorm;
+        rep->xnorm = res.xnorm;
+        rep->berr = res.berr;
+        return MIXLU_OK;
+    }
+    int info = 0;
+    LoopResult fres{};
+    RETCK(fp64_path(ctx, F->work, L, L.W64, A, lda, B, ldb, X, ldx, nrhs, op_, true, &info, &fres,
+                    nullptr));
+    rep->info = info;
+    rep->prec = MIXLU_FP64;
+    rep->fallback_iter = fres.iters;
+    rep->converged = fres.converged;
+    rep->rnorm = fres.rnorm;
+    rep->xnorm = fres.xnorm;
+    rep->berr = fres.berr;
+    return MIXLU_OK;
+}
+
+int mixlu_dxgesv(mixlu_ctx_t ctx, int prec, int n, int nrhs, const double *A, int lda,
+                 const double *B, int ldb, double *X, int ldx, void *work, size_t lwork,
+                 const mixlu_opts *o, mixlu_report *rep) {
+    if (!ctx) return -1;
+    if (!prec_valid(prec)) return -2;
+    RETCK(check_common(ctx, 3, n, nrhs, lda, ldb, ldx, A, B, X));
+    if (!work) return -11;
+    if (!rep) return -14;
+    const mixlu_opts op_ = opts_or_default(o);
+    if (op_.layout != MIXLU_ROW_MAJOR) return MIXLU_ERR_NOT_IMPLEMENTED;
+    std::memset(rep, 0, sizeof(*rep));
+    Layout L{};
+    plan_layout(L, MIXLU_OP_GESV, prec, n, nrhs, op_);
+    if (lwork < L.total) return MIXLU_ERR_WORKSPACE;
+    if (n == 0 || nrhs == 0) {
+        rep->converged = 1;
+        rep->prec = prec;
+        return MIXLU_OK;
+    }
+    if (L.npad > kPanelMaxWG * kPanelRowsPerWG) return MIXLU_ERR_NOT_IMPLEMENTED;
+    mixlu_factor F;
+    int info = 0;
+    {
+        // getrf with the solve's nrhs
+        fill_factor(&F, L, work, lwork, op_.layout);
+        const int equil = equil_for(prec, op_);
+        F.equilibrated = equil;
+        if (prec == MIXLU_FP64)
+            RETCK(convert_and_factor<double>(ctx, work, L, L.W, A, lda, 0, MIXLU_FP64));
+        else
+            RETCK(convert_and_factor<float>(ctx, work, L, L.W, A, lda, equil, prec));
+        int st[ST_COUNT];
+        double nrm[2];
+        RETCK(read_status(ctx, L, work, st, nrm));
+        if (st[ST_TIMEOUT]) return MIXLU_ERR_DEVICE_TIMEOUT;
+        if (prec == MIXLU_FP64) {
+            info = st[ST_BREAKDOWN] == INT_MAX ? 0 : st[ST_BREAKDOWN];
+        } else {
+            if (st[ST_OVERFLOW]) F.lowp_status = -2;
+            else if (st[ST_BREAKDOWN] != INT_MAX) F.lowp_status = -3;
+        }
+    }
+    if (info) {
+        rep->info = info;
+        rep->prec = MIXLU_FP64;
+        rep->iter = -1;
+        return MIXLU_OK;
+    }
+    if (F.lowp_status == 0) {
+        if (prec == MIXLU_FP64)
+            RETCK(lu_solve<double>(ctx->stream, work, L, L.W, nrhs, B, ldb, 0, X, ldx, 0, 1));
+        else
+            RETCK(lu_solve<float>(ctx->stream, work, L, L.W, nrhs, B, ldb, 0, X, ldx, 0, 1));
+    }
+    return mixlu_refine(ctx, &F, 0, A, lda, B, ldb, X, ldx, &op_, rep);
+}
+
+int mixlu_dxposv(mixlu_ctx_t ctx, int prec, int n, int nrhs, const double *A, int lda,
+                 const double *B, int ldb, double *X, int ldx, void *work, size_t lwork,
+                 const mixlu_opts *o, mixlu_report *rep) {
+    (void)ctx; (void)prec; (void)n; (void)nrhs; (void)A; (void)lda; (void)B; (void)ldb; (void)X;
+    (void)ldx; (void)work; (void)lwork; (void)o; (void)rep;
+    return MIXLU_ERR_NOT_IMPLEMENTED;
+}
+
+int mixlu_dgesv(mixlu_ctx_t ctx, int n, int nrhs, const double *A, int lda, const double *B,
+                int ldb, double *X, int ldx, void *work, size_t lwork, int *info) {
+    if (!ctx) return -1;
+    RETCK(check_common(ctx, 2, n, nrhs, lda, ldb, ldx, A, B, X));
+    if (!work) return -9;
+    if (!info) return -11;
+    mixlu_opts op_;
+    mixlu_default_opts(&op_);
+    Layout L{};
+    plan_layout(L, MIXLU_OP_DGESV, MIXLU_FP64, n, nrhs, op_);
+    if (lwork < L.total) return MIXLU_ERR_WORKSPACE;
+    *info = 0;
+    if (n == 0 || nrhs == 0) return MIXLU_OK;
+    if (L.npad > kPanelMaxWG * kPanelRowsPerWG) return MIXLU_ERR_NOT_IMPLEMENTED;
+    LoopResult res{};
+    return fp64_path(ctx, work, L, L.W, A, lda, B, ldb, X, ldx, nrhs, op_, false, info, &res,
+                     nullptr);
+}
+
+int mixlu_outer_update(mixlu_ctx_t ctx, int n, int nrhs, const double *Gb, int ldg,
+                       const double *X, int ldx, double *GA, int ldga, double alpha,
+                       double GA_beta) {
+    if (!ctx) return -1;
+    if (n < 0) return -2;
+    if (nrhs < 0) return -3;
+    if (n > 0 && nrhs > 0 && !Gb) return -4;
+    if (ldg < (nrhs > 1 ? nrhs : 1)) return -5;
+    if (n > 0 && nrhs > 0 && !X) return -6;
+    if (ldx < (nrhs > 1 ? nrhs : 1)) return -7;
+    if (n > 0 && !GA) return -8;
+    if (ldga < (n > 1 ? n : 1)) return -9;
+    HIPCK(launch_outer(n, nrhs, Gb, ldg, X, ldx, GA, ldga, alpha, GA_beta, ctx->stream));
+    return MIXLU_OK;
+}
+
+}  // extern "C"

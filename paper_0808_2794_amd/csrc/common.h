@@ -1,0 +1,164 @@
+// Internal definitions shared by the HIP sources of libmixlu (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/mixlu.h"
+
+namespace mixlu {
+
+// ------------------------------------------------------------ constants
+constexpr int kPanelTPB = 512;     // threads of one panel workgroup
+constexpr int kPanelRows = 1;      // panel rows held per thread
+constexpr int kPanelRowsPerWG = kPanelTPB * kPanelRows;
+constexpr int kPanelMaxWG = 64;    // at most 64 panel workgroups (m <= 32768)
+constexpr int kPanelBF = 64;       // panel width, FP32 factors
+constexpr int kPanelBD = 32;       // panel width, FP64 factors
+constexpr int kXcdStride = 8;      // workgroups are dealt round-robin to 8 XCDs
+constexpr int kTrsvBS = 64;        // rows per block of the chained solves
+constexpr int kTrsvNRT = 8;        // right-hand sides per chained-solve launch
+constexpr int kColChunks = 64;   // row chunks of the column-statistics pass
+constexpr unsigned kSpinLimit = 1u << 23;  // polls before a device wait gives up
+
+// status words kept in the workspace (int32 each)
+enum StatusWord {
+    ST_BREAKDOWN = 0,  // min over zero/non-finite pivot columns + 1 (INT_MAX: none)
+    ST_TIMEOUT = 1,    // nonzero: a bounded cross-workgroup wait gave up
+    ST_OVERFLOW = 2,   // count of non-finite values after conversion
+    ST_CHOL = 3,       // min over non-positive Cholesky pivots + 1 (INT_MAX: none)
+    ST_COUNT = 8
+};
+
+// ------------------------------------------------------------- helpers
+inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Exchange words: 32-bit tag in the high half, 32-bit payload in the low half.
+__device__ inline void xstore(unsigned long long *p, unsigned tag, unsigned payload) {
+    __hip_atomic_store(p, ((unsigned long long)tag << 32) | payload, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline unsigned long long xload(const unsigned long long *p) {
+    return __hip_atomic_load(const_cast<unsigned long long *>(p), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline bool flag_set(const int *p) {
+    return __hip_atomic_load(const_cast<int *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+}
+// Poll *p until its tag equals `tag`; returns the payload.  Gives up after
+// kSpinLimit polls or when *timeout is raised by another workgroup, raising
+// *timeout and setting `bad`.
+__device__ inline unsigned spin_tag(const unsigned long long *p, unsigned tag, int *timeout,
+                                    bool &bad) {
+    unsigned long long w = xload(p);
+    unsigned spins = 0;
+    while ((unsigned)(w >> 32) != tag) {
+        ++spins;
+        if (spins > kSpinLimit || ((spins & 1023u) == 0 && flag_set(timeout))) {
+            __hip_atomic_store(timeout, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            bad = true;
+            return 0u;
+        }
+        w = xload(p);
+    }
+    return (unsigned)w;
+}
+
+template <typename T> struct Words;
+template <> struct Words<float> {
+    static constexpr int n = 1;
+    __device__ static unsigned get(float v, int) { return __float_as_uint(v); }
+    __device__ static float make(const unsigned *w) { return __uint_as_float(w[0]); }
+};
+template <> struct Words<double> {
+    static constexpr int n = 2;
+    __device__ static unsigned get(double v, int i) {
+        unsigned long long b = (unsigned long long)__double_as_longlong(v);
+        return i ? (unsigned)(b >> 32) : (unsigned)b;
+    }
+    __device__ static double make(const unsigned *w) {
+        return __longlong_as_double((long long)(((unsigned long long)w[1] << 32) | w[0]));
+    }
+};
+
+// ------------------------------------------------------ workspace layout
+// Offsets (bytes) of the regions of one solver workspace; see plan_layout.
+struct Layout {
+    int n, npad, nb, nrhs, prec, kind;
+    bool fallback;
+    size_t W;        // working factor: npad x npad, float (or double when prec = FP64)
+    size_t W64;      // FP64 fallback factor (npad x npad double) or 0
+    size_t Ap, Bp;   // packed low-precision GEMM operands
+    size_t ipiv, perm, perm2;     // int[npad] each
+    size_t R, C;     // double[npad] scales
+    size_t vec_r;    // double[npad * nrhs] residual
+    size_t vec_y;    // double[npad * nrhs] solve vector (float or double view)
+    size_t xbuf;     // panel exchange words
+    size_t ybuf;     // chained-solve exchange words + tickets
+    size_t moves;    // int[2 * (2 * nb + 64) + 4] row-move lists
+    size_t tmp;      // scratch: row/column statistics (double[(kColChunks + 2) * npad])
+    size_t status;   // int[ST_COUNT]
+    size_t norms;    // double[4 + 3 * nrhs]: anorm, ..., rnorm[nrhs], xnorm[nrhs], prev[nrhs]
+    size_t total;
+};
+
+size_t plan_layout(Layout &L, int op, int prec, int n, int nrhs, const mixlu_opts &o);
+
+// -------------------------------------------------------- kernel launchers
+// Every launcher enqueues on `s` and returns hipGetLastError().
+hipError_t launch_fill_u32(unsigned *p, unsigned v, size_t count, hipStream_t s);
+
+// a1/a2: norms, equilibration, conversion (k_convert.hip).  The n x n input
+// is always read as the row-major matrix M (a column-major A is M = A^T).
+// rowmax/rowsum/colpart are scratch arrays in the workspace.
+hipError_t launch_row_stats(const double *A, int lda, int n, double *rowmax, double *rowsum,
+                            hipStream_t s);
+hipError_t launch_finish_rows(int n, int npad, const double *rowmax, const double *rowsum,
+                              double *R, int equil, double *norms, hipStream_t s);
+hipError_t launch_col_stats(const double *A, int lda, int n, int npad, const double *R,
+                            double *colpart, double *C, int equil, double *norms, hipStream_t s);
+template <typename Tw>
+hipError_t launch_convert(const double *A, int lda, int n, int npad, const double *R,
+                          const double *C, Tw *W, int ldw, int *status, hipStream_t s);
+
+// a3: factorization kernels (k_lu.hip)
+template <typename T>
+hipError_t launch_panel(T *W, int ldw, int k0, int m, int *ipiv, unsigned long long *xb,
+                        int *status, hipStream_t s);
+hipError_t launch_perm_build(const int *ipiv, int k0, int cnt, int npad, int *perm, int *moves,
+                             hipStream_t s);
+template <typename T>
+hipError_t launch_rows_move(T *W, int ldw, int npad, const int *moves, int max_moves,
+                            int c0, int c1, int skip0, int skip1, hipStream_t s);
+template <typename T>
+hipError_t launch_trsm_diag(const T *Ldiag, int ldl, T *X, int ldx, int ncols, hipStream_t s);
+template <typename T>
+hipError_t launch_gemm(int M, int N, int K, const T *A, int lda, const T *B, int ldb, T *C,
+                       int ldc, hipStream_t s);
+hipError_t launch_pack(int prec, const float *W, int ldw, int rows, int cols, int transpose,
+                       void *dst, int *status, hipStream_t s);
+hipError_t launch_gemm_lowp(int prec, int M, int N, int K, const void *Ap, const void *Bp,
+                            float *C, int ldc, hipStream_t s);
+
+// a4-a8: solves and refinement (k_solve.hip)
+template <typename Tw>
+hipError_t launch_rhs_gather(int n, int npad, int nrhs, const double *B, int ldb, int b_col_major,
+                             const int *perm, const double *R, Tw *Y, int ldy, hipStream_t s);
+template <typename Tw>
+hipError_t launch_trsv(int upper, const Tw *W, int ldw, int npad, Tw *Y, int ldy, int nrhs,
+                       unsigned long long *ybuf, int *status, hipStream_t s);
+template <typename Tw>
+hipError_t launch_x_update(int n, int nrhs, int assign, const Tw *Y, int ldy, const double *C,
+                           double *X, int ldx, int x_col_major, double *xnorm, hipStream_t s);
+hipError_t launch_residual(int n, int nrhs, const double *A, int lda, const double *X, int ldx,
+                           const double *B, int ldb, int bx_col_major, double *Rv, int ldr,
+                           double *rnorm, hipStream_t s);
+hipError_t launch_fill_f64(double *p, double v, size_t count, hipStream_t s);
+hipError_t launch_iota(int *p, int count, hipStream_t s);
+hipError_t launch_outer(int n, int nrhs, const double *G, int ldg, const double *X, int ldx,
+                        double *GA, int ldga, double alpha, double beta, hipStream_t s);
+
+}  // namespace mixlu

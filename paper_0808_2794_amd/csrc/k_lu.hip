@@ -1,0 +1,714 @@
+// Blocked LU with partial pivoting on gfx950: Algorithm 1 step 1 (the
+// SGETRF of Section 3.1.1), PA = LU with partial row pivoting (Section 2.1).
+//
+//   k_panel       GEPP on a tall panel of B columns; the panel rows are held
+//                 in registers across up to 32 workgroups placed on one XCD;
+//                 per column: wavefront argmax (first index on ties), one
+//                 tagged cross-workgroup exchange, swap, scale, rank-1 update.
+//   k_perm_build  composes a block of swaps into a list of row moves
+//   k_rows_move   applies the moves to the columns outside the panel
+//   k_trsm_diag   X = L^{-1} X with a unit lower diagonal block in LDS
+//   k_gemm        C -= A B on MFMA (f32 16x16x4, f64 16x16x4)
+//   k_pack_*      rounds L21 / U12 to FP16 or BF16 for the trailing update
+//   k_gemm_lowp   C -= A B^T on MFMA f16/bf16 16x16x32 with FP32 accumulate
+#include <climits>
+#include <type_traits>
+
+#include "common.h"
+
+namespace mixlu {
+
+// ======================================================================
+// Panel factorization
+// ======================================================================
+template <typename T, int B> struct PanelGeom {
+    static constexpr int PWV = Words<T>::n;
+    static constexpr int HDR = 1 + PWV;        // idx word + value words
+    static constexpr int SLOT = HDR + B * PWV;  // one workgroup's candidate
+    static constexpr int PAR = kPanelMaxWG * SLOT + B * PWV;  // words per parity
+};
+
+// Register-row access with a uniform run-time column index: each switch below
+// expands to constant indices only, so the row stays in VGPRs.
+#define MIXLU_REP8(M, b) M(b + 0) M(b + 1) M(b + 2) M(b + 3) M(b + 4) M(b + 5) M(b + 6) M(b + 7)
+#define MIXLU_REP64(M)                                                                       \
+    MIXLU_REP8(M, 0) MIXLU_REP8(M, 8) MIXLU_REP8(M, 16) MIXLU_REP8(M, 24) MIXLU_REP8(M, 32)  \
+    MIXLU_REP8(M, 40) MIXLU_REP8(M, 48) MIXLU_REP8(M, 56)
+
+template <int B, typename T> __device__ __forceinline__ T row_get(const T (&a)[B], int j) {
+    T v = (T)0;
+    switch (j) {
+#define MIXLU_GET(c)                         \
+    case c:                                  \
+        if constexpr (c < B) { v = a[c]; }  \
+        break;
+        MIXLU_REP64(MIXLU_GET)
+#undef MIXLU_GET
+        default:
+            break;
+    }
+    return v;
+}
+
+template <int B, typename T> __device__ __forceinline__ void row_set(T (&a)[B], int j, T v) {
+    switch (j) {
+#define MIXLU_SET(c)                         \
+    case c:                                  \
+        if constexpr (c < B) { a[c] = v; }  \
+        break;
+        MIXLU_REP64(MIXLU_SET)
+#undef MIXLU_SET
+        default:
+            break;
+    }
+}
+
+// a[c] -= l * u[c] for c = j+1 .. B-1: enter at case j and fall through.
+template <int B, typename T>
+__device__ __forceinline__ void row_axpy_tail(T (&a)[B], const T (&u)[B], int j, T l) {
+    switch (j) {
+#define MIXLU_UPD(c)                                          \
+    case c:                                                   \
+        if constexpr (c + 1 < B) { a[c + 1] -= l * u[c + 1]; } \
+        [[fallthrough]];
+        MIXLU_REP64(MIXLU_UPD)
+#undef MIXLU_UPD
+        default:
+            break;
+    }
+}
+
+template <typename T, int B>
+__device__ __forceinline__ void row_to_lds(T *dst, const T (&a)[B]) {
+#pragma unroll
+    for (int c = 0; c < B; ++c) dst[c] = a[c];
+}
+
+// One thread owns one panel row (position pos = w * TPB + tid, relative to
+// row k0).  Columns are processed by a run-time loop; per column the
+// workgroup reduces its candidates through LDS and, when the panel spans
+// several workgroups, exchanges (pivot value, index, full row) plus row j
+// through tagged words in global memory: one round trip per column.
+template <typename T, int B>
+__global__ __launch_bounds__(kPanelTPB) void k_panel(T *__restrict__ W, int ldw, int k0, int m,
+                                                     int *__restrict__ ipiv,
+                                                     unsigned long long *__restrict__ xb,
+                                                     int *__restrict__ status, int P, int stride) {
+    if (blockIdx.x % stride) return;
+    const int w = blockIdx.x / stride;
+    if (w >= P) return;
+    using G = PanelGeom<T, B>;
+    constexpr int TPB = kPanelTPB, NW = TPB / 64;
+    constexpr int PWV = G::PWV, HDR = G::HDR, SLOT = G::SLOT, PAR = G::PAR;
+    constexpr int DIAG = kPanelMaxWG * SLOT;  // offset of row j's words in a parity
+    static_assert(kPanelRows == 1, "one row per thread");
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int pos = w * TPB + tid;
+    const bool live = pos < m;
+
+    __shared__ T s_row[2][B];   // this workgroup's best row
+    __shared__ T s_drow[2][B];  // row j (held by workgroup 0)
+    __shared__ unsigned s_words[2][kPanelMaxWG * SLOT + B * PWV];
+    __shared__ T s_wval[2][NW];
+    __shared__ int s_widx[2][NW];
+    __shared__ int s_bad;
+
+    T a[B];
+    if (live) {
+        const T *src = W + (size_t)(k0 + pos) * ldw + k0;
+#pragma unroll
+        for (int c = 0; c < B; ++c) a[c] = src[c];
+    } else {
+#pragma unroll
+        for (int c = 0; c < B; ++c) a[c] = (T)0;
+    }
+    if (tid == 0) s_bad = 0;
+
+#pragma unroll 1
+    for (int j = 0; j < B; ++j) {
+        const int par = j & 1;
+        const unsigned tag = (unsigned)(k0 + j + 1);
+        // --- candidate: largest |a_ij| over positions >= j, first index on ties
+        T bv = (T)-1;
+        int bi = INT_MAX;
+        {
+            const T v = fabs(row_get<B>(a, j));
+            if (live && pos >= j && v == v) {
+                bv = v;
+                bi = pos;
+            }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const T ov = __shfl_xor(bv, off);
+            const int oi = __shfl_xor(bi, off);
+            if (ov > bv || (ov == bv && oi < bi)) {
+                bv = ov;
+                bi = oi;
+            }
+        }
+        if (lane == 0) {
+            s_wval[par][wave] = bv;
+            s_widx[par][wave] = bi;
+        }
+        __syncthreads();
+        T gv = s_wval[par][0];
+        int gi = s_widx[par][0];
+#pragma unroll
+        for (int q = 1; q < NW; ++q) {
+            const T v = s_wval[par][q];
+            const int i = s_widx[par][q];
+            if (v > gv || (v == gv && i < gi)) {
+                gv = v;
+                gi = i;
+            }
+        }
+        if (pos == gi) row_to_lds<T, B>(s_row[par], a);
+        if (pos == j) row_to_lds<T, B>(s_drow[par], a);
+        __syncthreads();
+
+        // --- global winner
+        int p = gi;
+        int qs = 0;
+        if (P > 1) {
+            unsigned long long *X = xb + (size_t)par * PAR;
+            unsigned long long *mine = X + (size_t)w * SLOT;
+            if (tid == 0) {
+                xstore(mine, tag, (unsigned)gi);
+#pragma unroll
+                for (int q = 0; q < PWV; ++q) xstore(mine + 1 + q, tag, Words<T>::get(gv, q));
+            }
+            if (tid < B * PWV) {
+                xstore(mine + HDR + tid, tag, Words<T>::get(s_row[par][tid / PWV], tid % PWV));
+                if (w == 0)
+                    xstore(X + DIAG + tid, tag, Words<T>::get(s_drow[par][tid / PWV], tid % PWV));
+            }
+            bool bad = false;
+            const int nslot = P * SLOT;
+            for (int t = tid; t < nslot + B * PWV; t += TPB) {
+                const int src = t < nslot ? t : DIAG + (t - nslot);
+                const unsigned v = spin_tag(X + src, tag, &status[ST_TIMEOUT], bad);
+                s_words[par][src] = v;
+                if (bad) break;
+            }
+            if (bad) s_bad = 1;
+            __syncthreads();
+            if (s_bad) return;  // uniform: every thread reads s_bad after the barrier
+            T best = Words<T>::make(&s_words[par][1]);
+            int bidx = (int)s_words[par][0];
+            for (int q = 1; q < P; ++q) {
+                const T v = Words<T>::make(&s_words[par][q * SLOT + 1]);
+                const int i = (int)s_words[par][q * SLOT];
+                if (v > best || (v == best && i < bidx)) {
+                    best = v;
+                    bidx = i;
+                    qs = q;
+                }
+            }
+            p = bidx;
+        }
+        if (p < j || p >= m) p = j;  // no usable candidate (all NaN): keep row j
+
+        // pivot row (row p before the swap) and row j, from LDS
+        const unsigned *cw = &s_words[par][qs * SLOT + HDR];
+        const unsigned *dw = &s_words[par][DIAG];
+        const bool from_j = (p == j);
+        T pr[B];
+        if (P > 1) {
+            const unsigned *src = from_j ? dw : cw;
+#pragma unroll
+            for (int c = 0; c < B; ++c) pr[c] = Words<T>::make(src + c * PWV);
+        } else {
+            const T *src = from_j ? s_drow[par] : s_row[par];
+#pragma unroll
+            for (int c = 0; c < B; ++c) pr[c] = src[c];
+        }
+        const T piv = row_get<B>(pr, j);
+        if (w == 0 && tid == 0) {
+            ipiv[k0 + j] = k0 + p;
+            if (!(piv != (T)0) || !isfinite(piv)) atomicMin(&status[ST_BREAKDOWN], k0 + j + 1);
+        }
+        // --- swap rows j and p (whole panel rows)
+        if (p != j) {
+            if (pos == j) {
+#pragma unroll
+                for (int c = 0; c < B; ++c) a[c] = pr[c];
+            } else if (pos == p) {
+                if (P > 1) {
+#pragma unroll
+                    for (int c = 0; c < B; ++c) a[c] = Words<T>::make(dw + c * PWV);
+                } else {
+#pragma unroll
+                    for (int c = 0; c < B; ++c) a[c] = s_drow[par][c];
+                }
+            }
+        }
+        // --- multiplier and rank-1 update of the remaining panel columns
+        if (live && pos > j && piv != (T)0) {
+            const T l = row_get<B>(a, j) / piv;
+            row_set<B>(a, j, l);
+            row_axpy_tail<B>(a, pr, j, l);
+        }
+    }
+    if (live) {
+        T *dst = W + (size_t)(k0 + pos) * ldw + k0;
+#pragma unroll
+        for (int c = 0; c < B; ++c) dst[c] = a[c];
+    }
+}
+
+template <typename T> struct PanelWidth;
+template <> struct PanelWidth<float> { static constexpr int v = kPanelBF; };
+template <> struct PanelWidth<double> { static constexpr int v = kPanelBD; };
+
+template <typename T>
+hipError_t launch_panel(T *W, int ldw, int k0, int m, int *ipiv, unsigned long long *xb,
+                        int *status, hipStream_t s) {
+    constexpr int B = PanelWidth<T>::v;
+    const int P = (m + kPanelRowsPerWG - 1) / kPanelRowsPerWG;
+    if (P < 1 || P > kPanelMaxWG) return hipErrorInvalidValue;
+    // workers are dealt round-robin over the 8 XCDs: with stride 8 all of them
+    // land on one XCD (32 CUs) and exchange through its L2
+    const int stride = P == 1 ? 1 : (P <= 32 ? kXcdStride : kXcdStride / 2);
+    k_panel<T, B><<<dim3(P * stride), dim3(kPanelTPB), 0, s>>>(W, ldw, k0, m, ipiv, xb, status,
+                                                               P, stride);
+    return hipGetLastError();
+}
+template hipError_t launch_panel<float>(float *, int, int, int, int *, unsigned long long *,
+                                        int *, hipStream_t);
+template hipError_t launch_panel<double>(double *, int, int, int, int *, unsigned long long *,
+                                         int *, hipStream_t);
+
+// ======================================================================
+// Row interchanges outside the panel
+// ======================================================================
+// One workgroup.  Composes the swaps ipiv[k0 .. k0+cnt) (absolute rows) on
+// positions [k0, npad) and emits moves = {count, pad, (dst, src)...}: after
+// the swaps, row dst holds what row src held before.  When perm is given it
+// is updated the same way (perm[dst] = old perm[src]).  cnt <= 512, so at most
+// 1024 positions move.
+__global__ __launch_bounds__(1024) void k_perm_build(const int *__restrict__ ipiv, int k0, int cnt,
+                                                     int npad, int *__restrict__ perm,
+                                                     int *__restrict__ moves) {
+    extern __shared__ int cur[];
+    __shared__ int s_count;
+    __shared__ int s_dst[1024], s_src[1024];
+    const int m = npad - k0;
+    for (int i = threadIdx.x; i < m; i += blockDim.x) cur[i] = i;
+    if (threadIdx.x == 0) s_count = 0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int s = 0; s < cnt; ++s) {
+            int q = ipiv[k0 + s] - k0;
+            if (q < s || q >= m) q = s;  // never index outside [k0, npad)
+            if (q != s) {
+                const int t = cur[s];
+                cur[s] = cur[q];
+                cur[q] = t;
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+        const int src = cur[i];
+        if (src != i) {
+            const int q = atomicAdd(&s_count, 1);
+            s_dst[q] = k0 + i;
+            s_src[q] = k0 + src;
+        }
+    }
+    __syncthreads();
+    const int count = s_count;
+    const int t = threadIdx.x;
+    int keep = 0;
+    if (t < count) {
+        moves[2 + 2 * t] = s_dst[t];
+        moves[3 + 2 * t] = s_src[t];
+        if (perm) keep = perm[s_src[t]];
+    }
+    __syncthreads();
+    if (perm && t < count) perm[s_dst[t]] = keep;
+    if (t == 0) moves[0] = count;
+}
+
+hipError_t launch_perm_build(const int *ipiv, int k0, int cnt, int npad, int *perm, int *moves,
+                             hipStream_t s) {
+    const int m = npad - k0;
+    const size_t lds = (size_t)m * sizeof(int);
+    if (cnt > 512 || lds > 120 * 1024) return hipErrorInvalidValue;
+    static bool attr_done = false;
+    if (!attr_done) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_perm_build),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 120 * 1024);
+        if (e != hipSuccess) return e;
+        attr_done = true;
+    }
+    k_perm_build<<<dim3(1), dim3(1024), lds, s>>>(ipiv, k0, cnt, npad, perm,
+                                                                     moves);
+    return hipGetLastError();
+}
+
+// Apply the moves to columns [c0, c1) minus [skip0, skip1).  Each workgroup
+// owns CW consecutive columns (after removing the skipped range), stages the
+// source segments of every move in LDS, then writes the destinations.
+template <typename T, int CW>
+__global__ __launch_bounds__(256) void k_rows_move(T *__restrict__ W, int ldw,
+                                                   const int *__restrict__ moves, int c0,
+                                                   int nleft, int gap, int ncols) {
+    extern __shared__ unsigned char smem[];
+    T *buf = reinterpret_cast<T *>(smem);
+    const int count = moves[0];
+    const int lc0 = blockIdx.x * CW;
+    for (int e = threadIdx.x; e < count * CW; e += 256) {
+        const int q = e / CW, cc = e % CW;
+        const int lc = lc0 + cc;
+        if (lc < ncols) {
+            const int col = c0 + lc + (lc >= nleft ? gap : 0);
+            buf[e] = W[(size_t)moves[3 + 2 * q] * ldw + col];
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < count * CW; e += 256) {
+        const int q = e / CW, cc = e % CW;
+        const int lc = lc0 + cc;
+        if (lc < ncols) {
+            const int col = c0 + lc + (lc >= nleft ? gap : 0);
+            W[(size_t)moves[2 + 2 * q] * ldw + col] = buf[e];
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_rows_move(T *W, int ldw, int npad, const int *moves, int max_moves, int c0,
+                            int c1, int skip0, int skip1, hipStream_t s) {
+    (void)npad;
+    constexpr int CW = sizeof(T) == 4 ? 16 : 8;
+    // skipped range clipped to [c0, c1)
+    if (skip0 < c0) skip0 = c0;
+    if (skip1 > c1) skip1 = c1;
+    if (skip1 < skip0) skip1 = skip0;
+    const int nleft = skip0 - c0;
+    const int gap = skip1 - skip0;
+    const int ncols = (c1 - c0) - gap;
+    if (ncols <= 0) return hipSuccess;
+    const size_t lds = (size_t)max_moves * CW * sizeof(T);
+    if (lds > 64 * 1024) return hipErrorInvalidValue;
+    static bool attr_done = false;
+    if (!attr_done) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rows_move<T, CW>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024);
+        if (e != hipSuccess) return e;
+        attr_done = true;
+    }
+    k_rows_move<T, CW><<<dim3((ncols + CW - 1) / CW), dim3(256), lds, s>>>(W, ldw, moves, c0, nleft,
+                                                                          gap, ncols);
+    return hipGetLastError();
+}
+template hipError_t launch_rows_move<float>(float *, int, int, const int *, int, int, int, int,
+                                            int, hipStream_t);
+template hipError_t launch_rows_move<double>(double *, int, int, const int *, int, int, int,
+                                             int, int, hipStream_t);
+
+// ======================================================================
+// Triangular solve with a unit lower diagonal block (LDS-staged)
+// ======================================================================
+// X[0:DB, :] = L^{-1} X[0:DB, :] for the DB x DB unit lower L; one thread
+// per column of X, the block of L in LDS (read by broadcast).
+template <typename T, int DB>
+__global__ __launch_bounds__(64) void k_trsm_diag(const T *__restrict__ L, int ldl,
+                                                  T *__restrict__ X, int ldx, int ncols) {
+    __shared__ T sL[DB][DB + 1];
+    const int t = threadIdx.x;
+    for (int i = 0; i < DB; ++i)
+        for (int c = t; c < DB; c += 64) sL[i][c] = L[(size_t)i * ldl + c];
+    __syncthreads();
+    const int col = blockIdx.x * 64 + t;
+    if (col >= ncols) return;
+    T x[DB];
+#pragma unroll
+    for (int i = 0; i < DB; ++i) x[i] = X[(size_t)i * ldx + col];
+#pragma unroll
+    for (int k = 0; k < DB; ++k) {
+#pragma unroll
+        for (int i = k + 1; i < DB; ++i) x[i] -= sL[i][k] * x[k];
+    }
+#pragma unroll
+    for (int i = 0; i < DB; ++i) X[(size_t)i * ldx + col] = x[i];
+}
+
+template <typename T>
+hipError_t launch_trsm_diag(const T *Ldiag, int ldl, T *X, int ldx, int ncols, hipStream_t s) {
+    if (ncols <= 0) return hipSuccess;
+    constexpr int DB = PanelWidth<T>::v;
+    k_trsm_diag<T, DB><<<dim3((ncols + 63) / 64), dim3(64), 0, s>>>(Ldiag, ldl, X, ldx, ncols);
+    return hipGetLastError();
+}
+template hipError_t launch_trsm_diag<float>(const float *, int, float *, int, int, hipStream_t);
+template hipError_t launch_trsm_diag<double>(const double *, int, double *, int, int, hipStream_t);
+
+// ======================================================================
+// GEMM C -= A B (row-major) on MFMA, FP32 or FP64
+// ======================================================================
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mfma;
+// Output layout of the 16x16x4 MFMAs: element v of lane l holds
+// D[row(l, v)][l % 16], row = 4*(l/16) + v for f32 and 4*v + l/16 for f64.
+template <> struct Mfma<float> {
+    typedef f32x4 acc_t;
+    __device__ static int row(int lane, int v) { return (lane >> 4) * 4 + v; }
+    __device__ static acc_t mac(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Mfma<double> {
+    typedef f64x4 acc_t;
+    __device__ static int row(int lane, int v) { return v * 4 + (lane >> 4); }
+    __device__ static acc_t mac(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+
+// 64x64 output tile per workgroup, 4 waves of 32x32, K step 16.
+// 16x16x4 operand layout: lane l supplies A[l%16][l/16] and B[l/16][l%16].
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const T *__restrict__ A, int lda,
+                                              const T *__restrict__ Bm, int ldb, T *__restrict__ C,
+                                              int ldc) {
+    constexpr int BM = 64, BN = 64, BK = 16;
+    __shared__ T sA[BK][BM + 4];
+    __shared__ T sB[BK][BN + 4];
+    using acc_t = typename Mfma<T>::acc_t;
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    acc_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+    for (int k0 = 0; k0 < K; k0 += BK) {
+        {
+            const int r = tid >> 2, kk = (tid & 3) * 4;
+            const int gr = m0 + r;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int gk = k0 + kk + q;
+                sA[kk + q][r] = (gr < M && gk < K) ? A[(size_t)gr * lda + gk] : (T)0;
+            }
+        }
+        {
+            const int kk = tid >> 4, c = (tid & 15) * 4;
+            const int gk = k0 + kk;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int gc = n0 + c + q;
+                sB[kk][c + q] = (gk < K && gc < N) ? Bm[(size_t)gk * ldb + gc] : (T)0;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+            const int kr = kk + (lane >> 4);
+            const T a0 = sA[kr][wm * 32 + (lane & 15)];
+            const T a1 = sA[kr][wm * 32 + 16 + (lane & 15)];
+            const T b0 = sB[kr][wn * 32 + (lane & 15)];
+            const T b1 = sB[kr][wn * 32 + 16 + (lane & 15)];
+            acc[0][0] = Mfma<T>::mac(a0, b0, acc[0][0]);
+            acc[0][1] = Mfma<T>::mac(a0, b1, acc[0][1]);
+            acc[1][0] = Mfma<T>::mac(a1, b0, acc[1][0]);
+            acc[1][1] = Mfma<T>::mac(a1, b1, acc[1][1]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = m0 + wm * 32 + i * 16 + Mfma<T>::row(lane, v);
+                const int col = n0 + wn * 32 + j * 16 + (lane & 15);
+                if (row < M && col < N) C[(size_t)row * ldc + col] -= acc[i][j][v];
+            }
+}
+
+template <typename T>
+hipError_t launch_gemm(int M, int N, int K, const T *A, int lda, const T *B, int ldb, T *C,
+                       int ldc, hipStream_t s) {
+    if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
+    k_gemm<T><<<dim3((N + 63) / 64, (M + 63) / 64), dim3(256), 0, s>>>(M, N, K, A, lda, B, ldb, C,
+                                                                      ldc);
+    return hipGetLastError();
+}
+template hipError_t launch_gemm<float>(int, int, int, const float *, int, const float *, int,
+                                       float *, int, hipStream_t);
+template hipError_t launch_gemm<double>(int, int, int, const double *, int, const double *, int,
+                                        double *, int, hipStream_t);
+
+// ======================================================================
+// Low-precision trailing update
+// ======================================================================
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+template <typename H> struct LowP;
+template <> struct LowP<_Float16> {
+    typedef f16x8 vec_t;
+    static constexpr float kMax = 65504.0f;
+    __device__ static f32x4 mac(vec_t a, vec_t b, f32x4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct LowP<__bf16> {
+    typedef bf16x8 vec_t;
+    static constexpr float kMax = 3.38953139e38f;
+    __device__ static f32x4 mac(vec_t a, vec_t b, f32x4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+};
+
+// dst[r][c] = round(W[r][c]) (ld of dst = cols); rows x cols.
+template <typename H>
+__global__ __launch_bounds__(256) void k_pack_rows(const float *__restrict__ W, int ldw, int rows,
+                                                   int cols, H *__restrict__ dst,
+                                                   int *__restrict__ status) {
+    const int r = blockIdx.x;
+    int bad = 0;
+    for (int c = threadIdx.x; c < cols; c += 256) {
+        const float v = W[(size_t)r * ldw + c];
+        if (fabsf(v) > LowP<H>::kMax) ++bad;
+        dst[(size_t)r * cols + c] = (H)v;
+    }
+    if (bad) atomicAdd(&status[ST_OVERFLOW], bad);
+}
+
+// dst[c][r] = round(W[r][c]) (ld of dst = rows): 64 x 64 tiles through LDS.
+template <typename H>
+__global__ __launch_bounds__(256) void k_pack_trans(const float *__restrict__ W, int ldw, int rows,
+                                                    int cols, H *__restrict__ dst,
+                                                    int *__restrict__ status) {
+    __shared__ float tile[64][65];
+    const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    int bad = 0;
+    for (int i = ty; i < 64; i += 4) {
+        const int r = r0 + i, c = c0 + tx;
+        tile[i][tx] = (r < rows && c < cols) ? W[(size_t)r * ldw + c] : 0.0f;
+    }
+    __syncthreads();
+    for (int i = ty; i < 64; i += 4) {
+        const int c = c0 + i, r = r0 + tx;
+        if (c < cols && r < rows) {
+            const float v = tile[tx][i];
+            if (fabsf(v) > LowP<H>::kMax) ++bad;
+            dst[(size_t)c * rows + r] = (H)v;
+        }
+    }
+    if (bad) atomicAdd(&status[ST_OVERFLOW], bad);
+}
+
+hipError_t launch_pack(int prec, const float *W, int ldw, int rows, int cols, int transpose,
+                       void *dst, int *status, hipStream_t s) {
+    if (rows <= 0 || cols <= 0) return hipSuccess;
+    if (prec == MIXLU_FP16) {
+        if (transpose)
+            k_pack_trans<_Float16><<<dim3((cols + 63) / 64, (rows + 63) / 64), dim3(256), 0, s>>>(
+                W, ldw, rows, cols, (_Float16 *)dst, status);
+        else
+            k_pack_rows<_Float16><<<dim3(rows), dim3(256), 0, s>>>(W, ldw, rows, cols,
+                                                                   (_Float16 *)dst, status);
+    } else if (prec == MIXLU_BF16) {
+        if (transpose)
+            k_pack_trans<__bf16><<<dim3((cols + 63) / 64, (rows + 63) / 64), dim3(256), 0, s>>>(
+                W, ldw, rows, cols, (__bf16 *)dst, status);
+        else
+            k_pack_rows<__bf16><<<dim3(rows), dim3(256), 0, s>>>(W, ldw, rows, cols,
+                                                                 (__bf16 *)dst, status);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// C[M x N] -= Ap[M x K] * Bp[N x K]^T, Ap and Bp K-contiguous; 128 x 128 tile,
+// 4 waves of 64 x 64 (4 x 4 MFMA 16x16x32 blocks), K step 64.
+// 16x16x32 operand layout: lane l supplies A[l%16][8*(l/16) .. +8] and
+// B[8*(l/16) .. +8][l%16]; result as for 16x16x4.
+template <typename H>
+__global__ __launch_bounds__(256) void k_gemm_lowp(int M, int N, int K, const H *__restrict__ Ap,
+                                                   const H *__restrict__ Bp, float *__restrict__ C,
+                                                   int ldc) {
+    constexpr int BM = 128, BN = 128, BK = 64, PITCH = BK + 8;
+    using vec_t = typename LowP<H>::vec_t;
+    __shared__ __attribute__((aligned(16))) H sA[BM * PITCH];
+    __shared__ __attribute__((aligned(16))) H sB[BN * PITCH];
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
+    for (int k0 = 0; k0 < K; k0 += BK) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = tid + q * 256;
+            const int row = e >> 3, seg = e & 7;
+            uint4 va = make_uint4(0, 0, 0, 0), vb = make_uint4(0, 0, 0, 0);
+            if (m0 + row < M)
+                va = *reinterpret_cast<const uint4 *>(Ap + (size_t)(m0 + row) * K + k0 + seg * 8);
+            if (n0 + row < N)
+                vb = *reinterpret_cast<const uint4 *>(Bp + (size_t)(n0 + row) * K + k0 + seg * 8);
+            *reinterpret_cast<uint4 *>(&sA[row * PITCH + seg * 8]) = va;
+            *reinterpret_cast<uint4 *>(&sB[row * PITCH + seg * 8]) = vb;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 32) {
+            vec_t av[4], bv[4];
+            const int ko = kk + (lane >> 4) * 8;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                av[i] = *reinterpret_cast<const vec_t *>(&sA[(wm * 64 + i * 16 + (lane & 15)) * PITCH + ko]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                bv[j] = *reinterpret_cast<const vec_t *>(&sB[(wn * 64 + j * 16 + (lane & 15)) * PITCH + ko]);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = LowP<H>::mac(av[i], bv[j], acc[i][j]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = m0 + wm * 64 + i * 16 + (lane >> 4) * 4 + v;
+                const int col = n0 + wn * 64 + j * 16 + (lane & 15);
+                if (row < M && col < N) C[(size_t)row * ldc + col] -= acc[i][j][v];
+            }
+}
+
+hipError_t launch_gemm_lowp(int prec, int M, int N, int K, const void *Ap, const void *Bp,
+                            float *C, int ldc, hipStream_t s) {
+    if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
+    if (K % 64) return hipErrorInvalidValue;
+    dim3 grid((N + 127) / 128, (M + 127) / 128);
+    if (prec == MIXLU_FP16)
+        k_gemm_lowp<_Float16><<<grid, dim3(256), 0, s>>>(M, N, K, (const _Float16 *)Ap,
+                                                         (const _Float16 *)Bp, C, ldc);
+    else if (prec == MIXLU_BF16)
+        k_gemm_lowp<__bf16><<<grid, dim3(256), 0, s>>>(M, N, K, (const __bf16 *)Ap,
+                                                       (const __bf16 *)Bp, C, ldc);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+}  // namespace mixlu

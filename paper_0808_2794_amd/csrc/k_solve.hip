@@ -1,0 +1,370 @@
+// Triangular solves and FP64 refinement kernels: Algorithm 1 steps 2-3 and
+// 5-6 (Ly = Pr, Uz = y in the factor's precision, the SGETRS of
+// Section 3.1.1), step 4 (r = b - A x in FP64 with the original A, the
+// DGEMM/DGEMV) and step 7 (x = x + z in FP64, the DAXPY), plus the norms of
+// the stopping test of Section 3 and the outer product of the adjoint.
+//
+// The triangular solves are single launches over 64-row blocks: a block
+// takes a ticket (so blocks start in order), accumulates the off-diagonal
+// products as the solution blocks above it are published, solves its
+// diagonal block in one wave, and publishes its 64 values as tagged words.
+#include <climits>
+
+#include "common.h"
+
+namespace mixlu {
+
+template <typename T> __device__ inline T bcast_lane(T v, int k);
+template <> __device__ inline float bcast_lane<float>(float v, int k) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+}
+template <> __device__ inline double bcast_lane<double>(double v, int k) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), k);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ inline void atomic_max_nonneg(double *p, double v) {
+    // non-negative doubles (and +NaN) order like their bit patterns
+    atomicMax(reinterpret_cast<unsigned long long *>(p), (unsigned long long)__double_as_longlong(v));
+}
+
+// Y[i][c] = round(R[perm[i]] * B[perm[i]][c]) for rows that map into A,
+// 0 for padding rows: the permuted, row-scaled right-hand side P(R b).
+template <typename Tw>
+__global__ __launch_bounds__(256) void k_rhs_gather(int n, int npad, int nrhs,
+                                                    const double *__restrict__ B, int ldb,
+                                                    int b_col_major, const int *__restrict__ perm,
+                                                    const double *__restrict__ R,
+                                                    Tw *__restrict__ Y, int ldy) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= npad) return;
+    const int src = perm[i];
+    for (int c = 0; c < nrhs; ++c) {
+        Tw v = (Tw)0;
+        if (src < n) {
+            const double b = b_col_major ? B[src + (size_t)c * ldb] : B[(size_t)src * ldb + c];
+            v = (Tw)(R[src] * b);
+        }
+        Y[(size_t)i * ldy + c] = v;
+    }
+}
+
+template <typename Tw>
+hipError_t launch_rhs_gather(int n, int npad, int nrhs, const double *B, int ldb, int b_col_major,
+                             const int *perm, const double *R, Tw *Y, int ldy, hipStream_t s) {
+    if (npad == 0 || nrhs == 0) return hipSuccess;
+    k_rhs_gather<Tw><<<dim3((npad + 255) / 256), dim3(256), 0, s>>>(n, npad, nrhs, B, ldb,
+                                                                    b_col_major, perm, R, Y, ldy);
+    return hipGetLastError();
+}
+template hipError_t launch_rhs_gather<float>(int, int, int, const double *, int, int, const int *,
+                                             const double *, float *, int, hipStream_t);
+template hipError_t launch_rhs_gather<double>(int, int, int, const double *, int, int,
+                                              const int *, const double *, double *, int,
+                                              hipStream_t);
+
+// Chained block triangular solve, in place in Y (npad x nrhs, ldy), nrhs <=
+// NRT.  upper = 0: unit lower L (below the diagonal of W), forward.
+// upper = 1: U (on and above the diagonal), backward.  yx holds the
+// published solution words ((row * NRT + c) * PWV + word), zeroed before the
+// launch together with the ticket counter at yx[npad * NRT * PWV].
+template <typename T, int NRT>
+__global__ __launch_bounds__(256) void k_trsv(int upper, const T *__restrict__ W, int ldw,
+                                              int nblk, T *__restrict__ Y, int ldy, int nrhs,
+                                              unsigned long long *__restrict__ yx,
+                                              int *__restrict__ status) {
+    constexpr int BS = kTrsvBS, PWV = Words<T>::n;
+    __shared__ T sL[BS][BS + 1];
+    __shared__ unsigned swords[2][BS * NRT * PWV];
+    __shared__ T sy[BS][NRT];
+    __shared__ int s_b, s_bad;
+    const int tid = threadIdx.x;
+    int *ticket = reinterpret_cast<int *>(yx + (size_t)nblk * BS * NRT * PWV);
+    if (tid == 0) {
+        s_b = atomicAdd(ticket, 1);
+        s_bad = 0;
+    }
+    __syncthreads();
+    const int order = s_b;
+    if (order >= nblk) return;
+    const int b = upper ? nblk - 1 - order : order;
+    const int r = tid >> 2, q = tid & 3;  // row of the block, quarter of the k range
+    const int nw = BS * nrhs * PWV;
+
+    T acc[NRT];
+#pragma unroll
+    for (int c = 0; c < NRT; ++c) acc[c] = (T)0;
+
+    const int nsteps = upper ? nblk - 1 - b : b;
+    for (int st = 0; st < nsteps; ++st) {
+        const int j = upper ? nblk - 1 - st : st;
+        const int par = st & 1;
+        T lv[16];
+        const T *lrow = W + (size_t)(b * BS + r) * ldw + (size_t)j * BS + q * 16;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) lv[e] = lrow[e];
+        bool bad = false;
+        for (int t = tid; t < nw; t += 256) {
+            const int i = t / (nrhs * PWV), rem = t - i * (nrhs * PWV);
+            const unsigned v = spin_tag(yx + ((size_t)(j * BS + i) * NRT) * PWV + rem, 1u,
+                                        &status[ST_TIMEOUT], bad);
+            swords[par][t] = v;
+            if (bad) break;
+        }
+        if (bad) s_bad = 1;
+        __syncthreads();
+        if (s_bad) return;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int i = q * 16 + e;
+#pragma unroll
+            for (int c = 0; c < NRT; ++c)
+                if (c < nrhs) acc[c] += lv[e] * Words<T>::make(&swords[par][(i * nrhs + c) * PWV]);
+        }
+    }
+    // combine the four k-quarters of each row
+#pragma unroll
+    for (int c = 0; c < NRT; ++c) {
+        acc[c] += __shfl_xor(acc[c], 1);
+        acc[c] += __shfl_xor(acc[c], 2);
+    }
+    if (q == 0) {
+#pragma unroll
+        for (int c = 0; c < NRT; ++c)
+            if (c < nrhs) sy[r][c] = Y[(size_t)(b * BS + r) * ldy + c] - acc[c];
+    }
+    for (int e = tid; e < BS * BS; e += 256) {
+        const int i = e / BS, k = e % BS;
+        sL[i][k] = W[(size_t)(b * BS + i) * ldw + (size_t)b * BS + k];
+    }
+    __syncthreads();
+    if (tid < 64) {
+        const int lane = tid;
+        T sv[NRT];
+#pragma unroll
+        for (int c = 0; c < NRT; ++c) sv[c] = (c < nrhs) ? sy[lane][c] : (T)0;
+        if (!upper) {
+            for (int k = 0; k < BS; ++k) {
+                const T lk = sL[lane][k];
+#pragma unroll
+                for (int c = 0; c < NRT; ++c) {
+                    const T yk = bcast_lane(sv[c], k);
+                    if (lane > k) sv[c] -= lk * yk;
+                }
+            }
+        } else {
+            for (int k = BS - 1; k >= 0; --k) {
+                const T uk = sL[lane][k];
+                const T dk = sL[k][k];
+#pragma unroll
+                for (int c = 0; c < NRT; ++c) {
+                    const T yk = bcast_lane(sv[c], k) / dk;
+                    if (lane == k) sv[c] = yk;
+                    else if (lane < k) sv[c] -= uk * yk;
+                }
+            }
+        }
+        const int row = b * BS + lane;
+#pragma unroll
+        for (int c = 0; c < NRT; ++c) {
+            if (c < nrhs) {
+                Y[(size_t)row * ldy + c] = sv[c];
+#pragma unroll
+                for (int wv = 0; wv < PWV; ++wv)
+                    xstore(yx + ((size_t)row * NRT + c) * PWV + wv, 1u, Words<T>::get(sv[c], wv));
+            }
+        }
+    }
+}
+
+template <typename Tw>
+hipError_t launch_trsv(int upper, const Tw *W, int ldw, int npad, Tw *Y, int ldy, int nrhs,
+                       unsigned long long *ybuf, int *status, hipStream_t s) {
+    if (npad == 0 || nrhs == 0) return hipSuccess;
+    if (nrhs > kTrsvNRT || npad % kTrsvBS) return hipErrorInvalidValue;
+    const int nblk = npad / kTrsvBS;
+    constexpr int PWV = sizeof(Tw) / 4;
+    hipError_t e = launch_fill_u32(reinterpret_cast<unsigned *>(ybuf), 0u,
+                                   ((size_t)npad * kTrsvNRT * PWV + 1) * 2, s);
+    if (e != hipSuccess) return e;
+    // each instantiation lays its words (and ticket) out inside the zeroed region
+    if (nrhs == 1)
+        k_trsv<Tw, 1><<<dim3(nblk), dim3(256), 0, s>>>(upper, W, ldw, nblk, Y, ldy, nrhs, ybuf,
+                                                       status);
+    else
+        k_trsv<Tw, kTrsvNRT><<<dim3(nblk), dim3(256), 0, s>>>(upper, W, ldw, nblk, Y, ldy, nrhs,
+                                                              ybuf, status);
+    return hipGetLastError();
+}
+template hipError_t launch_trsv<float>(int, const float *, int, int, float *, int, int,
+                                       unsigned long long *, int *, hipStream_t);
+template hipError_t launch_trsv<double>(int, const double *, int, int, double *, int, int,
+                                        unsigned long long *, int *, hipStream_t);
+
+// X = C z (assign) or X += C z, z promoted to FP64; xnorm[c] = max |X[:, c]|.
+template <typename Tw>
+__global__ __launch_bounds__(256) void k_x_update(int n, int nrhs, int assign,
+                                                  const Tw *__restrict__ Y, int ldy,
+                                                  const double *__restrict__ C,
+                                                  double *__restrict__ X, int ldx, int x_col_major,
+                                                  double *__restrict__ xnorm) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    for (int c = 0; c < nrhs; ++c) {
+        double v = 0.0;
+        if (i < n) {
+            double *px = x_col_major ? X + i + (size_t)c * ldx : X + (size_t)i * ldx + c;
+            v = C[i] * (double)Y[(size_t)i * ldy + c];
+            if (!assign) v += *px;
+            *px = v;
+        }
+        double a = fabs(v);
+        for (int off = 32; off > 0; off >>= 1) {
+            const double o = __shfl_xor(a, off);
+            a = (o > a || o != o) ? o : a;  // NaN wins, so it reaches the norm
+        }
+        if ((threadIdx.x & 63) == 0) atomic_max_nonneg(&xnorm[c], a);
+    }
+}
+
+template <typename Tw>
+hipError_t launch_x_update(int n, int nrhs, int assign, const Tw *Y, int ldy, const double *C,
+                           double *X, int ldx, int x_col_major, double *xnorm, hipStream_t s) {
+    if (n == 0 || nrhs == 0) return hipSuccess;
+    k_x_update<Tw><<<dim3((n + 255) / 256), dim3(256), 0, s>>>(n, nrhs, assign, Y, ldy, C, X, ldx,
+                                                              x_col_major, xnorm);
+    return hipGetLastError();
+}
+template hipError_t launch_x_update<float>(int, int, int, const float *, int, const double *,
+                                           double *, int, int, double *, hipStream_t);
+template hipError_t launch_x_update<double>(int, int, int, const double *, int, const double *,
+                                            double *, int, int, double *, hipStream_t);
+
+// r = b - A x in FP64 (A row-major n x n), 32 rows per workgroup (8 per
+// wave), up to NR right-hand sides; rnorm[c] = max_i |r_ic|.
+template <int NR>
+__global__ __launch_bounds__(256) void k_residual(int n, int nrhs, const double *__restrict__ A,
+                                                  int lda, const double *__restrict__ X, int ldx,
+                                                  const double *__restrict__ B, int ldb, int bx_cm,
+                                                  double *__restrict__ Rv, int ldr,
+                                                  double *__restrict__ rnorm) {
+    constexpr int RPW = 8;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r0 = blockIdx.x * 32 + wave * RPW;
+    double acc[RPW][NR];
+#pragma unroll
+    for (int rr = 0; rr < RPW; ++rr)
+#pragma unroll
+        for (int c = 0; c < NR; ++c) acc[rr][c] = 0.0;
+    for (int j = lane; j < n; j += 64) {
+        double xv[NR];
+#pragma unroll
+        for (int c = 0; c < NR; ++c)
+            xv[c] = (c < nrhs) ? (bx_cm ? X[j + (size_t)c * ldx] : X[(size_t)j * ldx + c]) : 0.0;
+#pragma unroll
+        for (int rr = 0; rr < RPW; ++rr) {
+            const int row = r0 + rr;
+            if (row < n) {
+                const double a = A[(size_t)row * lda + j];
+#pragma unroll
+                for (int c = 0; c < NR; ++c) acc[rr][c] += a * xv[c];
+            }
+        }
+    }
+    double rmax[NR];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) rmax[c] = 0.0;
+#pragma unroll
+    for (int rr = 0; rr < RPW; ++rr) {
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+            double v = acc[rr][c];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+            acc[rr][c] = v;
+        }
+        const int row = r0 + rr;
+        if (lane == 0 && row < n) {
+#pragma unroll
+            for (int c = 0; c < NR; ++c)
+                if (c < nrhs) {
+                    const double b = bx_cm ? B[row + (size_t)c * ldb] : B[(size_t)row * ldb + c];
+                    const double r = b - acc[rr][c];
+                    Rv[(size_t)row * ldr + c] = r;
+                    const double ar = fabs(r);
+                    rmax[c] = (ar > rmax[c] || ar != ar) ? ar : rmax[c];
+                }
+        }
+    }
+    if (lane == 0)
+        for (int c = 0; c < nrhs && c < NR; ++c) atomic_max_nonneg(&rnorm[c], rmax[c]);
+}
+
+hipError_t launch_residual(int n, int nrhs, const double *A, int lda, const double *X, int ldx,
+                           const double *B, int ldb, int bx_col_major, double *Rv, int ldr,
+                           double *rnorm, hipStream_t s) {
+    if (n == 0 || nrhs == 0) return hipSuccess;
+    const dim3 grid((n + 31) / 32);
+    for (int c0 = 0; c0 < nrhs; c0 += 8) {
+        const int nr = nrhs - c0 < 8 ? nrhs - c0 : 8;
+        const double *Xc = bx_col_major ? X + (size_t)c0 * ldx : X + c0;
+        const double *Bc = bx_col_major ? B + (size_t)c0 * ldb : B + c0;
+        if (nr == 1)
+            k_residual<1><<<grid, dim3(256), 0, s>>>(n, 1, A, lda, Xc, ldx, Bc, ldb, bx_col_major,
+                                                     Rv + c0, ldr, rnorm + c0);
+        else
+            k_residual<8><<<grid, dim3(256), 0, s>>>(n, nr, A, lda, Xc, ldx, Bc, ldb, bx_col_major,
+                                                     Rv + c0, ldr, rnorm + c0);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// GA = beta GA + alpha G X^T (all row-major FP64; G, X are n x nrhs).
+__global__ __launch_bounds__(256) void k_outer(int n, int nrhs, const double *__restrict__ G,
+                                               int ldg, const double *__restrict__ X, int ldx,
+                                               double *__restrict__ GA, int ldga, double alpha,
+                                               double beta) {
+    __shared__ double sg[64][17], sx[64][17];
+    const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    double acc[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[e] = 0.0;
+    for (int c0 = 0; c0 < nrhs; c0 += 16) {
+        for (int e = threadIdx.x; e < 64 * 16; e += 256) {
+            const int rr = e / 16, cc = e % 16;
+            sg[rr][cc] = (i0 + rr < n && c0 + cc < nrhs) ? G[(size_t)(i0 + rr) * ldg + c0 + cc] : 0.0;
+            sx[rr][cc] = (j0 + rr < n && c0 + cc < nrhs) ? X[(size_t)(j0 + rr) * ldx + c0 + cc] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int i = ty * 16 + e;
+            double sacc = 0.0;
+#pragma unroll
+            for (int cc = 0; cc < 16; ++cc) sacc += sg[i][cc] * sx[tx][cc];
+            acc[e] += sacc;
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int i = i0 + ty * 16 + e, j = j0 + tx;
+        if (i < n && j < n) {
+            double *p = GA + (size_t)i * ldga + j;
+            *p = (beta == 0.0 ? 0.0 : beta * *p) + alpha * acc[e];
+        }
+    }
+}
+
+hipError_t launch_outer(int n, int nrhs, const double *G, int ldg, const double *X, int ldx,
+                        double *GA, int ldga, double alpha, double beta, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    k_outer<<<dim3((n + 63) / 64, (n + 63) / 64), dim3(256), 0, s>>>(n, nrhs, G, ldg, X, ldx, GA,
+                                                                    ldga, alpha, beta);
+    return hipGetLastError();
+}
+
+}  // namespace mixlu

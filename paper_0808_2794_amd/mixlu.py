@@ -1,0 +1,272 @@
+"""Python binding of libmixlu: argument marshalling only.
+
+Every function named ``mixlu_*`` calls the C entry point of the same name in
+``libmixlu.so`` (declared in ``include/mixlu.h``) with raw device pointers
+taken from torch tensors; all arithmetic happens in the HIP kernels behind
+that C ABI.  ``Solver`` bundles a context with a workspace for repeated
+calls.  Loading fails loudly when the library is missing: there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmixlu.so")
+
+FP64, FP32, BF16, FP16, FP8 = 0, 1, 2, 3, 4
+PREC = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "fp16": FP16, "fp8": FP8}
+PREC_NAME = {v: k for k, v in PREC.items()}
+OP_GESV, OP_POSV, OP_DGESV = 0, 1, 2
+ROW_MAJOR, COL_MAJOR = 0, 1
+
+OK = 0
+ERR_HIP, ERR_WORKSPACE, ERR_NOT_IMPLEMENTED, ERR_UNSUPPORTED_ARCH, ERR_DEVICE_TIMEOUT = 1, 2, 3, 4, 5
+
+
+class mixlu_opts(ctypes.Structure):
+    _fields_ = [("itermax", ctypes.c_int), ("equilibrate", ctypes.c_int),
+                ("fallback", ctypes.c_int), ("nb", ctypes.c_int), ("layout", ctypes.c_int),
+                ("stall", ctypes.c_double), ("reserved", ctypes.c_int * 6)]
+
+
+class mixlu_report(ctypes.Structure):
+    _fields_ = [("iter", ctypes.c_int), ("info", ctypes.c_int), ("prec", ctypes.c_int),
+                ("fallback_iter", ctypes.c_int), ("anorm", ctypes.c_double),
+                ("rnorm", ctypes.c_double), ("xnorm", ctypes.c_double),
+                ("berr", ctypes.c_double), ("converged", ctypes.c_int),
+                ("reserved", ctypes.c_int * 3)]
+
+    def as_dict(self) -> dict:
+        return {"iter": self.iter, "info": self.info, "prec": PREC_NAME.get(self.prec, self.prec),
+                "fallback_iter": self.fallback_iter, "anorm": self.anorm, "rnorm": self.rnorm,
+                "xnorm": self.xnorm, "berr": self.berr, "converged": bool(self.converged)}
+
+
+class mixlu_factor(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("npad", ctypes.c_int), ("nb", ctypes.c_int),
+                ("prec", ctypes.c_int), ("kind", ctypes.c_int), ("layout", ctypes.c_int),
+                ("equilibrated", ctypes.c_int), ("lowp_status", ctypes.c_int),
+                ("nrhs_max", ctypes.c_int), ("work", ctypes.c_void_p),
+                ("lwork", ctypes.c_size_t), ("off", ctypes.c_size_t * 16)]
+
+
+EXPORTS = ("mixlu_status_string", "mixlu_default_opts", "mixlu_create", "mixlu_destroy",
+           "mixlu_set_stream", "mixlu_workspace_size", "mixlu_getrf", "mixlu_potrf",
+           "mixlu_getrs", "mixlu_refine", "mixlu_dxgesv", "mixlu_dxposv", "mixlu_dgesv",
+           "mixlu_outer_update")
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libmixlu.so and declare its signatures; raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libmixlu.so not built ({path}); run paper_0808_2794_amd.build")
+    lib = ctypes.CDLL(path)
+    P, I, D, S = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    sig = {
+        "mixlu_status_string": ([I], ctypes.c_char_p),
+        "mixlu_default_opts": ([P], None),
+        "mixlu_create": ([P, P], I),
+        "mixlu_destroy": ([P], I),
+        "mixlu_set_stream": ([P, P], I),
+        "mixlu_workspace_size": ([P, I, I, I, I, P, P], I),
+        "mixlu_getrf": ([P, I, I, P, I, P, S, P, P, P], I),
+        "mixlu_potrf": ([P, I, I, P, I, P, S, P, P, P], I),
+        "mixlu_getrs": ([P, P, I, I, P, I, P, I], I),
+        "mixlu_refine": ([P, P, I, P, I, P, I, P, I, P, P], I),
+        "mixlu_dxgesv": ([P, I, I, I, P, I, P, I, P, I, P, S, P, P], I),
+        "mixlu_dxposv": ([P, I, I, I, P, I, P, I, P, I, P, S, P, P], I),
+        "mixlu_dgesv": ([P, I, I, P, I, P, I, P, I, P, S, P], I),
+        "mixlu_outer_update": ([P, I, I, P, I, P, I, P, I, D, D], I),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+class MixluError(RuntimeError):
+    pass
+
+
+def check(rc: int, what: str = "") -> None:
+    if rc != OK:
+        msg = load().mixlu_status_string(rc).decode()
+        raise MixluError(f"{what}: {msg} (code {rc})")
+
+
+def default_opts(**kw) -> mixlu_opts:
+    o = mixlu_opts()
+    load().mixlu_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+# ----------------------------------------------------------- raw wrappers
+def _p(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _stream_ptr(stream=None):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def mixlu_create(stream=None):
+    h = ctypes.c_void_p()
+    check(load().mixlu_create(ctypes.byref(h), _stream_ptr(stream)), "mixlu_create")
+    return h
+
+
+def mixlu_destroy(ctx) -> None:
+    check(load().mixlu_destroy(ctx), "mixlu_destroy")
+
+
+def mixlu_set_stream(ctx, stream=None) -> None:
+    check(load().mixlu_set_stream(ctx, _stream_ptr(stream)), "mixlu_set_stream")
+
+
+def mixlu_workspace_size(ctx, op: int, prec: int, n: int, nrhs: int, opts=None) -> int:
+    b = ctypes.c_size_t()
+    check(load().mixlu_workspace_size(ctx, op, prec, n, nrhs,
+                                      None if opts is None else ctypes.byref(opts),
+                                      ctypes.byref(b)), "mixlu_workspace_size")
+    return b.value
+
+
+def _ld(t, n=None):
+    """Leading dimension of a row-major 2-D tensor (unit column stride)."""
+    if t.dim() != 2 or (t.shape[1] > 1 and t.stride(1) != 1):
+        raise ValueError("expected a row-major 2-D tensor")
+    return max(1, t.stride(0), t.shape[1])
+
+
+def mixlu_dxgesv(ctx, prec: int, A, B, X, work, opts=None) -> mixlu_report:
+    rep = mixlu_report()
+    n, nrhs = B.shape
+    check(load().mixlu_dxgesv(ctx, prec, n, nrhs, _p(A), _ld(A, n), _p(B), _ld(B, n), _p(X),
+                              _ld(X, n), _p(work), work.numel() * work.element_size(),
+                              None if opts is None else ctypes.byref(opts), ctypes.byref(rep)),
+          "mixlu_dxgesv")
+    return rep
+
+
+def mixlu_dgesv(ctx, A, B, X, work) -> int:
+    info = ctypes.c_int()
+    n, nrhs = B.shape
+    check(load().mixlu_dgesv(ctx, n, nrhs, _p(A), _ld(A, n), _p(B), _ld(B, n), _p(X), _ld(X, n),
+                             _p(work), work.numel() * work.element_size(), ctypes.byref(info)),
+          "mixlu_dgesv")
+    return info.value
+
+
+def mixlu_getrf(ctx, prec: int, A, work, opts=None):
+    F = mixlu_factor()
+    info = ctypes.c_int()
+    n = A.shape[0]
+    check(load().mixlu_getrf(ctx, prec, n, _p(A), _ld(A, n), _p(work),
+                             work.numel() * work.element_size(),
+                             None if opts is None else ctypes.byref(opts), ctypes.byref(F),
+                             ctypes.byref(info)), "mixlu_getrf")
+    return F, info.value
+
+
+def mixlu_getrs(ctx, F: mixlu_factor, B, X, trans: int = 0) -> None:
+    n, nrhs = B.shape
+    check(load().mixlu_getrs(ctx, ctypes.byref(F), trans, nrhs, _p(B), _ld(B, n), _p(X),
+                             _ld(X, n)), "mixlu_getrs")
+
+
+def mixlu_refine(ctx, F: mixlu_factor, A, B, X, opts=None, trans: int = 0) -> mixlu_report:
+    rep = mixlu_report()
+    n = A.shape[0]
+    check(load().mixlu_refine(ctx, ctypes.byref(F), trans, _p(A), _ld(A, n), _p(B), _ld(B, n),
+                              _p(X), _ld(X, n), None if opts is None else ctypes.byref(opts),
+                              ctypes.byref(rep)), "mixlu_refine")
+    return rep
+
+
+def mixlu_outer_update(ctx, G, X, GA, alpha: float = -1.0, beta: float = 0.0) -> None:
+    n, nrhs = G.shape
+    check(load().mixlu_outer_update(ctx, n, nrhs, _p(G), _ld(G, n), _p(X), _ld(X, n), _p(GA),
+                                    _ld(GA, n), alpha, beta), "mixlu_outer_update")
+
+
+# ------------------------------------------------------------ convenience
+@dataclass
+class Result:
+    x: object
+    report: dict
+
+
+class Solver:
+    """A context plus a reusable workspace on the current device/stream."""
+
+    def __init__(self, stream=None):
+        self.ctx = mixlu_create(stream)
+        self._work = None
+
+    def close(self):
+        if self.ctx is not None:
+            mixlu_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace(self, op: int, prec: int, n: int, nrhs: int, opts=None):
+        import torch
+
+        need = mixlu_workspace_size(self.ctx, op, prec, n, nrhs, opts)
+        if self._work is None or self._work.numel() < need:
+            self._work = None
+            torch.cuda.empty_cache()
+            self._work = torch.empty(max(need, 256), dtype=torch.uint8, device="cuda")
+        return self._work
+
+    @staticmethod
+    def _prep(A, B):
+        import torch
+
+        if A.dtype != torch.float64 or B.dtype != torch.float64:
+            raise TypeError("A and B must be float64")
+        vec = B.dim() == 1
+        B2 = B.reshape(-1, 1) if vec else B
+        return A.contiguous(), B2.contiguous(), vec
+
+    def dxgesv(self, A, B, prec="fp32", opts=None, **kw) -> Result:
+        import torch
+
+        p = PREC[prec] if isinstance(prec, str) else prec
+        o = opts if opts is not None else default_opts(**kw)
+        A, B2, vec = self._prep(A, B)
+        X = torch.empty_like(B2)
+        work = self.workspace(OP_GESV, p, A.shape[0], B2.shape[1], o)
+        rep = mixlu_dxgesv(self.ctx, p, A, B2, X, work, o)
+        return Result(X.reshape(-1) if vec else X, rep.as_dict())
+
+    def dgesv(self, A, B) -> Result:
+        import torch
+
+        A, B2, vec = self._prep(A, B)
+        X = torch.empty_like(B2)
+        work = self.workspace(OP_DGESV, FP64, A.shape[0], B2.shape[1])
+        info = mixlu_dgesv(self.ctx, A, B2, X, work)
+        return Result(X.reshape(-1) if vec else X, {"info": info})
