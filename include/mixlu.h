@@ -217,6 +217,27 @@ int mixlu_outer_update(mixlu_ctx_t ctx, int n, int nrhs, const double *Gb,
                        int ldg, const double *X, int ldx, double *GA, int ldga,
                        double alpha, double GA_beta);
 
+/* ------------------------------------------------------ kernel timing */
+/* Per-kernel-class timing for measurement: with profiling enabled, the
+   launches of the main kernel classes ("panel_getf2", "trailing_update",
+   "pack_operands", "trsv", "residual") are bracketed by HIP events on the
+   context's stream, and each class accumulates its launch count, total
+   device time and the algorithmic flops and bytes of its launches (the work
+   the method requires, not the traffic the kernels generate).  Enabling
+   clears the totals.  The timing adds two event records per launch. */
+typedef struct {
+    const char *name;     /* static string                              */
+    long long launches;
+    double ms;            /* summed event time of the launches          */
+    double flops;         /* algorithmic floating-point operations      */
+    double bytes;         /* algorithmic memory traffic                 */
+} mixlu_kstat;
+
+int mixlu_profile_enable(mixlu_ctx_t ctx, int on);
+/* Copies up to max class records into out (host) and the number of classes
+   into *count; synchronizes the stream. */
+int mixlu_profile_read(mixlu_ctx_t ctx, mixlu_kstat *out, int max, int *count);
+
 #ifdef __cplusplus
 }
 #endif

@@ -17,11 +17,33 @@
 
 using namespace mixlu;
 
+// Optional per-kernel-class timing: HIP events around the launches of the
+// main kernel classes, harvested after the synchronizing calls.
+struct ProfAcc {
+    long long launches = 0;
+    double ms = 0.0, flops = 0.0, bytes = 0.0;
+};
+struct ProfPending {
+    int cls;
+    hipEvent_t a, b;
+    double flops, bytes;
+};
+enum ProfClass { PC_PANEL, PC_TRAIL, PC_PACK, PC_TRSV, PC_RESID, PC_COUNT };
+static const char *const kProfNames[PC_COUNT] = {"panel_getf2", "trailing_update", "pack_operands",
+                                                 "trsv", "residual"};
+struct Prof {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    std::vector<ProfPending> pending;
+    ProfAcc acc[PC_COUNT];
+};
+
 struct mixlu_ctx_s {
     int device = 0;
     hipStream_t stream = nullptr;
     double *hbuf = nullptr;  // pinned host mirror of the norms / status
     size_t hbuf_bytes = 0;
+    Prof prof;
 };
 
 namespace {
@@ -66,6 +88,65 @@ int ensure_hbuf(mixlu_ctx_s *ctx, size_t bytes) {
     return MIXLU_OK;
 }
 
+thread_local Prof *t_prof = nullptr;  // profiler of the context making the current call
+
+hipEvent_t prof_event(Prof &p) {
+    if (!p.pool.empty()) {
+        hipEvent_t e = p.pool.back();
+        p.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Brackets one launch with events when profiling is on.
+struct ProfScope {
+    bool active = false;
+    hipStream_t s = nullptr;
+    ProfPending p{};
+    ProfScope(int cls, double flops, double bytes, hipStream_t st) {
+        if (!t_prof || !t_prof->on) return;
+        p = ProfPending{cls, prof_event(*t_prof), prof_event(*t_prof), flops, bytes};
+        if (!p.a || !p.b) return;
+        s = st;
+        active = hipEventRecord(p.a, s) == hipSuccess;
+    }
+    ~ProfScope() {
+        if (!active) return;
+        if (hipEventRecord(p.b, s) == hipSuccess) t_prof->pending.push_back(p);
+    }
+};
+
+// Fold finished event pairs into the totals (the stream has been synchronized).
+void prof_harvest(Prof &p) {
+    for (auto &q : p.pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, q.a, q.b) == hipSuccess) {
+            ProfAcc &c = p.acc[q.cls];
+            c.launches += 1;
+            c.ms += ms;
+            c.flops += q.flops;
+            c.bytes += q.bytes;
+        }
+        p.pool.push_back(q.a);
+        p.pool.push_back(q.b);
+    }
+    p.pending.clear();
+}
+
+struct ProfCall {  // binds the context's profiler to this thread for one API call
+    mixlu_ctx_s *ctx;
+    explicit ProfCall(mixlu_ctx_s *c) : ctx(c) { t_prof = c ? &c->prof : nullptr; }
+    ~ProfCall() {
+        if (ctx && ctx->prof.on && !ctx->prof.pending.empty() &&
+            hipStreamSynchronize(ctx->stream) == hipSuccess)
+            prof_harvest(ctx->prof);
+        t_prof = nullptr;
+    }
+};
+
 }  // namespace
 
 size_t mixlu::plan_layout(Layout &L, int op, int prec, int n, int nrhs, const mixlu_opts &o) {
@@ -96,7 +177,7 @@ size_t mixlu::plan_layout(Layout &L, int op, int prec, int n, int nrhs, const mi
     L.C = take(np * 8);
     L.vec_r = take(np * L.nrhs * 8);
     L.vec_y = take(np * L.nrhs * 8);
-    L.xbuf = take((size_t)2 * (kPanelMaxWG * (3 + kPanelBF * 2) + kPanelBF * 2) * 8);
+    L.xbuf = take((size_t)kXbufWords * 8);
     L.ybuf = take((np * kTrsvNRT * 2 + 64) * 8);
     L.moves = take((size_t)(4 + 2 * 1024) * 4);
     L.tmp = take((size_t)(2 * kColChunks + 2) * np * 8);
@@ -173,13 +254,18 @@ int factor_lu(hipStream_t s, void *work, const Layout &L, size_t woff, int trail
     auto *xbuf = at<unsigned long long>(work, L.xbuf);
     if (nb % B || nb % 64 || nb > 512) return MIXLU_ERR_NOT_IMPLEMENTED;
     HIPCK(launch_iota(perm, np, s));
-    HIPCK(launch_fill_u32(reinterpret_cast<unsigned *>(xbuf), 0u,
-                          (size_t)2 * (kPanelMaxWG * (3 + kPanelBF * 2) + kPanelBF * 2) * 2, s));
+    HIPCK(launch_fill_u32(reinterpret_cast<unsigned *>(xbuf), 0u, (size_t)kXbufWords * 2, s));
     auto Wp = [&](int r, int c) { return W + (size_t)r * np + c; };
     for (int K0 = 0; K0 < np; K0 += nb) {
         const int kend = K0 + nb;
         for (int k = K0; k < kend; k += B) {
-            HIPCK(launch_panel<T>(W, np, k, np - k, ipiv, xbuf, status, s));
+            {
+                const double m = np - k;
+                double fl = 0.0;
+                for (int j = 0; j < B; ++j) fl += (m - j - 1) * (1.0 + 2.0 * (B - j - 1));
+                ProfScope ps(PC_PANEL, fl, 2.0 * m * B * sizeof(T), s);
+                HIPCK(launch_panel<T>(W, np, k, np - k, ipiv, xbuf, status, s));
+            }
             HIPCK(launch_perm_build(ipiv, k, B, np, perm, moves, s));
             HIPCK(launch_rows_move<T>(W, np, np, moves, 2 * B, K0, kend, k, k + B, s));
             if (k + B < kend) {
@@ -199,13 +285,19 @@ int factor_lu(hipStream_t s, void *work, const Layout &L, size_t woff, int trail
                                          Wp(K0 + ib, kend), np, Wp(K0 + ib + B, kend), np, s));
             }
             if (trail_prec == MIXLU_FP64 || trail_prec == MIXLU_FP32) {
+                ProfScope ps(PC_TRAIL, 2.0 * nr * nr * nb,
+                             (2.0 * nr * nr + 2.0 * nr * nb) * sizeof(T), s);
                 HIPCK(launch_gemm<T>(nr, nr, nb, Wp(kend, K0), np, Wp(K0, kend), np,
                                      Wp(kend, kend), np, s));
             } else {
                 if constexpr (sizeof(T) == 4) {
                     void *Ap = at<void>(work, L.Ap), *Bp = at<void>(work, L.Bp);
-                    HIPCK(launch_pack(trail_prec, Wp(kend, K0), np, nr, nb, 0, Ap, status, s));
-                    HIPCK(launch_pack(trail_prec, Wp(K0, kend), np, nb, nr, 1, Bp, status, s));
+                    {
+                        ProfScope ps(PC_PACK, 0.0, 2.0 * nr * nb * (4 + 2), s);
+                        HIPCK(launch_pack(trail_prec, Wp(kend, K0), np, nr, nb, 0, Ap, status, s));
+                        HIPCK(launch_pack(trail_prec, Wp(K0, kend), np, nb, nr, 1, Bp, status, s));
+                    }
+                    ProfScope ps(PC_TRAIL, 2.0 * nr * nr * nb, 8.0 * nr * nr + 4.0 * nr * nb, s);
                     HIPCK(launch_gemm_lowp(trail_prec, nr, nr, nb, Ap, Bp, Wp(kend, kend), np, s));
                 } else {
                     return MIXLU_ERR_NOT_IMPLEMENTED;
@@ -273,8 +365,15 @@ int lu_solve(hipStream_t s, void *work, const Layout &L, size_t woff, int nrhs,
                                 at<double>(work, L.R), Y, nrhs, s));
     for (int c0 = 0; c0 < nrhs; c0 += kTrsvNRT) {
         const int nc = nrhs - c0 < kTrsvNRT ? nrhs - c0 : kTrsvNRT;
-        HIPCK(launch_trsv<Tw>(0, W, np, np, Y + c0, nrhs, nc, ybuf, status, s));
-        HIPCK(launch_trsv<Tw>(1, W, np, np, Y + c0, nrhs, nc, ybuf, status, s));
+        const double tb = 0.5 * np * (np + 64.0) * sizeof(Tw) + 2.0 * np * nc * sizeof(Tw);
+        {
+            ProfScope ps(PC_TRSV, (double)np * np * nc, tb, s);
+            HIPCK(launch_trsv<Tw>(0, W, np, np, Y + c0, nrhs, nc, ybuf, status, s));
+        }
+        {
+            ProfScope ps(PC_TRSV, (double)np * np * nc, tb, s);
+            HIPCK(launch_trsv<Tw>(1, W, np, np, Y + c0, nrhs, nc, ybuf, status, s));
+        }
     }
     HIPCK(launch_fill_f64(xnorm, 0.0, nrhs, s));
     HIPCK(launch_x_update<Tw>(n, nrhs, assign, Y, nrhs, at<double>(work, L.C), X, ldx, x_cm,
@@ -308,7 +407,11 @@ int refine_loop(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t woff, cons
     res = LoopResult{0, 0, 0.0, 0.0, 0.0};
     for (int k = 0;; ++k) {
         HIPCK(launch_fill_f64(rnorm, 0.0, nrhs, s));
-        HIPCK(launch_residual(n, nrhs, A, lda, X, ldx, B, ldb, cm, Rv, nrhs, rnorm, s));
+        {
+            ProfScope ps(PC_RESID, 2.0 * n * n * nrhs,
+                         8.0 * n * n + 8.0 * n * nrhs * 3.0, s);
+            HIPCK(launch_residual(n, nrhs, A, lda, X, ldx, B, ldb, cm, Rv, nrhs, rnorm, s));
+        }
         HIPCK(hipMemcpyAsync(ctx->hbuf, rnorm, (size_t)2 * L.nrhs * 8, hipMemcpyDeviceToHost, s));
         HIPCK(hipMemcpyAsync(ctx->hbuf + 2 * L.nrhs, status, ST_COUNT * 4, hipMemcpyDeviceToHost,
                              s));
@@ -452,6 +555,11 @@ int mixlu_create(mixlu_ctx_t *ctx, void *stream) {
 int mixlu_destroy(mixlu_ctx_t ctx) {
     if (!ctx) return -1;
     if (ctx->hbuf) (void)hipHostFree(ctx->hbuf);
+    for (auto &q : ctx->prof.pending) {
+        (void)hipEventDestroy(q.a);
+        (void)hipEventDestroy(q.b);
+    }
+    for (auto e : ctx->prof.pool) (void)hipEventDestroy(e);
     delete ctx;
     return MIXLU_OK;
 }
@@ -480,6 +588,7 @@ int mixlu_workspace_size(mixlu_ctx_t ctx, int op, int prec, int n, int nrhs,
 int mixlu_getrf(mixlu_ctx_t ctx, int prec, int n, const double *A, int lda, void *work,
                 size_t lwork, const mixlu_opts *o, mixlu_factor *F, int *info) {
     if (!ctx) return -1;
+    ProfCall pc_(ctx);
     if (!prec_valid(prec)) return -2;
     if (n < 0) return -3;
     if (n > 0 && !A) return -4;
@@ -525,6 +634,7 @@ int mixlu_potrf(mixlu_ctx_t ctx, int prec, int n, const double *A, int lda, void
 int mixlu_getrs(mixlu_ctx_t ctx, const mixlu_factor *F, int trans, const int nrhs,
                 const double *B, int ldb, double *X, int ldx) {
     if (!ctx) return -1;
+    ProfCall pc_(ctx);
     if (!F || !F->work) return -2;
     if (trans != 0 && trans != 1) return -3;
     if (nrhs < 0 || nrhs > F->nrhs_max) return -4;
@@ -544,6 +654,7 @@ int mixlu_refine(mixlu_ctx_t ctx, mixlu_factor *F, int trans, const double *A, i
                  const double *B, int ldb, double *X, int ldx, const mixlu_opts *o,
                  mixlu_report *rep) {
     if (!ctx) return -1;
+    ProfCall pc_(ctx);
     if (!F || !F->work) return -2;
     if (trans != 0 && trans != 1) return -3;
     if (F->n > 0 && !A) return -4;
@@ -612,6 +723,7 @@ int mixlu_dxgesv(mixlu_ctx_t ctx, int prec, int n, int nrhs, const double *A, in
                  const double *B, int ldb, double *X, int ldx, void *work, size_t lwork,
                  const mixlu_opts *o, mixlu_report *rep) {
     if (!ctx) return -1;
+    ProfCall pc_(ctx);
     if (!prec_valid(prec)) return -2;
     RETCK(check_common(ctx, 3, n, nrhs, lda, ldb, ldx, A, B, X));
     if (!work) return -11;
@@ -676,6 +788,7 @@ int mixlu_dxposv(mixlu_ctx_t ctx, int prec, int n, int nrhs, const double *A, in
 int mixlu_dgesv(mixlu_ctx_t ctx, int n, int nrhs, const double *A, int lda, const double *B,
                 int ldb, double *X, int ldx, void *work, size_t lwork, int *info) {
     if (!ctx) return -1;
+    ProfCall pc_(ctx);
     RETCK(check_common(ctx, 2, n, nrhs, lda, ldb, ldx, A, B, X));
     if (!work) return -9;
     if (!info) return -11;
@@ -690,6 +803,34 @@ int mixlu_dgesv(mixlu_ctx_t ctx, int n, int nrhs, const double *A, int lda, cons
     LoopResult res{};
     return fp64_path(ctx, work, L, L.W, A, lda, B, ldb, X, ldx, nrhs, op_, false, info, &res,
                      nullptr);
+}
+
+int mixlu_profile_enable(mixlu_ctx_t ctx, int on) {
+    if (!ctx) return -1;
+    if (on) {
+        for (auto &c : ctx->prof.acc) c = ProfAcc{};
+        ctx->prof.pending.clear();
+    }
+    ctx->prof.on = on != 0;
+    return MIXLU_OK;
+}
+
+int mixlu_profile_read(mixlu_ctx_t ctx, mixlu_kstat *out, int max, int *count) {
+    if (!ctx) return -1;
+    if (max < 0 || (max > 0 && !out)) return -2;
+    if (!count) return -4;
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    prof_harvest(ctx->prof);
+    const int nout = max < PC_COUNT ? max : PC_COUNT;
+    for (int i = 0; i < nout; ++i) {
+        out[i].name = kProfNames[i];
+        out[i].launches = ctx->prof.acc[i].launches;
+        out[i].ms = ctx->prof.acc[i].ms;
+        out[i].flops = ctx->prof.acc[i].flops;
+        out[i].bytes = ctx->prof.acc[i].bytes;
+    }
+    *count = PC_COUNT;
+    return MIXLU_OK;
 }
 
 int mixlu_outer_update(mixlu_ctx_t ctx, int n, int nrhs, const double *Gb, int ldg,

@@ -17,6 +17,7 @@ constexpr int kPanelRowsPerWG = kPanelTPB * kPanelRows;
 constexpr int kPanelMaxWG = 64;    // at most 64 panel workgroups (m <= 32768)
 constexpr int kPanelBF = 64;       // panel width, FP32 factors
 constexpr int kPanelBD = 32;       // panel width, FP64 factors
+constexpr int kXbufWords = 2 * (kPanelMaxWG * (4 + 64) + 64);  // panel exchange words
 constexpr int kXcdStride = 8;      // workgroups are dealt round-robin to 8 XCDs
 constexpr int kTrsvBS = 64;        // rows per block of the chained solves
 constexpr int kTrsvNRT = 8;        // right-hand sides per chained-solve launch

@@ -23,9 +23,124 @@ namespace mixlu {
 // ======================================================================
 template <typename T, int B> struct PanelGeom {
     static constexpr int PWV = Words<T>::n;
-    static constexpr int HDR = 1 + PWV;        // idx word + value words
-    static constexpr int SLOT = HDR + B * PWV;  // one workgroup's candidate
+    static_assert(2 * (kPanelMaxWG * (4 + B * Words<T>::n) + B * Words<T>::n) <= kXbufWords,
+                  "exchange buffer");
+    static constexpr int HDR = 4;               // key words (+ padding to 16 bytes)
+    static constexpr int SLOT = HDR + B * PWV;  // one workgroup's candidate row
     static constexpr int PAR = kPanelMaxWG * SLOT + B * PWV;  // words per parity
+};
+
+// ---------------------------------------------------------------------
+// Wave-wide reductions on DPP (no LDS traffic).  After the four in-row
+// steps every lane of a 16-lane row holds the row's result; row_bcast:15
+// and row_bcast:31 fold the rows so that lane 63 holds the wave's result,
+// which is then read into a scalar register.
+// ---------------------------------------------------------------------
+template <int CTRL, int RM>
+__device__ __forceinline__ unsigned dpp32(unsigned x) {
+    return (unsigned)__builtin_amdgcn_update_dpp((int)x, (int)x, CTRL, RM, 0xF, false);
+}
+template <int CTRL, int RM>
+__device__ __forceinline__ unsigned long long dpp64(unsigned long long x) {
+    const unsigned lo = dpp32<CTRL, RM>((unsigned)x);
+    const unsigned hi = dpp32<CTRL, RM>((unsigned)(x >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+}
+__device__ __forceinline__ unsigned long long umax64(unsigned long long a, unsigned long long b) {
+    return a > b ? a : b;
+}
+// max over the wave of a 64-bit key; uniform result
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x) {
+    x = umax64(x, dpp64<0xB1, 0xF>(x));   // quad_perm [1,0,3,2]
+    x = umax64(x, dpp64<0x4E, 0xF>(x));   // quad_perm [2,3,0,1]
+    x = umax64(x, dpp64<0x141, 0xF>(x));  // row_half_mirror
+    x = umax64(x, dpp64<0x140, 0xF>(x));  // row_mirror
+    x = umax64(x, dpp64<0x142, 0xA>(x));  // row_bcast:15 into rows 1, 3
+    x = umax64(x, dpp64<0x143, 0xC>(x));  // row_bcast:31 into rows 2, 3
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)x, 63);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(x >> 32), 63);
+    return ((unsigned long long)hi << 32) | lo;
+}
+__device__ __forceinline__ double wave_max_f64(double x) {
+    auto step = [](double a, double b) { return a > b ? a : b; };
+    unsigned long long u = (unsigned long long)__double_as_longlong(x);
+    x = step(x, __longlong_as_double((long long)dpp64<0xB1, 0xF>(u)));
+    u = (unsigned long long)__double_as_longlong(x);
+    x = step(x, __longlong_as_double((long long)dpp64<0x4E, 0xF>(u)));
+    u = (unsigned long long)__double_as_longlong(x);
+    x = step(x, __longlong_as_double((long long)dpp64<0x141, 0xF>(u)));
+    u = (unsigned long long)__double_as_longlong(x);
+    x = step(x, __longlong_as_double((long long)dpp64<0x140, 0xF>(u)));
+    u = (unsigned long long)__double_as_longlong(x);
+    x = step(x, __longlong_as_double((long long)dpp64<0x142, 0xA>(u)));
+    u = (unsigned long long)__double_as_longlong(x);
+    x = step(x, __longlong_as_double((long long)dpp64<0x143, 0xC>(u)));
+    u = (unsigned long long)__double_as_longlong(x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, 63);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), 63);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Pivot candidate ordering: larger |value| first, then smaller row.  For
+// FP32 the pair packs into one 64-bit key (|v| bits << 32 | ~row) whose
+// unsigned maximum is the winner; FP64 values need their own 64 bits, so the
+// wave first takes max |v| and then the smallest row holding it.  Invalid
+// candidates have key 0 / value -1.
+template <typename T> struct Cand;
+template <> struct Cand<float> {
+    unsigned long long key;
+    __device__ static Cand make(float av, int row, bool ok) {
+        Cand c;
+        c.key = ok ? (((unsigned long long)__float_as_uint(av) << 32) | (unsigned)(~row)) : 0ull;
+        return c;
+    }
+    __device__ Cand wave_reduce() const {
+        Cand c;
+        c.key = wave_max_u64(key);
+        return c;
+    }
+    __device__ bool better(const Cand &o) const { return key > o.key; }
+    __device__ bool valid() const { return key != 0ull; }
+    __device__ int row() const { return (int)(~(unsigned)key); }
+    __device__ float value() const { return __uint_as_float((unsigned)(key >> 32)); }
+    __device__ unsigned word(int i) const { return i == 0 ? (unsigned)key : (unsigned)(key >> 32); }
+    __device__ static Cand from_words(const unsigned *w) {
+        Cand c;
+        c.key = ((unsigned long long)w[1] << 32) | w[0];
+        return c;
+    }
+};
+template <> struct Cand<double> {
+    double v;
+    int r;
+    __device__ static Cand make(double av, int row, bool ok) {
+        Cand c;
+        c.v = ok ? av : -1.0;
+        c.r = ok ? row : INT_MAX;
+        return c;
+    }
+    __device__ Cand wave_reduce() const {
+        Cand c;
+        c.v = wave_max_f64(v);
+        // smallest row among the lanes holding the maximum: max of ~row
+        const unsigned long long k = (v == c.v) ? (unsigned long long)(unsigned)(~r) : 0ull;
+        c.r = (int)(~(unsigned)wave_max_u64(k));
+        return c;
+    }
+    __device__ bool better(const Cand &o) const { return v > o.v || (v == o.v && r < o.r); }
+    __device__ bool valid() const { return v >= 0.0; }
+    __device__ int row() const { return r; }
+    __device__ double value() const { return v; }
+    __device__ unsigned word(int i) const {
+        const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+        return i == 0 ? (unsigned)b : (i == 1 ? (unsigned)(b >> 32) : (unsigned)r);
+    }
+    __device__ static Cand from_words(const unsigned *w) {
+        Cand c;
+        c.v = __longlong_as_double((long long)(((unsigned long long)w[1] << 32) | w[0]));
+        c.r = (int)w[2];
+        return c;
+    }
 };
 
 // Register-row access with a uniform run-time column index: each switch below
@@ -85,10 +200,11 @@ __device__ __forceinline__ void row_to_lds(T *dst, const T (&a)[B]) {
 }
 
 // One thread owns one panel row (position pos = w * TPB + tid, relative to
-// row k0).  Columns are processed by a run-time loop; per column the
-// workgroup reduces its candidates through LDS and, when the panel spans
-// several workgroups, exchanges (pivot value, index, full row) plus row j
-// through tagged words in global memory: one round trip per column.
+// row k0).  Columns are processed by a run-time loop.  Per column: each wave
+// reduces its candidates on DPP and its winning lane stages its row in LDS;
+// after one barrier every thread picks the workgroup's winner.  When the
+// panel spans several workgroups they exchange (key, row) and row j through
+// tagged words in global memory: one round trip and one more barrier.
 template <typename T, int B>
 __global__ __launch_bounds__(kPanelTPB) void k_panel(T *__restrict__ W, int ldw, int k0, int m,
                                                      int *__restrict__ ipiv,
@@ -101,16 +217,18 @@ __global__ __launch_bounds__(kPanelTPB) void k_panel(T *__restrict__ W, int ldw,
     constexpr int TPB = kPanelTPB, NW = TPB / 64;
     constexpr int PWV = G::PWV, HDR = G::HDR, SLOT = G::SLOT, PAR = G::PAR;
     constexpr int DIAG = kPanelMaxWG * SLOT;  // offset of row j's words in a parity
+    constexpr int V = 16 / sizeof(T);         // values per 16-byte LDS access
     static_assert(kPanelRows == 1, "one row per thread");
+    static_assert(B % V == 0, "row length");
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int pos = w * TPB + tid;
     const bool live = pos < m;
 
-    __shared__ T s_row[2][B];   // this workgroup's best row
-    __shared__ T s_drow[2][B];  // row j (held by workgroup 0)
-    __shared__ unsigned s_words[2][kPanelMaxWG * SLOT + B * PWV];
-    __shared__ T s_wval[2][NW];
-    __shared__ int s_widx[2][NW];
+    __shared__ __attribute__((aligned(16))) T s_wrow[2][NW][B];  // each wave's best row
+    __shared__ __attribute__((aligned(16))) T s_drow[2][B];      // row j (held by workgroup 0)
+    __shared__ __attribute__((aligned(16))) unsigned s_words[2][kPanelMaxWG * SLOT + B * PWV];
+    __shared__ unsigned s_wkey[2][NW][4];
+    __shared__ int s_piv[B];  // pivot rows, written to global memory after the loop
     __shared__ int s_bad;
 
     T a[B];
@@ -124,128 +242,128 @@ __global__ __launch_bounds__(kPanelTPB) void k_panel(T *__restrict__ W, int ldw,
     }
     if (tid == 0) s_bad = 0;
 
+    auto row_out = [&](T *dst) {
+#pragma unroll
+        for (int c = 0; c < B; c += V) {
+            typedef T vec_t __attribute__((ext_vector_type(V)));
+            vec_t v;
+#pragma unroll
+            for (int e = 0; e < V; ++e) v[e] = a[c + e];
+            *reinterpret_cast<vec_t *>(dst + c) = v;
+        }
+    };
+    auto row_in = [&](T (&dst)[B], const T *src) {
+#pragma unroll
+        for (int c = 0; c < B; c += V) {
+            typedef T vec_t __attribute__((ext_vector_type(V)));
+            const vec_t v = *reinterpret_cast<const vec_t *>(src + c);
+#pragma unroll
+            for (int e = 0; e < V; ++e) dst[c + e] = v[e];
+        }
+    };
+
 #pragma unroll 1
     for (int j = 0; j < B; ++j) {
         const int par = j & 1;
         const unsigned tag = (unsigned)(k0 + j + 1);
-        // --- candidate: largest |a_ij| over positions >= j, first index on ties
-        T bv = (T)-1;
-        int bi = INT_MAX;
-        {
-            const T v = fabs(row_get<B>(a, j));
-            if (live && pos >= j && v == v) {
-                bv = v;
-                bi = pos;
-            }
-        }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            const T ov = __shfl_xor(bv, off);
-            const int oi = __shfl_xor(bi, off);
-            if (ov > bv || (ov == bv && oi < bi)) {
-                bv = ov;
-                bi = oi;
-            }
-        }
+        // --- wave candidates
+        const T aj = row_get<B>(a, j);
+        const T av = fabs(aj);
+        const Cand<T> mine = Cand<T>::make(av, pos, live && pos >= j && av == av);
+        const Cand<T> wbest = mine.wave_reduce();
+        if (wbest.valid() && pos == wbest.row()) row_out(s_wrow[par][wave]);
+        if (pos == j) row_out(s_drow[par]);
         if (lane == 0) {
-            s_wval[par][wave] = bv;
-            s_widx[par][wave] = bi;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) s_wkey[par][wave][i] = wbest.word(i);
         }
         __syncthreads();
-        T gv = s_wval[par][0];
-        int gi = s_widx[par][0];
+        // --- workgroup winner (every thread, same answer)
+        Cand<T> gbest = Cand<T>::from_words(s_wkey[par][0]);
+        int qw = 0;
 #pragma unroll
         for (int q = 1; q < NW; ++q) {
-            const T v = s_wval[par][q];
-            const int i = s_widx[par][q];
-            if (v > gv || (v == gv && i < gi)) {
-                gv = v;
-                gi = i;
+            const Cand<T> c = Cand<T>::from_words(s_wkey[par][q]);
+            if (c.better(gbest)) {
+                gbest = c;
+                qw = q;
             }
         }
-        if (pos == gi) row_to_lds<T, B>(s_row[par], a);
-        if (pos == j) row_to_lds<T, B>(s_drow[par], a);
-        __syncthreads();
-
-        // --- global winner
-        int p = gi;
-        int qs = 0;
+        const T *prow = s_wrow[par][qw];
+        const T *drow = s_drow[par];
+        int p = gbest.row();
         if (P > 1) {
             unsigned long long *X = xb + (size_t)par * PAR;
-            unsigned long long *mine = X + (size_t)w * SLOT;
-            if (tid == 0) {
-                xstore(mine, tag, (unsigned)gi);
-#pragma unroll
-                for (int q = 0; q < PWV; ++q) xstore(mine + 1 + q, tag, Words<T>::get(gv, q));
-            }
+            unsigned long long *slot = X + (size_t)w * SLOT;
+            if (tid < HDR) xstore(slot + tid, tag, tid < 3 ? gbest.word(tid) : 0u);
             if (tid < B * PWV) {
-                xstore(mine + HDR + tid, tag, Words<T>::get(s_row[par][tid / PWV], tid % PWV));
-                if (w == 0)
-                    xstore(X + DIAG + tid, tag, Words<T>::get(s_drow[par][tid / PWV], tid % PWV));
+                xstore(slot + HDR + tid, tag, Words<T>::get(prow[tid / PWV], tid % PWV));
+                if (w == 0) xstore(X + DIAG + tid, tag, Words<T>::get(drow[tid / PWV], tid % PWV));
             }
+            // gather every slot: issue all loads, then poll the late ones
             bool bad = false;
             const int nslot = P * SLOT;
-            for (int t = tid; t < nslot + B * PWV; t += TPB) {
+            const int total = nslot + B * PWV;
+            constexpr int MAXW = (kPanelMaxWG * SLOT + B * PWV + TPB - 1) / TPB;
+            unsigned long long wv[MAXW];
+#pragma unroll
+            for (int q = 0; q < MAXW; ++q) {
+                const int t = tid + q * TPB;
                 const int src = t < nslot ? t : DIAG + (t - nslot);
-                const unsigned v = spin_tag(X + src, tag, &status[ST_TIMEOUT], bad);
-                s_words[par][src] = v;
-                if (bad) break;
+                wv[q] = (t < total) ? xload(X + src) : 0ull;
+            }
+#pragma unroll
+            for (int q = 0; q < MAXW; ++q) {
+                const int t = tid + q * TPB;
+                if (t < total) {
+                    const int src = t < nslot ? t : DIAG + (t - nslot);
+                    unsigned v = (unsigned)wv[q];
+                    if ((unsigned)(wv[q] >> 32) != tag && !bad)
+                        v = spin_tag(X + src, tag, &status[ST_TIMEOUT], bad);
+                    s_words[par][src] = v;
+                }
             }
             if (bad) s_bad = 1;
             __syncthreads();
             if (s_bad) return;  // uniform: every thread reads s_bad after the barrier
-            T best = Words<T>::make(&s_words[par][1]);
-            int bidx = (int)s_words[par][0];
+            Cand<T> best = Cand<T>::from_words(&s_words[par][0]);
+            int qs = 0;
             for (int q = 1; q < P; ++q) {
-                const T v = Words<T>::make(&s_words[par][q * SLOT + 1]);
-                const int i = (int)s_words[par][q * SLOT];
-                if (v > best || (v == best && i < bidx)) {
-                    best = v;
-                    bidx = i;
+                const Cand<T> c = Cand<T>::from_words(&s_words[par][q * SLOT]);
+                if (c.better(best)) {
+                    best = c;
                     qs = q;
                 }
             }
-            p = bidx;
+            p = best.row();
+            prow = reinterpret_cast<const T *>(&s_words[par][qs * SLOT + HDR]);
+            drow = reinterpret_cast<const T *>(&s_words[par][DIAG]);
         }
-        if (p < j || p >= m) p = j;  // no usable candidate (all NaN): keep row j
-
-        // pivot row (row p before the swap) and row j, from LDS
-        const unsigned *cw = &s_words[par][qs * SLOT + HDR];
-        const unsigned *dw = &s_words[par][DIAG];
-        const bool from_j = (p == j);
+        if (p < j || p >= m) {  // no usable candidate (all NaN): keep row j
+            p = j;
+            prow = drow;
+        }
+        const T piv = prow[j];
+        // no global stores inside the loop: a barrier waits for every
+        // outstanding store of the wave, which would put a memory round trip
+        // on each column
+        if (tid == 0) s_piv[j] = (!(piv != (T)0) || !isfinite(piv)) ? -(p + 1) : p;
         T pr[B];
-        if (P > 1) {
-            const unsigned *src = from_j ? dw : cw;
-#pragma unroll
-            for (int c = 0; c < B; ++c) pr[c] = Words<T>::make(src + c * PWV);
-        } else {
-            const T *src = from_j ? s_drow[par] : s_row[par];
-#pragma unroll
-            for (int c = 0; c < B; ++c) pr[c] = src[c];
-        }
-        const T piv = row_get<B>(pr, j);
-        if (w == 0 && tid == 0) {
-            ipiv[k0 + j] = k0 + p;
-            if (!(piv != (T)0) || !isfinite(piv)) atomicMin(&status[ST_BREAKDOWN], k0 + j + 1);
-        }
-        // --- swap rows j and p (whole panel rows)
+        row_in(pr, prow);
+        // --- swap rows j and p (whole panel rows); then the multiplier
+        T aj2 = aj;
         if (p != j) {
             if (pos == j) {
 #pragma unroll
                 for (int c = 0; c < B; ++c) a[c] = pr[c];
+                aj2 = piv;
             } else if (pos == p) {
-                if (P > 1) {
-#pragma unroll
-                    for (int c = 0; c < B; ++c) a[c] = Words<T>::make(dw + c * PWV);
-                } else {
-#pragma unroll
-                    for (int c = 0; c < B; ++c) a[c] = s_drow[par][c];
-                }
+                row_in(a, drow);
+                aj2 = drow[j];
             }
         }
-        // --- multiplier and rank-1 update of the remaining panel columns
         if (live && pos > j && piv != (T)0) {
-            const T l = row_get<B>(a, j) / piv;
+            const T l = aj2 / piv;
             row_set<B>(a, j, l);
             row_axpy_tail<B>(a, pr, j, l);
         }
@@ -254,6 +372,12 @@ __global__ __launch_bounds__(kPanelTPB) void k_panel(T *__restrict__ W, int ldw,
         T *dst = W + (size_t)(k0 + pos) * ldw + k0;
 #pragma unroll
         for (int c = 0; c < B; ++c) dst[c] = a[c];
+    }
+    __syncthreads();
+    if (w == 0 && tid < B) {
+        const int v = s_piv[tid];
+        ipiv[k0 + tid] = k0 + (v < 0 ? -v - 1 : v);
+        if (v < 0) atomicMin(&status[ST_BREAKDOWN], k0 + tid + 1);
     }
 }
 

@@ -76,8 +76,11 @@ __global__ __launch_bounds__(256) void k_trsv(int upper, const T *__restrict__ W
                                               unsigned long long *__restrict__ yx,
                                               int *__restrict__ status) {
     constexpr int BS = kTrsvBS, PWV = Words<T>::n;
+    constexpr int JB = 4;                          // off-diagonal blocks per round trip
+    constexpr int NWMAX = JB * BS * NRT * PWV;     // words of JB solution blocks
+    constexpr int WPT = (NWMAX + 255) / 256;       // words per thread
     __shared__ T sL[BS][BS + 1];
-    __shared__ unsigned swords[2][BS * NRT * PWV];
+    __shared__ unsigned swords[2][NWMAX];
     __shared__ T sy[BS][NRT];
     __shared__ int s_b, s_bad;
     const int tid = threadIdx.x;
@@ -91,37 +94,81 @@ __global__ __launch_bounds__(256) void k_trsv(int upper, const T *__restrict__ W
     if (order >= nblk) return;
     const int b = upper ? nblk - 1 - order : order;
     const int r = tid >> 2, q = tid & 3;  // row of the block, quarter of the k range
-    const int nw = BS * nrhs * PWV;
+    const int wblk = BS * nrhs * PWV;      // words of one solution block
 
     T acc[NRT];
 #pragma unroll
     for (int c = 0; c < NRT; ++c) acc[c] = (T)0;
+    // the diagonal tile is needed last but does not depend on anything:
+    // request it now so its latency is off the critical path
+    T dg[16];
+    {
+        const T *drow = W + (size_t)(b * BS + r) * ldw + (size_t)b * BS + q * 16;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) dg[e] = drow[e];
+    }
 
     const int nsteps = upper ? nblk - 1 - b : b;
-    for (int st = 0; st < nsteps; ++st) {
-        const int j = upper ? nblk - 1 - st : st;
-        const int par = st & 1;
-        T lv[16];
-        const T *lrow = W + (size_t)(b * BS + r) * ldw + (size_t)j * BS + q * 16;
+    int par = 0;
+    for (int st0 = 0; st0 < nsteps; st0 += JB, par ^= 1) {
+        const int nb_ = nsteps - st0 < JB ? nsteps - st0 : JB;
+        // L (or U) tile rows for up to JB blocks, and their solution words,
+        // all requested before any wait
+        T lv[JB][16];
 #pragma unroll
-        for (int e = 0; e < 16; ++e) lv[e] = lrow[e];
+        for (int u = 0; u < JB; ++u) {
+            const int st = st0 + u;
+            const int j = upper ? nblk - 1 - st : st;
+            const T *lrow = W + (size_t)(b * BS + r) * ldw + (size_t)j * BS + q * 16;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) lv[u][e] = (u < nb_) ? lrow[e] : (T)0;
+        }
+        unsigned long long wv[WPT];
+#pragma unroll
+        for (int p = 0; p < WPT; ++p) {
+            const int t = tid + p * 256;
+            wv[p] = 0ull;
+            if (t < nb_ * wblk) {
+                const int u = t / wblk, rem = t - u * wblk;
+                const int st = st0 + u;
+                const int j = upper ? nblk - 1 - st : st;
+                const int i = rem / (nrhs * PWV), rr = rem - i * (nrhs * PWV);
+                wv[p] = xload(yx + ((size_t)(j * BS + i) * NRT) * PWV + rr);
+            }
+        }
         bool bad = false;
-        for (int t = tid; t < nw; t += 256) {
-            const int i = t / (nrhs * PWV), rem = t - i * (nrhs * PWV);
-            const unsigned v = spin_tag(yx + ((size_t)(j * BS + i) * NRT) * PWV + rem, 1u,
-                                        &status[ST_TIMEOUT], bad);
-            swords[par][t] = v;
-            if (bad) break;
+#pragma unroll
+        for (int p = 0; p < WPT; ++p) {
+            const int t = tid + p * 256;
+            if (t < nb_ * wblk) {
+                unsigned v = (unsigned)wv[p];
+                if ((unsigned)(wv[p] >> 32) != 1u && !bad) {
+                    const int u = t / wblk, rem = t - u * wblk;
+                    const int st = st0 + u;
+                    const int j = upper ? nblk - 1 - st : st;
+                    const int i = rem / (nrhs * PWV), rr = rem - i * (nrhs * PWV);
+                    v = spin_tag(yx + ((size_t)(j * BS + i) * NRT) * PWV + rr, 1u,
+                                 &status[ST_TIMEOUT], bad);
+                }
+                swords[par][t] = v;
+            }
         }
         if (bad) s_bad = 1;
         __syncthreads();
         if (s_bad) return;
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const int i = q * 16 + e;
+        for (int u = 0; u < JB; ++u) {
+            if (u < nb_) {
 #pragma unroll
-            for (int c = 0; c < NRT; ++c)
-                if (c < nrhs) acc[c] += lv[e] * Words<T>::make(&swords[par][(i * nrhs + c) * PWV]);
+                for (int e = 0; e < 16; ++e) {
+                    const int i = q * 16 + e;
+#pragma unroll
+                    for (int c = 0; c < NRT; ++c)
+                        if (c < nrhs)
+                            acc[c] += lv[u][e] *
+                                      Words<T>::make(&swords[par][u * wblk + (i * nrhs + c) * PWV]);
+                }
+            }
         }
     }
     // combine the four k-quarters of each row
@@ -135,34 +182,37 @@ __global__ __launch_bounds__(256) void k_trsv(int upper, const T *__restrict__ W
         for (int c = 0; c < NRT; ++c)
             if (c < nrhs) sy[r][c] = Y[(size_t)(b * BS + r) * ldy + c] - acc[c];
     }
-    for (int e = tid; e < BS * BS; e += 256) {
-        const int i = e / BS, k = e % BS;
-        sL[i][k] = W[(size_t)(b * BS + i) * ldw + (size_t)b * BS + k];
-    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) sL[r][q * 16 + e] = dg[e];
     __syncthreads();
     if (tid < 64) {
         const int lane = tid;
         T sv[NRT];
 #pragma unroll
         for (int c = 0; c < NRT; ++c) sv[c] = (c < nrhs) ? sy[lane][c] : (T)0;
+        // this lane's row of the diagonal block, in registers: the sequential
+        // steps below then touch no memory at all
+        T lrow[BS];
+#pragma unroll
+        for (int k = 0; k < BS; ++k) lrow[k] = sL[lane][k];
         if (!upper) {
+#pragma unroll
             for (int k = 0; k < BS; ++k) {
-                const T lk = sL[lane][k];
 #pragma unroll
                 for (int c = 0; c < NRT; ++c) {
                     const T yk = bcast_lane(sv[c], k);
-                    if (lane > k) sv[c] -= lk * yk;
+                    if (lane > k) sv[c] -= lrow[k] * yk;
                 }
             }
         } else {
+#pragma unroll
             for (int k = BS - 1; k >= 0; --k) {
-                const T uk = sL[lane][k];
-                const T dk = sL[k][k];
+                const T dk = bcast_lane(lrow[k], k);
 #pragma unroll
                 for (int c = 0; c < NRT; ++c) {
                     const T yk = bcast_lane(sv[c], k) / dk;
                     if (lane == k) sv[c] = yk;
-                    else if (lane < k) sv[c] -= uk * yk;
+                    else if (lane < k) sv[c] -= lrow[k] * yk;
                 }
             }
         }
@@ -241,34 +291,64 @@ template hipError_t launch_x_update<float>(int, int, int, const float *, int, co
 template hipError_t launch_x_update<double>(int, int, int, const double *, int, const double *,
                                             double *, int, int, double *, hipStream_t);
 
-// r = b - A x in FP64 (A row-major n x n), 32 rows per workgroup (8 per
-// wave), up to NR right-hand sides; rnorm[c] = max_i |r_ic|.
-template <int NR>
+// r = b - A x in FP64 (A row-major n x n), 16 rows per workgroup (4 per
+// wave), up to NR right-hand sides; rnorm[c] = max_i |r_ic|.  VEC: rows are
+// read as 16-byte pairs (needs even n and lda and 16-byte aligned A), two
+// pairs in flight per lane and row.
+template <int NR, bool VEC>
 __global__ __launch_bounds__(256) void k_residual(int n, int nrhs, const double *__restrict__ A,
                                                   int lda, const double *__restrict__ X, int ldx,
                                                   const double *__restrict__ B, int ldb, int bx_cm,
                                                   double *__restrict__ Rv, int ldr,
                                                   double *__restrict__ rnorm) {
-    constexpr int RPW = 8;
+    constexpr int RPW = 4;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int r0 = blockIdx.x * 32 + wave * RPW;
+    const int r0 = (blockIdx.x * 4 + wave) * RPW;
     double acc[RPW][NR];
 #pragma unroll
     for (int rr = 0; rr < RPW; ++rr)
 #pragma unroll
         for (int c = 0; c < NR; ++c) acc[rr][c] = 0.0;
-    for (int j = lane; j < n; j += 64) {
-        double xv[NR];
+    auto xat = [&](int j, int c) -> double {
+        return (c < nrhs) ? (bx_cm ? X[j + (size_t)c * ldx] : X[(size_t)j * ldx + c]) : 0.0;
+    };
+    if constexpr (VEC) {
+        for (int j0 = 2 * lane; j0 < n; j0 += 256) {
 #pragma unroll
-        for (int c = 0; c < NR; ++c)
-            xv[c] = (c < nrhs) ? (bx_cm ? X[j + (size_t)c * ldx] : X[(size_t)j * ldx + c]) : 0.0;
+            for (int h = 0; h < 2; ++h) {
+                const int j = j0 + 128 * h;
+                if (j < n) {
+                    double x0[NR], x1[NR];
 #pragma unroll
-        for (int rr = 0; rr < RPW; ++rr) {
-            const int row = r0 + rr;
-            if (row < n) {
-                const double a = A[(size_t)row * lda + j];
+                    for (int c = 0; c < NR; ++c) {
+                        x0[c] = xat(j, c);
+                        x1[c] = xat(j + 1, c);
+                    }
 #pragma unroll
-                for (int c = 0; c < NR; ++c) acc[rr][c] += a * xv[c];
+                    for (int rr = 0; rr < RPW; ++rr) {
+                        const int row = r0 + rr;
+                        if (row < n) {
+                            const double2 a = *reinterpret_cast<const double2 *>(A + (size_t)row * lda + j);
+#pragma unroll
+                            for (int c = 0; c < NR; ++c) acc[rr][c] += a.x * x0[c] + a.y * x1[c];
+                        }
+                    }
+                }
+            }
+        }
+    } else {
+        for (int j = lane; j < n; j += 64) {
+            double xv[NR];
+#pragma unroll
+            for (int c = 0; c < NR; ++c) xv[c] = xat(j, c);
+#pragma unroll
+            for (int rr = 0; rr < RPW; ++rr) {
+                const int row = r0 + rr;
+                if (row < n) {
+                    const double a = A[(size_t)row * lda + j];
+#pragma unroll
+                    for (int c = 0; c < NR; ++c) acc[rr][c] += a * xv[c];
+                }
             }
         }
     }
@@ -296,25 +376,38 @@ __global__ __launch_bounds__(256) void k_residual(int n, int nrhs, const double 
                 }
         }
     }
-    if (lane == 0)
-        for (int c = 0; c < nrhs && c < NR; ++c) atomic_max_nonneg(&rnorm[c], rmax[c]);
+    if (lane == 0) {
+#pragma unroll
+        for (int c = 0; c < NR; ++c)
+            if (c < nrhs) atomic_max_nonneg(&rnorm[c], rmax[c]);
+    }
 }
 
 hipError_t launch_residual(int n, int nrhs, const double *A, int lda, const double *X, int ldx,
                            const double *B, int ldb, int bx_col_major, double *Rv, int ldr,
                            double *rnorm, hipStream_t s) {
     if (n == 0 || nrhs == 0) return hipSuccess;
-    const dim3 grid((n + 31) / 32);
+    const dim3 grid((n + 15) / 16);
+    const bool vec = (n % 2 == 0) && (lda % 2 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
     for (int c0 = 0; c0 < nrhs; c0 += 8) {
         const int nr = nrhs - c0 < 8 ? nrhs - c0 : 8;
         const double *Xc = bx_col_major ? X + (size_t)c0 * ldx : X + c0;
         const double *Bc = bx_col_major ? B + (size_t)c0 * ldb : B + c0;
-        if (nr == 1)
-            k_residual<1><<<grid, dim3(256), 0, s>>>(n, 1, A, lda, Xc, ldx, Bc, ldb, bx_col_major,
-                                                     Rv + c0, ldr, rnorm + c0);
-        else
-            k_residual<8><<<grid, dim3(256), 0, s>>>(n, nr, A, lda, Xc, ldx, Bc, ldb, bx_col_major,
-                                                     Rv + c0, ldr, rnorm + c0);
+        if (nr == 1) {
+            if (vec)
+                k_residual<1, true><<<grid, dim3(256), 0, s>>>(n, 1, A, lda, Xc, ldx, Bc, ldb,
+                                                               bx_col_major, Rv + c0, ldr, rnorm + c0);
+            else
+                k_residual<1, false><<<grid, dim3(256), 0, s>>>(n, 1, A, lda, Xc, ldx, Bc, ldb,
+                                                                bx_col_major, Rv + c0, ldr, rnorm + c0);
+        } else {
+            if (vec)
+                k_residual<8, true><<<grid, dim3(256), 0, s>>>(n, nr, A, lda, Xc, ldx, Bc, ldb,
+                                                               bx_col_major, Rv + c0, ldr, rnorm + c0);
+            else
+                k_residual<8, false><<<grid, dim3(256), 0, s>>>(n, nr, A, lda, Xc, ldx, Bc, ldb,
+                                                                bx_col_major, Rv + c0, ldr, rnorm + c0);
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

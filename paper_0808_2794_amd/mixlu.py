@@ -53,10 +53,15 @@ class mixlu_factor(ctypes.Structure):
                 ("lwork", ctypes.c_size_t), ("off", ctypes.c_size_t * 16)]
 
 
+class mixlu_kstat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char_p), ("launches", ctypes.c_longlong),
+                ("ms", ctypes.c_double), ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
 EXPORTS = ("mixlu_status_string", "mixlu_default_opts", "mixlu_create", "mixlu_destroy",
            "mixlu_set_stream", "mixlu_workspace_size", "mixlu_getrf", "mixlu_potrf",
            "mixlu_getrs", "mixlu_refine", "mixlu_dxgesv", "mixlu_dxposv", "mixlu_dgesv",
-           "mixlu_outer_update")
+           "mixlu_outer_update", "mixlu_profile_enable", "mixlu_profile_read")
 
 _lib = None
 
@@ -85,6 +90,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "mixlu_dxposv": ([P, I, I, I, P, I, P, I, P, I, P, S, P, P], I),
         "mixlu_dgesv": ([P, I, I, P, I, P, I, P, I, P, S, P], I),
         "mixlu_outer_update": ([P, I, I, P, I, P, I, P, I, D, D], I),
+        "mixlu_profile_enable": ([P, I], I),
+        "mixlu_profile_read": ([P, P, I, P], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -204,6 +211,20 @@ def mixlu_outer_update(ctx, G, X, GA, alpha: float = -1.0, beta: float = 0.0) ->
     n, nrhs = G.shape
     check(load().mixlu_outer_update(ctx, n, nrhs, _p(G), _ld(G, n), _p(X), _ld(X, n), _p(GA),
                                     _ld(GA, n), alpha, beta), "mixlu_outer_update")
+
+
+def mixlu_profile_enable(ctx, on: bool = True) -> None:
+    check(load().mixlu_profile_enable(ctx, int(on)), "mixlu_profile_enable")
+
+
+def mixlu_profile_read(ctx) -> dict:
+    """Per-kernel-class totals: {name: {launches, ms, flops, bytes}}."""
+    arr = (mixlu_kstat * 16)()
+    cnt = ctypes.c_int()
+    check(load().mixlu_profile_read(ctx, arr, 16, ctypes.byref(cnt)), "mixlu_profile_read")
+    return {arr[i].name.decode(): {"launches": arr[i].launches, "ms": arr[i].ms,
+                                   "flops": arr[i].flops, "bytes": arr[i].bytes}
+            for i in range(min(cnt.value, 16))}
 
 
 # ------------------------------------------------------------ convenience
