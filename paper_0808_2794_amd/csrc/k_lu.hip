@@ -46,165 +46,187 @@ __device__ __forceinline__ unsigned long long dpp64(unsigned long long x) {
     const unsigned hi = dpp32<CTRL, RM>((unsigned)(x >> 32));
     return ((unsigned long long)hi << 32) | lo;
 }
-__device__ __forceinline__ unsigned long long umax64(unsigned long long a, unsigned long long b) {
-    return a > b ? a : b;
+// Wave-wide maximum of a float or double with the result in every lane
+// (read back as a uniform value).  For FP32 each step is one DPP-fused
+// v_max; FP64 moves both halves and takes v_max_f64.
+template <int CTRL, int RM> __device__ __forceinline__ float dppf(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(x), __float_as_int(x), CTRL,
+                                                      RM, 0xF, false));
 }
-// max over the wave of a 64-bit key; uniform result
-__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x) {
-    x = umax64(x, dpp64<0xB1, 0xF>(x));   // quad_perm [1,0,3,2]
-    x = umax64(x, dpp64<0x4E, 0xF>(x));   // quad_perm [2,3,0,1]
-    x = umax64(x, dpp64<0x141, 0xF>(x));  // row_half_mirror
-    x = umax64(x, dpp64<0x140, 0xF>(x));  // row_mirror
-    x = umax64(x, dpp64<0x142, 0xA>(x));  // row_bcast:15 into rows 1, 3
-    x = umax64(x, dpp64<0x143, 0xC>(x));  // row_bcast:31 into rows 2, 3
-    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)x, 63);
-    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(x >> 32), 63);
-    return ((unsigned long long)hi << 32) | lo;
+template <int CTRL, int RM> __device__ __forceinline__ double dppd(double x) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+    return __longlong_as_double((long long)dpp64<CTRL, RM>(u));
 }
-__device__ __forceinline__ double wave_max_f64(double x) {
-    auto step = [](double a, double b) { return a > b ? a : b; };
-    unsigned long long u = (unsigned long long)__double_as_longlong(x);
-    x = step(x, __longlong_as_double((long long)dpp64<0xB1, 0xF>(u)));
-    u = (unsigned long long)__double_as_longlong(x);
-    x = step(x, __longlong_as_double((long long)dpp64<0x4E, 0xF>(u)));
-    u = (unsigned long long)__double_as_longlong(x);
-    x = step(x, __longlong_as_double((long long)dpp64<0x141, 0xF>(u)));
-    u = (unsigned long long)__double_as_longlong(x);
-    x = step(x, __longlong_as_double((long long)dpp64<0x140, 0xF>(u)));
-    u = (unsigned long long)__double_as_longlong(x);
-    x = step(x, __longlong_as_double((long long)dpp64<0x142, 0xA>(u)));
-    u = (unsigned long long)__double_as_longlong(x);
-    x = step(x, __longlong_as_double((long long)dpp64<0x143, 0xC>(u)));
-    u = (unsigned long long)__double_as_longlong(x);
-    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, 63);
-    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), 63);
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+// Candidate values are |x| >= 0 or -1 (no candidate).  For FP32 they order
+// like their bit patterns read as signed integers, so the step is an integer
+// max, which takes a DPP operand directly (a float max would have to
+// canonicalize NaNs first).
+template <int CTRL, int RM> __device__ __forceinline__ int dpp_maxi(int x) {
+    // rows outside RM keep x: max(x, x) = x
+    return max(x, __builtin_amdgcn_update_dpp(x, x, CTRL, RM, 0xF, false));
+}
+template <typename T, int CTRL, int RM> __device__ __forceinline__ T dmax(T x) {
+    if constexpr (sizeof(T) == 4) return __int_as_float(dpp_maxi<CTRL, RM>(__float_as_int(x)));
+    else return fmax(x, dppd<CTRL, RM>(x));
+}
+template <typename T> __device__ __forceinline__ T readlane_t(T v, int lane) {
+    if constexpr (sizeof(T) == 4) {
+        return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+    } else {
+        const long long b = __double_as_longlong(v);
+        const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+        const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+        return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+    }
+}
+// max over all 64 lanes
+template <typename T> __device__ __forceinline__ T wave_max(T x) {
+    x = dmax<T, 0xB1, 0xF>(x);   // quad_perm [1,0,3,2]
+    x = dmax<T, 0x4E, 0xF>(x);   // quad_perm [2,3,0,1]
+    x = dmax<T, 0x141, 0xF>(x);  // row_half_mirror
+    x = dmax<T, 0x140, 0xF>(x);  // row_mirror
+    x = dmax<T, 0x142, 0xA>(x);  // row_bcast:15 into rows 1, 3
+    x = dmax<T, 0x143, 0xC>(x);  // row_bcast:31 into rows 2, 3
+    return readlane_t(x, 63);
+}
+// max over lanes 0..7 (the other lanes must hold -1)
+template <typename T> __device__ __forceinline__ T max8(T x) {
+    x = dmax<T, 0xB1, 0xF>(x);
+    x = dmax<T, 0x4E, 0xF>(x);
+    x = dmax<T, 0x141, 0xF>(x);
+    return readlane_t(x, 0);
+}
+// Index of the first lane whose predicate holds (64 if none).
+__device__ __forceinline__ int first_lane(bool pred) {
+    const unsigned long long m = __ballot(pred);
+    return m ? __ffsll((long long)m) - 1 : 64;
 }
 
-// Pivot candidate ordering: larger |value| first, then smaller row.  For
-// FP32 the pair packs into one 64-bit key (|v| bits << 32 | ~row) whose
-// unsigned maximum is the winner; FP64 values need their own 64 bits, so the
-// wave first takes max |v| and then the smallest row holding it.  Invalid
-// candidates have key 0 / value -1.
-template <typename T> struct Cand;
-template <> struct Cand<float> {
-    unsigned long long key;
-    __device__ static Cand make(float av, int row, bool ok) {
-        Cand c;
-        c.key = ok ? (((unsigned long long)__float_as_uint(av) << 32) | (unsigned)(~row)) : 0ull;
-        return c;
-    }
-    __device__ Cand wave_reduce() const {
-        Cand c;
-        c.key = wave_max_u64(key);
-        return c;
-    }
-    __device__ bool better(const Cand &o) const { return key > o.key; }
-    __device__ bool valid() const { return key != 0ull; }
-    __device__ int row() const { return (int)(~(unsigned)key); }
-    __device__ float value() const { return __uint_as_float((unsigned)(key >> 32)); }
-    __device__ unsigned word(int i) const { return i == 0 ? (unsigned)key : (unsigned)(key >> 32); }
-    __device__ static Cand from_words(const unsigned *w) {
-        Cand c;
-        c.key = ((unsigned long long)w[1] << 32) | w[0];
-        return c;
-    }
+// Pivot choice inside one wave: the largest |value| among the valid lanes,
+// the smallest lane (= smallest row) on ties.  Invalid lanes hold -1.
+template <typename T> struct WaveArgmax {
+    T val;    // winning |value| (-1 if no valid lane)
+    int lane; // winning lane (64 if none)
 };
-template <> struct Cand<double> {
-    double v;
-    int r;
-    __device__ static Cand make(double av, int row, bool ok) {
-        Cand c;
-        c.v = ok ? av : -1.0;
-        c.r = ok ? row : INT_MAX;
-        return c;
+template <typename T> __device__ __forceinline__ WaveArgmax<T> wave_argmax(T v) {
+    WaveArgmax<T> r;
+    r.val = wave_max(v);
+    r.lane = first_lane(r.val >= (T)0 && v == r.val);
+    return r;
+}
+
+// Compile-time loop: f(integral_constant<int, I>) for I = 0 .. N-1.
+template <int I, int N, class F> __device__ __forceinline__ void sfor(F &&f) {
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        sfor<I + 1, N>(f);
     }
-    __device__ Cand wave_reduce() const {
-        Cand c;
-        c.v = wave_max_f64(v);
-        // smallest row among the lanes holding the maximum: max of ~row
-        const unsigned long long k = (v == c.v) ? (unsigned long long)(unsigned)(~r) : 0ull;
-        c.r = (int)(~(unsigned)wave_max_u64(k));
-        return c;
-    }
-    __device__ bool better(const Cand &o) const { return v > o.v || (v == o.v && r < o.r); }
-    __device__ bool valid() const { return v >= 0.0; }
-    __device__ int row() const { return r; }
-    __device__ double value() const { return v; }
-    __device__ unsigned word(int i) const {
-        const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-        return i == 0 ? (unsigned)b : (i == 1 ? (unsigned)(b >> 32) : (unsigned)r);
-    }
-    __device__ static Cand from_words(const unsigned *w) {
-        Cand c;
-        c.v = __longlong_as_double((long long)(((unsigned long long)w[1] << 32) | w[0]));
-        c.r = (int)w[2];
-        return c;
-    }
+}
+
+// A register row as B / V vectors of V = 16 / sizeof(T) values: LDS copies
+// are then plain 16-byte moves with no repacking.
+template <typename T> struct Vq {
+    static constexpr int V = 16 / sizeof(T);
+    typedef T type __attribute__((ext_vector_type(V)));
 };
-
-// Register-row access with a uniform run-time column index: each switch below
-// expands to constant indices only, so the row stays in VGPRs.
-#define MIXLU_REP8(M, b) M(b + 0) M(b + 1) M(b + 2) M(b + 3) M(b + 4) M(b + 5) M(b + 6) M(b + 7)
-#define MIXLU_REP64(M)                                                                       \
-    MIXLU_REP8(M, 0) MIXLU_REP8(M, 8) MIXLU_REP8(M, 16) MIXLU_REP8(M, 24) MIXLU_REP8(M, 32)  \
-    MIXLU_REP8(M, 40) MIXLU_REP8(M, 48) MIXLU_REP8(M, 56)
-
-template <int B, typename T> __device__ __forceinline__ T row_get(const T (&a)[B], int j) {
-    T v = (T)0;
-    switch (j) {
-#define MIXLU_GET(c)                         \
-    case c:                                  \
-        if constexpr (c < B) { v = a[c]; }  \
-        break;
-        MIXLU_REP64(MIXLU_GET)
-#undef MIXLU_GET
-        default:
-            break;
-    }
-    return v;
-}
-
-template <int B, typename T> __device__ __forceinline__ void row_set(T (&a)[B], int j, T v) {
-    switch (j) {
-#define MIXLU_SET(c)                         \
-    case c:                                  \
-        if constexpr (c < B) { a[c] = v; }  \
-        break;
-        MIXLU_REP64(MIXLU_SET)
-#undef MIXLU_SET
-        default:
-            break;
-    }
-}
-
-// a[c] -= l * u[c] for c = j+1 .. B-1: enter at case j and fall through.
-template <int B, typename T>
-__device__ __forceinline__ void row_axpy_tail(T (&a)[B], const T (&u)[B], int j, T l) {
-    switch (j) {
-#define MIXLU_UPD(c)                                          \
-    case c:                                                   \
-        if constexpr (c + 1 < B) { a[c + 1] -= l * u[c + 1]; } \
-        [[fallthrough]];
-        MIXLU_REP64(MIXLU_UPD)
-#undef MIXLU_UPD
-        default:
-            break;
-    }
-}
-
-template <typename T, int B>
-__device__ __forceinline__ void row_to_lds(T *dst, const T (&a)[B]) {
+template <typename T, int NQ>
+__device__ __forceinline__ void row_to_lds(T *dst, const typename Vq<T>::type (&a)[NQ]) {
 #pragma unroll
-    for (int c = 0; c < B; ++c) dst[c] = a[c];
+    for (int q = 0; q < NQ; ++q) reinterpret_cast<typename Vq<T>::type *>(dst)[q] = a[q];
+}
+template <typename T, int NQ, int Q0 = 0>
+__device__ __forceinline__ void row_from_lds(typename Vq<T>::type (&a)[NQ], const T *src) {
+#pragma unroll
+    for (int q = Q0; q < NQ; ++q) a[q] = reinterpret_cast<const typename Vq<T>::type *>(src)[q];
+}
+
+// Pointer into LDS that keeps its address space through a call, so that
+// accesses compile to ds_* instructions (not flat ones, which wait on both
+// the memory and the LDS counters).
+typedef __attribute__((address_space(3))) unsigned lds_u32;
+
+struct ExchangeResult {
+    int ok;  // 0: a bounded wait gave up
+    int p;   // winning row (panel position), -1 if none
+    int qs;  // slot (workgroup) holding it
+};
+
+// Cross-workgroup step of one column (P > 1): publish this workgroup's best
+// (header: |value| words and row; thread tid < B*PWV publishes row word
+// `rw`), plus row j's word `dw` from workgroup 0; gather every slot into
+// `words` (all loads issued first, late words polled); pick the winner with
+// one wave argmax over the slot headers.  Kept out of line: one copy serves
+// all columns.
+template <typename T, int B>
+__device__ __noinline__ ExchangeResult panel_exchange(unsigned long long *X, lds_u32 *words, int P,
+                                                      int w, unsigned tag, unsigned h0,
+                                                      unsigned h1, unsigned h2, unsigned rw,
+                                                      unsigned dw, int *timeout) {
+    using G = PanelGeom<T, B>;
+    constexpr int TPB = kPanelTPB, PWV = G::PWV, HDR = G::HDR, SLOT = G::SLOT;
+    constexpr int DIAG = kPanelMaxWG * SLOT;
+    const int tid = threadIdx.x;
+    unsigned long long *slot = X + (size_t)w * SLOT;
+    if (tid < HDR) xstore(slot + tid, tag, tid == 0 ? h0 : (tid == 1 ? h1 : (tid == 2 ? h2 : 0u)));
+    if (tid < B * PWV) {
+        xstore(slot + HDR + tid, tag, rw);
+        if (w == 0) xstore(X + DIAG + tid, tag, dw);
+    }
+    bool bad = false;
+    const int nslot = P * SLOT;
+    const int total = nslot + B * PWV;
+    constexpr int MAXW = (kPanelMaxWG * SLOT + B * PWV + TPB - 1) / TPB;
+    unsigned long long wv[MAXW];
+#pragma unroll
+    for (int q = 0; q < MAXW; ++q) {
+        const int t = tid + q * TPB;
+        const int src = t < nslot ? t : DIAG + (t - nslot);
+        wv[q] = (t < total) ? xload(X + src) : 0ull;
+    }
+#pragma unroll
+    for (int q = 0; q < MAXW; ++q) {
+        const int t = tid + q * TPB;
+        if (t < total) {
+            const int src = t < nslot ? t : DIAG + (t - nslot);
+            unsigned v = (unsigned)wv[q];
+            if ((unsigned)(wv[q] >> 32) != tag && !bad) v = spin_tag(X + src, tag, timeout, bad);
+            words[src] = v;
+        }
+    }
+    ExchangeResult r{1, -1, 0};
+    if (__syncthreads_or(bad ? 1 : 0)) {
+        r.ok = 0;
+        return r;
+    }
+    // lane q of every wave takes slot header q; slots hold increasing rows,
+    // so the first lane with the maximum is also the smallest row
+    const int lane = tid & 63;
+    T hv = (T)-1;
+    int hp = 0;
+    if (lane < P) {
+        const unsigned w0 = words[lane * SLOT], w1 = words[lane * SLOT + 1];
+        if constexpr (sizeof(T) == 4) hv = __uint_as_float(w0);
+        else hv = __longlong_as_double((long long)(((unsigned long long)w1 << 32) | w0));
+        hp = (int)words[lane * SLOT + 2];
+    }
+    const WaveArgmax<T> best = wave_argmax(hv);
+    if (best.lane < P) {
+        r.p = __builtin_amdgcn_readlane(hp, best.lane);
+        r.qs = best.lane;
+    }
+    return r;
 }
 
 // One thread owns one panel row (position pos = w * TPB + tid, relative to
-// row k0).  Columns are processed by a run-time loop.  Per column: each wave
-// reduces its candidates on DPP and its winning lane stages its row in LDS;
-// after one barrier every thread picks the workgroup's winner.  When the
-// panel spans several workgroups they exchange (key, row) and row j through
-// tagged words in global memory: one round trip and one more barrier.
+// row k0), kept in registers; the B columns are unrolled so every register
+// access has a constant index.  Per column: each wave takes its argmax on
+// DPP (value) and a ballot (first row among equals) and its winning lane
+// stages its row in LDS; after one barrier every thread picks the
+// workgroup's winner the same way over the wave results.  When the panel
+// spans several workgroups they exchange (|value|, row index, row) and row j
+// through tagged words in global memory: one round trip and one more
+// barrier.  Multipliers use the reciprocal of the pivot when it is a normal
+// number (as LAPACK's getf2 does) and a division otherwise.
 template <typename T, int B>
 __global__ __launch_bounds__(kPanelTPB) void k_panel(T *__restrict__ W, int ldw, int k0, int m,
                                                      int *__restrict__ ipiv,
@@ -215,128 +237,78 @@ __global__ __launch_bounds__(kPanelTPB) void k_panel(T *__restrict__ W, int ldw,
     if (w >= P) return;
     using G = PanelGeom<T, B>;
     constexpr int TPB = kPanelTPB, NW = TPB / 64;
-    constexpr int PWV = G::PWV, HDR = G::HDR, SLOT = G::SLOT, PAR = G::PAR;
+    constexpr int HDR = G::HDR, SLOT = G::SLOT, PAR = G::PAR, PWV = G::PWV;
     constexpr int DIAG = kPanelMaxWG * SLOT;  // offset of row j's words in a parity
-    constexpr int V = 16 / sizeof(T);         // values per 16-byte LDS access
     static_assert(kPanelRows == 1, "one row per thread");
-    static_assert(B % V == 0, "row length");
+    static_assert(NW <= 8, "workgroup winner is picked over at most 8 waves");
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int pos = w * TPB + tid;
     const bool live = pos < m;
 
     __shared__ __attribute__((aligned(16))) T s_wrow[2][NW][B];  // each wave's best row
     __shared__ __attribute__((aligned(16))) T s_drow[2][B];      // row j (held by workgroup 0)
-    __shared__ __attribute__((aligned(16))) unsigned s_words[2][kPanelMaxWG * SLOT + B * PWV];
-    __shared__ unsigned s_wkey[2][NW][4];
+    __shared__ __attribute__((aligned(16))) unsigned s_words[2][kPanelMaxWG * SLOT + PWV * B];
+    __shared__ T s_wval[2][NW];
+    __shared__ int s_wpos[2][NW];
     __shared__ int s_piv[B];  // pivot rows, written to global memory after the loop
-    __shared__ int s_bad;
 
-    T a[B];
+    constexpr int V = Vq<T>::V, NQ = B / V;
+    using vq = typename Vq<T>::type;
+    vq a[NQ];
     if (live) {
-        const T *src = W + (size_t)(k0 + pos) * ldw + k0;
+        const vq *src = reinterpret_cast<const vq *>(W + (size_t)(k0 + pos) * ldw + k0);
 #pragma unroll
-        for (int c = 0; c < B; ++c) a[c] = src[c];
+        for (int q = 0; q < NQ; ++q) a[q] = src[q];
     } else {
 #pragma unroll
-        for (int c = 0; c < B; ++c) a[c] = (T)0;
+        for (int q = 0; q < NQ; ++q)
+#pragma unroll
+            for (int e = 0; e < V; ++e) a[q][e] = (T)0;
     }
-    if (tid == 0) s_bad = 0;
+    bool dead = false;
+    const T tiny = sizeof(T) == 4 ? (T)1.17549435e-38f : (T)2.2250738585072014e-308;
 
-    auto row_out = [&](T *dst) {
-#pragma unroll
-        for (int c = 0; c < B; c += V) {
-            typedef T vec_t __attribute__((ext_vector_type(V)));
-            vec_t v;
-#pragma unroll
-            for (int e = 0; e < V; ++e) v[e] = a[c + e];
-            *reinterpret_cast<vec_t *>(dst + c) = v;
-        }
-    };
-    auto row_in = [&](T (&dst)[B], const T *src) {
-#pragma unroll
-        for (int c = 0; c < B; c += V) {
-            typedef T vec_t __attribute__((ext_vector_type(V)));
-            const vec_t v = *reinterpret_cast<const vec_t *>(src + c);
-#pragma unroll
-            for (int e = 0; e < V; ++e) dst[c + e] = v[e];
-        }
-    };
-
-#pragma unroll 1
-    for (int j = 0; j < B; ++j) {
-        const int par = j & 1;
-        const unsigned tag = (unsigned)(k0 + j + 1);
-        // --- wave candidates
-        const T aj = row_get<B>(a, j);
-        const T av = fabs(aj);
-        const Cand<T> mine = Cand<T>::make(av, pos, live && pos >= j && av == av);
-        const Cand<T> wbest = mine.wave_reduce();
-        if (wbest.valid() && pos == wbest.row()) row_out(s_wrow[par][wave]);
-        if (pos == j) row_out(s_drow[par]);
+    sfor<0, B>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        constexpr int par = j & 1;
+        if (dead) return;
+        // --- wave argmax
+        const T av = fabs(a[j / V][j % V]);
+        const T cv = (live && pos >= j && av == av) ? av : (T)-1;
+        const WaveArgmax<T> wa = wave_argmax(cv);
+        if (lane == wa.lane) row_to_lds<T, NQ>(s_wrow[par][wave], a);
+        if (pos == j) row_to_lds<T, NQ>(s_drow[par], a);
         if (lane == 0) {
-#pragma unroll
-            for (int i = 0; i < 3; ++i) s_wkey[par][wave][i] = wbest.word(i);
+            s_wval[par][wave] = wa.val;
+            s_wpos[par][wave] = w * TPB + wave * 64 + wa.lane;
         }
         __syncthreads();
-        // --- workgroup winner (every thread, same answer)
-        Cand<T> gbest = Cand<T>::from_words(s_wkey[par][0]);
-        int qw = 0;
-#pragma unroll
-        for (int q = 1; q < NW; ++q) {
-            const Cand<T> c = Cand<T>::from_words(s_wkey[par][q]);
-            if (c.better(gbest)) {
-                gbest = c;
-                qw = q;
-            }
+        // --- workgroup winner (every wave, same answer): waves hold increasing rows
+        T kv = (T)-1;
+        int kp = 0;
+        if (lane < NW) {
+            kv = s_wval[par][lane];
+            kp = s_wpos[par][lane];
         }
-        const T *prow = s_wrow[par][qw];
+        const T gmax = max8(kv);
+        const int qw = first_lane(lane < NW && gmax >= (T)0 && kv == gmax);
+        int p = qw < NW ? __builtin_amdgcn_readlane(kp, qw) : -1;
+        const T *prow = s_wrow[par][qw < NW ? qw : 0];
         const T *drow = s_drow[par];
-        int p = gbest.row();
         if (P > 1) {
-            unsigned long long *X = xb + (size_t)par * PAR;
-            unsigned long long *slot = X + (size_t)w * SLOT;
-            if (tid < HDR) xstore(slot + tid, tag, tid < 3 ? gbest.word(tid) : 0u);
-            if (tid < B * PWV) {
-                xstore(slot + HDR + tid, tag, Words<T>::get(prow[tid / PWV], tid % PWV));
-                if (w == 0) xstore(X + DIAG + tid, tag, Words<T>::get(drow[tid / PWV], tid % PWV));
+            const unsigned rw = tid < B * PWV ? Words<T>::get(prow[tid / PWV], tid % PWV) : 0u;
+            const unsigned dw = tid < B * PWV ? Words<T>::get(drow[tid / PWV], tid % PWV) : 0u;
+            const ExchangeResult ex = panel_exchange<T, B>(
+                xb + (size_t)par * PAR, (lds_u32 *)&s_words[par][0], P, w,
+                (unsigned)(k0 + j + 1), Words<T>::get(gmax, 0),
+                PWV > 1 ? Words<T>::get(gmax, PWV - 1) : 0u, (unsigned)p, rw, dw,
+                &status[ST_TIMEOUT]);
+            if (!ex.ok) {
+                dead = true;
+                return;
             }
-            // gather every slot: issue all loads, then poll the late ones
-            bool bad = false;
-            const int nslot = P * SLOT;
-            const int total = nslot + B * PWV;
-            constexpr int MAXW = (kPanelMaxWG * SLOT + B * PWV + TPB - 1) / TPB;
-            unsigned long long wv[MAXW];
-#pragma unroll
-            for (int q = 0; q < MAXW; ++q) {
-                const int t = tid + q * TPB;
-                const int src = t < nslot ? t : DIAG + (t - nslot);
-                wv[q] = (t < total) ? xload(X + src) : 0ull;
-            }
-#pragma unroll
-            for (int q = 0; q < MAXW; ++q) {
-                const int t = tid + q * TPB;
-                if (t < total) {
-                    const int src = t < nslot ? t : DIAG + (t - nslot);
-                    unsigned v = (unsigned)wv[q];
-                    if ((unsigned)(wv[q] >> 32) != tag && !bad)
-                        v = spin_tag(X + src, tag, &status[ST_TIMEOUT], bad);
-                    s_words[par][src] = v;
-                }
-            }
-            if (bad) s_bad = 1;
-            __syncthreads();
-            if (s_bad) return;  // uniform: every thread reads s_bad after the barrier
-            Cand<T> best = Cand<T>::from_words(&s_words[par][0]);
-            int qs = 0;
-            for (int q = 1; q < P; ++q) {
-                const Cand<T> c = Cand<T>::from_words(&s_words[par][q * SLOT]);
-                if (c.better(best)) {
-                    best = c;
-                    qs = q;
-                }
-            }
-            p = best.row();
-            prow = reinterpret_cast<const T *>(&s_words[par][qs * SLOT + HDR]);
+            p = ex.p;
+            prow = reinterpret_cast<const T *>(&s_words[par][ex.qs * SLOT + HDR]);
             drow = reinterpret_cast<const T *>(&s_words[par][DIAG]);
         }
         if (p < j || p >= m) {  // no usable candidate (all NaN): keep row j
@@ -344,34 +316,33 @@ __global__ __launch_bounds__(kPanelTPB) void k_panel(T *__restrict__ W, int ldw,
             prow = drow;
         }
         const T piv = prow[j];
+        const bool normal = fabs(piv) >= tiny && isfinite(piv);
+        const T rcp = (T)1 / piv;
         // no global stores inside the loop: a barrier waits for every
         // outstanding store of the wave, which would put a memory round trip
         // on each column
         if (tid == 0) s_piv[j] = (!(piv != (T)0) || !isfinite(piv)) ? -(p + 1) : p;
-        T pr[B];
-        row_in(pr, prow);
-        // --- swap rows j and p (whole panel rows); then the multiplier
-        T aj2 = aj;
+        // --- swap rows j and p (whole panel rows)
         if (p != j) {
-            if (pos == j) {
-#pragma unroll
-                for (int c = 0; c < B; ++c) a[c] = pr[c];
-                aj2 = piv;
-            } else if (pos == p) {
-                row_in(a, drow);
-                aj2 = drow[j];
-            }
+            if (pos == j) row_from_lds<T, NQ>(a, prow);
+            else if (pos == p) row_from_lds<T, NQ>(a, drow);
         }
+        // --- multiplier and rank-1 update of the remaining panel columns
         if (live && pos > j && piv != (T)0) {
-            const T l = aj2 / piv;
-            row_set<B>(a, j, l);
-            row_axpy_tail<B>(a, pr, j, l);
-        }
-    }
-    if (live) {
-        T *dst = W + (size_t)(k0 + pos) * ldw + k0;
+            vq u[NQ];
+            row_from_lds<T, NQ, (j + 1) / V>(u, prow);
+            const T ajv = a[j / V][j % V];
+            const T l = normal ? ajv * rcp : ajv / piv;
+            a[j / V][j % V] = l;
 #pragma unroll
-        for (int c = 0; c < B; ++c) dst[c] = a[c];
+            for (int c = j + 1; c < B; ++c) a[c / V][c % V] -= l * u[c / V][c % V];
+        }
+    });
+    if (dead) return;  // uniform: every thread saw the same exchange result
+    if (live) {
+        vq *dst = reinterpret_cast<vq *>(W + (size_t)(k0 + pos) * ldw + k0);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) dst[q] = a[q];
     }
     __syncthreads();
     if (w == 0 && tid < B) {
