@@ -131,7 +131,8 @@ int mixlu_set_stream(mixlu_ctx_t ctx, void *stream);
 typedef enum {
     MIXLU_OP_GESV = 0,  /* mixlu_dxgesv, or mixlu_getrf + getrs/refine      */
     MIXLU_OP_POSV = 1,  /* mixlu_dxposv, or mixlu_potrf + getrs/refine      */
-    MIXLU_OP_DGESV = 2  /* mixlu_dgesv (FP64 LU, no refinement)             */
+    MIXLU_OP_DGESV = 2, /* mixlu_dgesv (FP64 LU, no refinement)             */
+    MIXLU_OP_DPOSV = 3  /* mixlu_dposv (FP64 Cholesky, no refinement)       */
 } mixlu_op;
 
 /* Bytes of device workspace the operation needs for (prec, n, nrhs) with
@@ -168,8 +169,17 @@ int mixlu_getrf(mixlu_ctx_t ctx, int prec, int n, const double *A, int lda,
                 void *work, size_t lwork, const mixlu_opts *o,
                 mixlu_factor *F, int *info);
 
-/* Cholesky A = L L^T of a symmetric positive definite A (lower triangle of
-   the row-major A is read; SPOTRF of Section 3.1.1). */
+/* Cholesky factorization of a symmetric positive definite A (the SPOTRF of
+   Section 3.1.1): symmetric power-of-two scaling S (when equilibration is
+   on), W = fl(S A S), blocked right-looking W = L L^T with the trailing
+   update in prec (FP32 or BF16/FP16 operands with FP32 accumulation).  Only
+   the lower triangle of the row-major A is used by the factorization; the
+   refinement residual uses the whole stored A, which must be symmetric.
+   The factor is stored as W = L' U' with L' = L D^{-1} (unit lower),
+   U' = D L^T and an identity permutation, so mixlu_getrs and mixlu_refine
+   apply to it unchanged.  A non-positive or non-finite pivot is reported
+   like a zero pivot of mixlu_getrf (info = k+1 for FP64, F->lowp_status =
+   -3 otherwise).  Synchronizes the stream. */
 int mixlu_potrf(mixlu_ctx_t ctx, int prec, int n, const double *A, int lda,
                 void *work, size_t lwork, const mixlu_opts *o,
                 mixlu_factor *F, int *info);
@@ -197,7 +207,9 @@ int mixlu_dxgesv(mixlu_ctx_t ctx, int prec, int n, int nrhs, const double *A,
                  void *work, size_t lwork, const mixlu_opts *o,
                  mixlu_report *rep);
 
-/* Same for symmetric positive definite A (DSPOSV-style, Cholesky). */
+/* Same for symmetric positive definite A (DSPOSV-style, Cholesky; see
+   mixlu_potrf).  The fallback is the FP64 Cholesky; if that breaks down
+   too, rep->info = k+1 (A not positive definite) and X is undefined. */
 int mixlu_dxposv(mixlu_ctx_t ctx, int prec, int n, int nrhs, const double *A,
                  int lda, const double *B, int ldb, double *X, int ldx,
                  void *work, size_t lwork, const mixlu_opts *o,
@@ -207,6 +219,14 @@ int mixlu_dxposv(mixlu_ctx_t ctx, int prec, int n, int nrhs, const double *A,
    (the DGESV comparator, and the factorization the fallback uses).
    A is const; *info (host) as in mixlu_getrf.  Synchronizes. */
 int mixlu_dgesv(mixlu_ctx_t ctx, int n, int nrhs, const double *A, int lda,
+                const double *B, int ldb, double *X, int ldx, void *work,
+                size_t lwork, int *info);
+
+/* FP64 Cholesky and FP64 triangular solves, no refinement (the DPOSV
+   comparator, and the factorization the Cholesky fallback uses).  *info
+   (host): 0, or k+1 when the leading minor of order k+1 is not positive
+   definite.  Synchronizes. */
+int mixlu_dposv(mixlu_ctx_t ctx, int n, int nrhs, const double *A, int lda,
                 const double *B, int ldb, double *X, int ldx, void *work,
                 size_t lwork, int *info);
 
@@ -220,7 +240,7 @@ int mixlu_outer_update(mixlu_ctx_t ctx, int n, int nrhs, const double *Gb,
 /* ------------------------------------------------------ kernel timing */
 /* Per-kernel-class timing for measurement: with profiling enabled, the
    launches of the main kernel classes ("panel_getf2", "trailing_update",
-   "pack_operands", "trsv", "residual") are bracketed by HIP events on the
+   "pack_operands", "trsv", "residual", "panel_potf2") are bracketed by HIP events on the
    context's stream, and each class accumulates its launch count, total
    device time and the algorithmic flops and bytes of its launches (the work
    the method requires, not the traffic the kernels generate).  Enabling

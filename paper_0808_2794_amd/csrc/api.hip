@@ -28,9 +28,9 @@ struct ProfPending {
     hipEvent_t a, b;
     double flops, bytes;
 };
-enum ProfClass { PC_PANEL, PC_TRAIL, PC_PACK, PC_TRSV, PC_RESID, PC_COUNT };
+enum ProfClass { PC_PANEL, PC_TRAIL, PC_PACK, PC_TRSV, PC_RESID, PC_CPANEL, PC_COUNT };
 static const char *const kProfNames[PC_COUNT] = {"panel_getf2", "trailing_update", "pack_operands",
-                                                 "trsv", "residual"};
+                                                 "trsv", "residual", "panel_potf2"};
 struct Prof {
     bool on = false;
     std::vector<hipEvent_t> pool;
@@ -152,8 +152,8 @@ struct ProfCall {  // binds the context's profiler to this thread for one API ca
 size_t mixlu::plan_layout(Layout &L, int op, int prec, int n, int nrhs, const mixlu_opts &o) {
     L.n = n;
     L.nrhs = nrhs < 1 ? 1 : nrhs;
-    L.prec = (op == MIXLU_OP_DGESV) ? MIXLU_FP64 : prec;
-    L.kind = (op == MIXLU_OP_POSV) ? 1 : 0;
+    L.prec = (op == MIXLU_OP_DGESV || op == MIXLU_OP_DPOSV) ? MIXLU_FP64 : prec;
+    L.kind = (op == MIXLU_OP_POSV || op == MIXLU_OP_DPOSV) ? 1 : 0;
     L.nb = o.nb > 0 ? o.nb : auto_nb(n);
     L.npad = round_up(n > 0 ? n : 1, L.nb);
     L.fallback = (L.prec != MIXLU_FP64) && o.fallback;
@@ -308,6 +308,64 @@ int factor_lu(hipStream_t s, void *work, const Layout &L, size_t woff, int trail
     return MIXLU_OK;
 }
 
+// Blocked right-looking Cholesky of the symmetric W (lower triangle used):
+// per 64-column step the diagonal block and the rows below it (k_chol_panel),
+// the update of the rest of the outer block in FP32/FP64, then per outer
+// block the symmetric trailing update A22 -= L21 L21^T on the lower tiles
+// (FP32/FP64, or BF16/FP16 operands on MFMA).  Finally L L^T is rewritten as
+// L' U' (unit lower L' = L D^{-1}, U' = D L^T) and perm = identity, so the LU
+// solves apply unchanged.
+template <typename T>
+int factor_chol(hipStream_t s, void *work, const Layout &L, size_t woff, int trail_prec) {
+    constexpr int B = 64;
+    const int np = L.npad, nb = L.nb;
+    T *W = at<T>(work, woff);
+    T *diag = at<T>(work, L.tmp);
+    int *status = at<int>(work, L.status);
+    if (nb % B || nb > 512) return MIXLU_ERR_NOT_IMPLEMENTED;
+    HIPCK(launch_iota(at<int>(work, L.perm), np, s));
+    HIPCK(launch_iota(at<int>(work, L.ipiv), np, s));
+    auto Wp = [&](int r, int c) { return W + (size_t)r * np + c; };
+    for (int K0 = 0; K0 < np; K0 += nb) {
+        const int kend = K0 + nb;
+        for (int k = K0; k < kend; k += B) {
+            const int below = np - k - B;
+            {
+                ProfScope ps(PC_CPANEL, B * B * (B / 3.0) + (double)below * B * B,
+                             ((double)B * B + 2.0 * below * B) * sizeof(T), s);
+                HIPCK(launch_chol_panel<T>(W, np, k, below, diag, status, s));
+            }
+            if (k + B < kend)
+                HIPCK(launch_gemm<T>(below, kend - k - B, B, Wp(k + B, k), np, Wp(k + B, k), np,
+                                     Wp(k + B, k + B), np, s, 1, 1));
+        }
+        if (kend < np) {
+            const int nr = np - kend;
+            if (trail_prec == MIXLU_FP64 || trail_prec == MIXLU_FP32) {
+                ProfScope ps(PC_TRAIL, 1.0 * nr * (nr + 1.0) * nb,
+                             (1.0 * nr * (nr + 1.0) + 1.0 * nr * nb) * sizeof(T), s);
+                HIPCK(launch_gemm<T>(nr, nr, nb, Wp(kend, K0), np, Wp(kend, K0), np,
+                                     Wp(kend, kend), np, s, 1, 1));
+            } else {
+                if constexpr (sizeof(T) == 4) {
+                    void *Ap = at<void>(work, L.Ap);
+                    {
+                        ProfScope ps(PC_PACK, 0.0, 1.0 * nr * nb * (4 + 2), s);
+                        HIPCK(launch_pack(trail_prec, Wp(kend, K0), np, nr, nb, 0, Ap, status, s));
+                    }
+                    ProfScope ps(PC_TRAIL, 1.0 * nr * (nr + 1.0) * nb,
+                                 4.0 * nr * (nr + 1.0) + 2.0 * nr * nb, s);
+                    HIPCK(launch_gemm_lowp(trail_prec, nr, nr, nb, Ap, Ap, Wp(kend, kend), np, s, 1));
+                } else {
+                    return MIXLU_ERR_NOT_IMPLEMENTED;
+                }
+            }
+        }
+    }
+    HIPCK(launch_chol_to_lu<T>(W, np, np, diag, s));
+    return MIXLU_OK;
+}
+
 void init_status(hipStream_t s, int *status) {
     // ST_BREAKDOWN and ST_CHOL start at INT_MAX (no failure), the rest at 0
     static const int zero = 0;
@@ -315,6 +373,11 @@ void init_status(hipStream_t s, int *status) {
     launch_fill_u32(reinterpret_cast<unsigned *>(status), 0u, ST_COUNT, s);
     launch_fill_u32(reinterpret_cast<unsigned *>(status + ST_BREAKDOWN), (unsigned)INT_MAX, 1, s);
     launch_fill_u32(reinterpret_cast<unsigned *>(status + ST_CHOL), (unsigned)INT_MAX, 1, s);
+}
+
+// Failure column + 1 of the factorization (INT_MAX: none).
+int breakdown_of(const Layout &L, const int st[ST_COUNT]) {
+    return L.kind == 1 ? st[ST_CHOL] : st[ST_BREAKDOWN];
 }
 
 // Read status words and the two matrix norms (synchronizes).
@@ -345,9 +408,16 @@ int convert_and_factor(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t wof
     int *status = at<int>(work, L.status);
     init_status(s, status);
     HIPCK(launch_row_stats(A, lda, n, tmp, tmp + np, s));
-    HIPCK(launch_finish_rows(n, np, tmp, tmp + np, R, equil, norms, s));
-    HIPCK(launch_col_stats(A, lda, n, np, R, tmp + 2 * (size_t)np, C, equil, norms, s));
+    if (L.kind == 1) {
+        // ||A||_inf from the row sums; symmetric scaling keeps W symmetric
+        HIPCK(launch_finish_rows(n, np, tmp, tmp + np, R, 0, norms, s));
+        HIPCK(launch_sym_scale(A, lda, n, np, R, C, equil, s));
+    } else {
+        HIPCK(launch_finish_rows(n, np, tmp, tmp + np, R, equil, norms, s));
+        HIPCK(launch_col_stats(A, lda, n, np, R, tmp + 2 * (size_t)np, C, equil, norms, s));
+    }
     HIPCK(launch_convert<T>(A, lda, n, np, R, C, at<T>(work, woff), np, status, s));
+    if (L.kind == 1) return factor_chol<T>(s, work, L, woff, trail_prec);
     return factor_lu<T>(s, work, L, woff, trail_prec);
 }
 
@@ -498,13 +568,119 @@ int fp64_path(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t woff, const 
     double nrm[2];
     RETCK(read_status(ctx, L, work, st, nrm));
     if (st[ST_TIMEOUT]) return MIXLU_ERR_DEVICE_TIMEOUT;
-    *info = st[ST_BREAKDOWN] == INT_MAX ? 0 : st[ST_BREAKDOWN];
+    *info = breakdown_of(L, st) == INT_MAX ? 0 : breakdown_of(L, st);
     if (anorm_out) *anorm_out = nrm[0];
     if (*info) return MIXLU_OK;
     RETCK(lu_solve<double>(s, work, L, woff, nrhs, B, ldb, 0, X, ldx, 0, 1));
     if (refine) RETCK(refine_loop<double>(ctx, work, L, woff, A, lda, B, ldb, X, ldx, 0, nrhs,
                                           nrm[0], o, *res));
     return MIXLU_OK;
+}
+
+// Conversion and factorization of A into the workspace for op GESV (LU) or
+// POSV (Cholesky) and fill F; status words are read back (synchronizes).
+int factor_into(mixlu_ctx_s *ctx, const Layout &L, int prec, const double *A, int lda,
+                void *work, size_t lwork, const mixlu_opts &o, mixlu_factor *F, int *info) {
+    fill_factor(F, L, work, lwork, o.layout);
+    *info = 0;
+    const int equil = equil_for(prec, o);
+    F->equilibrated = equil;
+    if (prec == MIXLU_FP64)
+        RETCK(convert_and_factor<double>(ctx, work, L, L.W, A, lda, equil, MIXLU_FP64));
+    else
+        RETCK(convert_and_factor<float>(ctx, work, L, L.W, A, lda, equil, prec));
+    int st[ST_COUNT];
+    double nrm[2];
+    RETCK(read_status(ctx, L, work, st, nrm));
+    if (st[ST_TIMEOUT]) return MIXLU_ERR_DEVICE_TIMEOUT;
+    const int brk = breakdown_of(L, st);
+    if (prec == MIXLU_FP64) {
+        *info = brk == INT_MAX ? 0 : brk;
+    } else {
+        if (st[ST_OVERFLOW]) F->lowp_status = -2;
+        else if (brk != INT_MAX) F->lowp_status = -3;
+    }
+    return MIXLU_OK;
+}
+
+int factor_entry(mixlu_ctx_s *ctx, int op, int prec, int n, const double *A, int lda, void *work,
+                 size_t lwork, const mixlu_opts *o, mixlu_factor *F, int *info) {
+    if (!prec_valid(prec)) return -2;
+    if (n < 0) return -3;
+    if (n > 0 && !A) return -4;
+    if (lda < (n > 1 ? n : 1)) return -5;
+    if (!work) return -6;
+    if (!F) return -9;
+    if (!info) return -10;
+    const mixlu_opts op_ = opts_or_default(o);
+    if (op_.layout != MIXLU_ROW_MAJOR) return MIXLU_ERR_NOT_IMPLEMENTED;
+    Layout L{};
+    plan_layout(L, op, prec, n, 1, op_);
+    if (lwork < L.total) return MIXLU_ERR_WORKSPACE;
+    if (L.npad > kPanelMaxWG * kPanelRowsPerWG) return MIXLU_ERR_NOT_IMPLEMENTED;
+    if (n == 0) {
+        fill_factor(F, L, work, lwork, op_.layout);
+        *info = 0;
+        return MIXLU_OK;
+    }
+    return factor_into(ctx, L, prec, A, lda, work, lwork, op_, F, info);
+}
+
+// One-shot solve (op GESV or POSV): factor, x_0, refinement, fallback.
+int dx_entry(mixlu_ctx_s *ctx, int op, int prec, int n, int nrhs, const double *A, int lda,
+             const double *B, int ldb, double *X, int ldx, void *work, size_t lwork,
+             const mixlu_opts *o, mixlu_report *rep) {
+    if (!prec_valid(prec)) return -2;
+    RETCK(check_common(ctx, 3, n, nrhs, lda, ldb, ldx, A, B, X));
+    if (!work) return -11;
+    if (!rep) return -14;
+    const mixlu_opts op_ = opts_or_default(o);
+    if (op_.layout != MIXLU_ROW_MAJOR) return MIXLU_ERR_NOT_IMPLEMENTED;
+    std::memset(rep, 0, sizeof(*rep));
+    Layout L{};
+    plan_layout(L, op, prec, n, nrhs, op_);
+    if (lwork < L.total) return MIXLU_ERR_WORKSPACE;
+    if (n == 0 || nrhs == 0) {
+        rep->converged = 1;
+        rep->prec = prec;
+        return MIXLU_OK;
+    }
+    if (L.npad > kPanelMaxWG * kPanelRowsPerWG) return MIXLU_ERR_NOT_IMPLEMENTED;
+    mixlu_factor F;
+    int info = 0;
+    RETCK(factor_into(ctx, L, prec, A, lda, work, lwork, op_, &F, &info));
+    if (info) {
+        rep->info = info;
+        rep->prec = MIXLU_FP64;
+        rep->iter = -1;
+        return MIXLU_OK;
+    }
+    if (F.lowp_status == 0) {
+        if (prec == MIXLU_FP64)
+            RETCK(lu_solve<double>(ctx->stream, work, L, L.W, nrhs, B, ldb, 0, X, ldx, 0, 1));
+        else
+            RETCK(lu_solve<float>(ctx->stream, work, L, L.W, nrhs, B, ldb, 0, X, ldx, 0, 1));
+    }
+    return mixlu_refine(ctx, &F, 0, A, lda, B, ldb, X, ldx, &op_, rep);
+}
+
+// FP64 factorization and solve without refinement (op DGESV or DPOSV).
+int d_entry(mixlu_ctx_s *ctx, int op, int n, int nrhs, const double *A, int lda, const double *B,
+            int ldb, double *X, int ldx, void *work, size_t lwork, int *info) {
+    RETCK(check_common(ctx, 2, n, nrhs, lda, ldb, ldx, A, B, X));
+    if (!work) return -9;
+    if (!info) return -11;
+    mixlu_opts op_;
+    mixlu_default_opts(&op_);
+    Layout L{};
+    plan_layout(L, op, MIXLU_FP64, n, nrhs, op_);
+    if (lwork < L.total) return MIXLU_ERR_WORKSPACE;
+    *info = 0;
+    if (n == 0 || nrhs == 0) return MIXLU_OK;
+    if (L.npad > kPanelMaxWG * kPanelRowsPerWG) return MIXLU_ERR_NOT_IMPLEMENTED;
+    LoopResult res{};
+    return fp64_path(ctx, work, L, L.W, A, lda, B, ldb, X, ldx, nrhs, op_, false, info, &res,
+                     nullptr);
 }
 
 }  // namespace
@@ -573,12 +749,11 @@ int mixlu_set_stream(mixlu_ctx_t ctx, void *stream) {
 int mixlu_workspace_size(mixlu_ctx_t ctx, int op, int prec, int n, int nrhs,
                          const mixlu_opts *o, size_t *bytes) {
     if (!ctx) return -1;
-    if (op < MIXLU_OP_GESV || op > MIXLU_OP_DGESV) return -2;
+    if (op < MIXLU_OP_GESV || op > MIXLU_OP_DPOSV) return -2;
     if (!prec_valid(prec)) return -3;
     if (n < 0) return -4;
     if (nrhs < 0) return -5;
     if (!bytes) return -7;
-    if (op == MIXLU_OP_POSV) return MIXLU_ERR_NOT_IMPLEMENTED;
     const mixlu_opts op_ = opts_or_default(o);
     Layout L{};
     *bytes = plan_layout(L, op, prec, n, nrhs, op_);
@@ -589,46 +764,14 @@ int mixlu_getrf(mixlu_ctx_t ctx, int prec, int n, const double *A, int lda, void
                 size_t lwork, const mixlu_opts *o, mixlu_factor *F, int *info) {
     if (!ctx) return -1;
     ProfCall pc_(ctx);
-    if (!prec_valid(prec)) return -2;
-    if (n < 0) return -3;
-    if (n > 0 && !A) return -4;
-    if (lda < (n > 1 ? n : 1)) return -5;
-    if (!work) return -6;
-    if (!F) return -9;
-    if (!info) return -10;
-    const mixlu_opts op_ = opts_or_default(o);
-    if (op_.layout != MIXLU_ROW_MAJOR) return MIXLU_ERR_NOT_IMPLEMENTED;
-    Layout L{};
-    plan_layout(L, MIXLU_OP_GESV, prec, n, 1, op_);
-    if (lwork < L.total) return MIXLU_ERR_WORKSPACE;
-    if (L.npad > kPanelMaxWG * kPanelRowsPerWG) return MIXLU_ERR_NOT_IMPLEMENTED;
-    fill_factor(F, L, work, lwork, op_.layout);
-    *info = 0;
-    if (n == 0) return MIXLU_OK;
-    const int equil = equil_for(prec, op_);
-    F->equilibrated = equil;
-    if (prec == MIXLU_FP64)
-        RETCK(convert_and_factor<double>(ctx, work, L, L.W, A, lda, 0, MIXLU_FP64));
-    else
-        RETCK(convert_and_factor<float>(ctx, work, L, L.W, A, lda, equil, prec));
-    int st[ST_COUNT];
-    double nrm[2];
-    RETCK(read_status(ctx, L, work, st, nrm));
-    if (st[ST_TIMEOUT]) return MIXLU_ERR_DEVICE_TIMEOUT;
-    if (prec == MIXLU_FP64) {
-        *info = st[ST_BREAKDOWN] == INT_MAX ? 0 : st[ST_BREAKDOWN];
-    } else {
-        if (st[ST_OVERFLOW]) F->lowp_status = -2;
-        else if (st[ST_BREAKDOWN] != INT_MAX) F->lowp_status = -3;
-    }
-    return MIXLU_OK;
+    return factor_entry(ctx, MIXLU_OP_GESV, prec, n, A, lda, work, lwork, o, F, info);
 }
 
 int mixlu_potrf(mixlu_ctx_t ctx, int prec, int n, const double *A, int lda, void *work,
                 size_t lwork, const mixlu_opts *o, mixlu_factor *F, int *info) {
-    (void)ctx; (void)prec; (void)n; (void)A; (void)lda; (void)work; (void)lwork; (void)o;
-    (void)F; (void)info;
-    return MIXLU_ERR_NOT_IMPLEMENTED;
+    if (!ctx) return -1;
+    ProfCall pc_(ctx);
+    return factor_entry(ctx, MIXLU_OP_POSV, prec, n, A, lda, work, lwork, o, F, info);
 }
 
 int mixlu_getrs(mixlu_ctx_t ctx, const mixlu_factor *F, int trans, const int nrhs,
@@ -724,85 +867,31 @@ int mixlu_dxgesv(mixlu_ctx_t ctx, int prec, int n, int nrhs, const double *A, in
                  const mixlu_opts *o, mixlu_report *rep) {
     if (!ctx) return -1;
     ProfCall pc_(ctx);
-    if (!prec_valid(prec)) return -2;
-    RETCK(check_common(ctx, 3, n, nrhs, lda, ldb, ldx, A, B, X));
-    if (!work) return -11;
-    if (!rep) return -14;
-    const mixlu_opts op_ = opts_or_default(o);
-    if (op_.layout != MIXLU_ROW_MAJOR) return MIXLU_ERR_NOT_IMPLEMENTED;
-    std::memset(rep, 0, sizeof(*rep));
-    Layout L{};
-    plan_layout(L, MIXLU_OP_GESV, prec, n, nrhs, op_);
-    if (lwork < L.total) return MIXLU_ERR_WORKSPACE;
-    if (n == 0 || nrhs == 0) {
-        rep->converged = 1;
-        rep->prec = prec;
-        return MIXLU_OK;
-    }
-    if (L.npad > kPanelMaxWG * kPanelRowsPerWG) return MIXLU_ERR_NOT_IMPLEMENTED;
-    mixlu_factor F;
-    int info = 0;
-    {
-        // getrf with the solve's nrhs
-        fill_factor(&F, L, work, lwork, op_.layout);
-        const int equil = equil_for(prec, op_);
-        F.equilibrated = equil;
-        if (prec == MIXLU_FP64)
-            RETCK(convert_and_factor<double>(ctx, work, L, L.W, A, lda, 0, MIXLU_FP64));
-        else
-            RETCK(convert_and_factor<float>(ctx, work, L, L.W, A, lda, equil, prec));
-        int st[ST_COUNT];
-        double nrm[2];
-        RETCK(read_status(ctx, L, work, st, nrm));
-        if (st[ST_TIMEOUT]) return MIXLU_ERR_DEVICE_TIMEOUT;
-        if (prec == MIXLU_FP64) {
-            info = st[ST_BREAKDOWN] == INT_MAX ? 0 : st[ST_BREAKDOWN];
-        } else {
-            if (st[ST_OVERFLOW]) F.lowp_status = -2;
-            else if (st[ST_BREAKDOWN] != INT_MAX) F.lowp_status = -3;
-        }
-    }
-    if (info) {
-        rep->info = info;
-        rep->prec = MIXLU_FP64;
-        rep->iter = -1;
-        return MIXLU_OK;
-    }
-    if (F.lowp_status == 0) {
-        if (prec == MIXLU_FP64)
-            RETCK(lu_solve<double>(ctx->stream, work, L, L.W, nrhs, B, ldb, 0, X, ldx, 0, 1));
-        else
-            RETCK(lu_solve<float>(ctx->stream, work, L, L.W, nrhs, B, ldb, 0, X, ldx, 0, 1));
-    }
-    return mixlu_refine(ctx, &F, 0, A, lda, B, ldb, X, ldx, &op_, rep);
+    return dx_entry(ctx, MIXLU_OP_GESV, prec, n, nrhs, A, lda, B, ldb, X, ldx, work, lwork, o,
+                    rep);
 }
 
 int mixlu_dxposv(mixlu_ctx_t ctx, int prec, int n, int nrhs, const double *A, int lda,
                  const double *B, int ldb, double *X, int ldx, void *work, size_t lwork,
                  const mixlu_opts *o, mixlu_report *rep) {
-    (void)ctx; (void)prec; (void)n; (void)nrhs; (void)A; (void)lda; (void)B; (void)ldb; (void)X;
-    (void)ldx; (void)work; (void)lwork; (void)o; (void)rep;
-    return MIXLU_ERR_NOT_IMPLEMENTED;
+    if (!ctx) return -1;
+    ProfCall pc_(ctx);
+    return dx_entry(ctx, MIXLU_OP_POSV, prec, n, nrhs, A, lda, B, ldb, X, ldx, work, lwork, o,
+                    rep);
 }
 
 int mixlu_dgesv(mixlu_ctx_t ctx, int n, int nrhs, const double *A, int lda, const double *B,
                 int ldb, double *X, int ldx, void *work, size_t lwork, int *info) {
     if (!ctx) return -1;
     ProfCall pc_(ctx);
-    RETCK(check_common(ctx, 2, n, nrhs, lda, ldb, ldx, A, B, X));
-    if (!work) return -9;
-    if (!info) return -11;
-    mixlu_opts op_;
-    mixlu_default_opts(&op_);
-    Layout L{};
-    plan_layout(L, MIXLU_OP_DGESV, MIXLU_FP64, n, nrhs, op_);
-    if (lwork < L.total) return MIXLU_ERR_WORKSPACE;
-    *info = 0;
-    if (n == 0 || nrhs == 0) return MIXLU_OK;
-    if (L.npad > kPanelMaxWG * kPanelRowsPerWG) return MIXLU_ERR_NOT_IMPLEMENTED;
-    LoopResult res{};
-    return fp64_path(ctx, work, L, L.W, A, lda, B, ldb, X, ldx, nrhs, op_, false, info, &res,
-                     nullptr);
+    return d_entry(ctx, MIXLU_OP_DGESV, n, nrhs, A, lda, B, ldb, X, ldx, work, lwork, info);
+}
+
+int mixlu_dposv(mixlu_ctx_t ctx, int n, int nrhs, const double *A, int lda, const double *B,
+                int ldb, double *X, int ldx, void *work, size_t lwork, int *info) {
+    if (!ctx) return -1;
+    ProfCall pc_(ctx);
+    return d_entry(ctx, MIXLU_OP_DPOSV, n, nrhs, A, lda, B, ldb, X, ldx, work, lwork, info);
 }
 
 int mixlu_profile_enable(mixlu_ctx_t ctx, int on) {

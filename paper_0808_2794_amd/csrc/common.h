@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <type_traits>
 
 #include "../../include/mixlu.h"
 
@@ -68,6 +69,31 @@ __device__ inline unsigned spin_tag(const unsigned long long *p, unsigned tag, i
     return (unsigned)w;
 }
 
+// Uniform value of lane `lane` (a compile-time or wave-uniform index).
+template <typename T> __device__ __forceinline__ T readlane_t(T v, int lane) {
+    if constexpr (sizeof(T) == 4) {
+        return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+    } else {
+        const long long b = __double_as_longlong(v);
+        const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+        const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+        return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+    }
+}
+// Compile-time loop: f(integral_constant<int, I>) for I = 0 .. N-1.
+template <int I, int N, class F> __device__ __forceinline__ void sfor(F &&f) {
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        sfor<I + 1, N>(f);
+    }
+}
+
+// A register row as B / V vectors of V = 16 / sizeof(T) values: LDS copies
+// are then plain 16-byte moves with no repacking.
+template <typename T> struct Vq {
+    static constexpr int V = 16 / sizeof(T);
+    typedef T type __attribute__((ext_vector_type(V)));
+};
 template <typename T> struct Words;
 template <> struct Words<float> {
     static constexpr int n = 1;
@@ -138,11 +164,19 @@ template <typename T>
 hipError_t launch_trsm_diag(const T *Ldiag, int ldl, T *X, int ldx, int ncols, hipStream_t s);
 template <typename T>
 hipError_t launch_gemm(int M, int N, int K, const T *A, int lda, const T *B, int ldb, T *C,
-                       int ldc, hipStream_t s);
+                       int ldc, hipStream_t s, int transb = 0, int lower = 0);
 hipError_t launch_pack(int prec, const float *W, int ldw, int rows, int cols, int transpose,
                        void *dst, int *status, hipStream_t s);
 hipError_t launch_gemm_lowp(int prec, int M, int N, int K, const void *Ap, const void *Bp,
-                            float *C, int ldc, hipStream_t s);
+                            float *C, int ldc, hipStream_t s, int lower = 0);
+
+// a3.5: Cholesky variant (k_chol.hip)
+hipError_t launch_sym_scale(const double *A, int lda, int n, int npad, double *R, double *C,
+                            int equil, hipStream_t s);
+template <typename T>
+hipError_t launch_chol_panel(T *W, int ldw, int k, int below, T *diag, int *status, hipStream_t s);
+template <typename T>
+hipError_t launch_chol_to_lu(T *W, int ldw, int npad, const T *diag, hipStream_t s);
 
 // a4-a8: solves and refinement (k_solve.hip)
 template <typename Tw>

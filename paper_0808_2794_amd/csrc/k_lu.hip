@@ -69,16 +69,6 @@ template <typename T, int CTRL, int RM> __device__ __forceinline__ T dmax(T x) {
     if constexpr (sizeof(T) == 4) return __int_as_float(dpp_maxi<CTRL, RM>(__float_as_int(x)));
     else return fmax(x, dppd<CTRL, RM>(x));
 }
-template <typename T> __device__ __forceinline__ T readlane_t(T v, int lane) {
-    if constexpr (sizeof(T) == 4) {
-        return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
-    } else {
-        const long long b = __double_as_longlong(v);
-        const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
-        const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-        return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-    }
-}
 // max over all 64 lanes
 template <typename T> __device__ __forceinline__ T wave_max(T x) {
     x = dmax<T, 0xB1, 0xF>(x);   // quad_perm [1,0,3,2]
@@ -115,20 +105,6 @@ template <typename T> __device__ __forceinline__ WaveArgmax<T> wave_argmax(T v) 
     return r;
 }
 
-// Compile-time loop: f(integral_constant<int, I>) for I = 0 .. N-1.
-template <int I, int N, class F> __device__ __forceinline__ void sfor(F &&f) {
-    if constexpr (I < N) {
-        f(std::integral_constant<int, I>{});
-        sfor<I + 1, N>(f);
-    }
-}
-
-// A register row as B / V vectors of V = 16 / sizeof(T) values: LDS copies
-// are then plain 16-byte moves with no repacking.
-template <typename T> struct Vq {
-    static constexpr int V = 16 / sizeof(T);
-    typedef T type __attribute__((ext_vector_type(V)));
-};
 template <typename T, int NQ>
 __device__ __forceinline__ void row_to_lds(T *dst, const typename Vq<T>::type (&a)[NQ]) {
 #pragma unroll
@@ -567,15 +543,19 @@ template <> struct Mfma<double> {
 
 // 64x64 output tile per workgroup, 4 waves of 32x32, K step 16.
 // 16x16x4 operand layout: lane l supplies A[l%16][l/16] and B[l/16][l%16].
-template <typename T>
+// TB: B is given transposed (Bm is N x K row-major, as L21 for the Cholesky
+// update C -= L21 L21^T).  lower != 0: only tiles that touch the lower
+// triangle (col <= row) of C are computed.
+template <typename T, bool TB>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const T *__restrict__ A, int lda,
                                               const T *__restrict__ Bm, int ldb, T *__restrict__ C,
-                                              int ldc) {
+                                              int ldc, int lower) {
     constexpr int BM = 64, BN = 64, BK = 16;
     __shared__ T sA[BK][BM + 4];
     __shared__ T sB[BK][BN + 4];
     using acc_t = typename Mfma<T>::acc_t;
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    if (lower && n0 > m0 + BM - 1) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     acc_t acc[2][2];
@@ -593,7 +573,15 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const T *__re
                 sA[kk + q][r] = (gr < M && gk < K) ? A[(size_t)gr * lda + gk] : (T)0;
             }
         }
-        {
+        if constexpr (TB) {
+            const int c = tid >> 2, kk = (tid & 3) * 4;
+            const int gc = n0 + c;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int gk = k0 + kk + q;
+                sB[kk + q][c] = (gc < N && gk < K) ? Bm[(size_t)gc * ldb + gk] : (T)0;
+            }
+        } else {
             const int kk = tid >> 4, c = (tid & 15) * 4;
             const int gk = k0 + kk;
 #pragma unroll
@@ -631,16 +619,19 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const T *__re
 
 template <typename T>
 hipError_t launch_gemm(int M, int N, int K, const T *A, int lda, const T *B, int ldb, T *C,
-                       int ldc, hipStream_t s) {
+                       int ldc, hipStream_t s, int transb, int lower) {
     if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
-    k_gemm<T><<<dim3((N + 63) / 64, (M + 63) / 64), dim3(256), 0, s>>>(M, N, K, A, lda, B, ldb, C,
-                                                                      ldc);
+    const dim3 grid((N + 63) / 64, (M + 63) / 64);
+    if (transb)
+        k_gemm<T, true><<<grid, dim3(256), 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc, lower);
+    else
+        k_gemm<T, false><<<grid, dim3(256), 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc, lower);
     return hipGetLastError();
 }
 template hipError_t launch_gemm<float>(int, int, int, const float *, int, const float *, int,
-                                       float *, int, hipStream_t);
+                                       float *, int, hipStream_t, int, int);
 template hipError_t launch_gemm<double>(int, int, int, const double *, int, const double *, int,
-                                        double *, int, hipStream_t);
+                                        double *, int, hipStream_t, int, int);
 
 // ======================================================================
 // Low-precision trailing update
@@ -727,19 +718,21 @@ hipError_t launch_pack(int prec, const float *W, int ldw, int rows, int cols, in
     return hipGetLastError();
 }
 
-// C[M x N] -= Ap[M x K] * Bp[N x K]^T, Ap and Bp K-contiguous; 128 x 128 tile,
+// C[M x N] -= Ap[M x K] * Bp[N x K]^T, Ap and Bp K-contiguous (Bp = Ap for the
+// Cholesky update; lower != 0 skips tiles above the diagonal); 128 x 128 tile,
 // 4 waves of 64 x 64 (4 x 4 MFMA 16x16x32 blocks), K step 64.
 // 16x16x32 operand layout: lane l supplies A[l%16][8*(l/16) .. +8] and
 // B[8*(l/16) .. +8][l%16]; result as for 16x16x4.
 template <typename H>
 __global__ __launch_bounds__(256) void k_gemm_lowp(int M, int N, int K, const H *__restrict__ Ap,
                                                    const H *__restrict__ Bp, float *__restrict__ C,
-                                                   int ldc) {
+                                                   int ldc, int lower) {
     constexpr int BM = 128, BN = 128, BK = 64, PITCH = BK + 8;
     using vec_t = typename LowP<H>::vec_t;
     __shared__ __attribute__((aligned(16))) H sA[BM * PITCH];
     __shared__ __attribute__((aligned(16))) H sB[BN * PITCH];
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    if (lower && n0 > m0 + BM - 1) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     f32x4 acc[4][4];
@@ -791,16 +784,16 @@ __global__ __launch_bounds__(256) void k_gemm_lowp(int M, int N, int K, const H 
 }
 
 hipError_t launch_gemm_lowp(int prec, int M, int N, int K, const void *Ap, const void *Bp,
-                            float *C, int ldc, hipStream_t s) {
+                            float *C, int ldc, hipStream_t s, int lower) {
     if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
     if (K % 64) return hipErrorInvalidValue;
     dim3 grid((N + 127) / 128, (M + 127) / 128);
     if (prec == MIXLU_FP16)
         k_gemm_lowp<_Float16><<<grid, dim3(256), 0, s>>>(M, N, K, (const _Float16 *)Ap,
-                                                         (const _Float16 *)Bp, C, ldc);
+                                                         (const _Float16 *)Bp, C, ldc, lower);
     else if (prec == MIXLU_BF16)
         k_gemm_lowp<__bf16><<<grid, dim3(256), 0, s>>>(M, N, K, (const __bf16 *)Ap,
-                                                       (const __bf16 *)Bp, C, ldc);
+                                                       (const __bf16 *)Bp, C, ldc, lower);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libmixlu.so")
 FP64, FP32, BF16, FP16, FP8 = 0, 1, 2, 3, 4
 PREC = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "fp16": FP16, "fp8": FP8}
 PREC_NAME = {v: k for k, v in PREC.items()}
-OP_GESV, OP_POSV, OP_DGESV = 0, 1, 2
+OP_GESV, OP_POSV, OP_DGESV, OP_DPOSV = 0, 1, 2, 3
 ROW_MAJOR, COL_MAJOR = 0, 1
 
 OK = 0
@@ -61,7 +61,7 @@ class mixlu_kstat(ctypes.Structure):
 EXPORTS = ("mixlu_status_string", "mixlu_default_opts", "mixlu_create", "mixlu_destroy",
            "mixlu_set_stream", "mixlu_workspace_size", "mixlu_getrf", "mixlu_potrf",
            "mixlu_getrs", "mixlu_refine", "mixlu_dxgesv", "mixlu_dxposv", "mixlu_dgesv",
-           "mixlu_outer_update", "mixlu_profile_enable", "mixlu_profile_read")
+           "mixlu_dposv", "mixlu_outer_update", "mixlu_profile_enable", "mixlu_profile_read")
 
 _lib = None
 
@@ -89,6 +89,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "mixlu_dxgesv": ([P, I, I, I, P, I, P, I, P, I, P, S, P, P], I),
         "mixlu_dxposv": ([P, I, I, I, P, I, P, I, P, I, P, S, P, P], I),
         "mixlu_dgesv": ([P, I, I, P, I, P, I, P, I, P, S, P], I),
+        "mixlu_dposv": ([P, I, I, P, I, P, I, P, I, P, S, P], I),
         "mixlu_outer_update": ([P, I, I, P, I, P, I, P, I, D, D], I),
         "mixlu_profile_enable": ([P, I], I),
         "mixlu_profile_read": ([P, P, I, P], I),
@@ -172,24 +173,50 @@ def mixlu_dxgesv(ctx, prec: int, A, B, X, work, opts=None) -> mixlu_report:
     return rep
 
 
-def mixlu_dgesv(ctx, A, B, X, work) -> int:
+def mixlu_dxposv(ctx, prec: int, A, B, X, work, opts=None) -> mixlu_report:
+    rep = mixlu_report()
+    n, nrhs = B.shape
+    check(load().mixlu_dxposv(ctx, prec, n, nrhs, _p(A), _ld(A, n), _p(B), _ld(B, n), _p(X),
+                              _ld(X, n), _p(work), work.numel() * work.element_size(),
+                              None if opts is None else ctypes.byref(opts), ctypes.byref(rep)),
+          "mixlu_dxposv")
+    return rep
+
+
+def _d_solve(name, ctx, A, B, X, work) -> int:
     info = ctypes.c_int()
     n, nrhs = B.shape
-    check(load().mixlu_dgesv(ctx, n, nrhs, _p(A), _ld(A, n), _p(B), _ld(B, n), _p(X), _ld(X, n),
-                             _p(work), work.numel() * work.element_size(), ctypes.byref(info)),
-          "mixlu_dgesv")
+    check(getattr(load(), name)(ctx, n, nrhs, _p(A), _ld(A, n), _p(B), _ld(B, n), _p(X),
+                                _ld(X, n), _p(work), work.numel() * work.element_size(),
+                                ctypes.byref(info)), name)
     return info.value
 
 
-def mixlu_getrf(ctx, prec: int, A, work, opts=None):
+def mixlu_dgesv(ctx, A, B, X, work) -> int:
+    return _d_solve("mixlu_dgesv", ctx, A, B, X, work)
+
+
+def mixlu_dposv(ctx, A, B, X, work) -> int:
+    return _d_solve("mixlu_dposv", ctx, A, B, X, work)
+
+
+def _factor(name, ctx, prec: int, A, work, opts=None):
     F = mixlu_factor()
     info = ctypes.c_int()
     n = A.shape[0]
-    check(load().mixlu_getrf(ctx, prec, n, _p(A), _ld(A, n), _p(work),
-                             work.numel() * work.element_size(),
-                             None if opts is None else ctypes.byref(opts), ctypes.byref(F),
-                             ctypes.byref(info)), "mixlu_getrf")
+    check(getattr(load(), name)(ctx, prec, n, _p(A), _ld(A, n), _p(work),
+                                work.numel() * work.element_size(),
+                                None if opts is None else ctypes.byref(opts), ctypes.byref(F),
+                                ctypes.byref(info)), name)
     return F, info.value
+
+
+def mixlu_getrf(ctx, prec: int, A, work, opts=None):
+    return _factor("mixlu_getrf", ctx, prec, A, work, opts)
+
+
+def mixlu_potrf(ctx, prec: int, A, work, opts=None):
+    return _factor("mixlu_potrf", ctx, prec, A, work, opts)
 
 
 def mixlu_getrs(ctx, F: mixlu_factor, B, X, trans: int = 0) -> None:
@@ -283,11 +310,29 @@ class Solver:
         rep = mixlu_dxgesv(self.ctx, p, A, B2, X, work, o)
         return Result(X.reshape(-1) if vec else X, rep.as_dict())
 
-    def dgesv(self, A, B) -> Result:
+    def dxposv(self, A, B, prec="fp32", opts=None, **kw) -> Result:
+        """Symmetric positive definite A: Cholesky in prec + FP64 refinement."""
+        import torch
+
+        p = PREC[prec] if isinstance(prec, str) else prec
+        o = opts if opts is not None else default_opts(**kw)
+        A, B2, vec = self._prep(A, B)
+        X = torch.empty_like(B2)
+        work = self.workspace(OP_POSV, p, A.shape[0], B2.shape[1], o)
+        rep = mixlu_dxposv(self.ctx, p, A, B2, X, work, o)
+        return Result(X.reshape(-1) if vec else X, rep.as_dict())
+
+    def _d(self, op, fn, A, B) -> Result:
         import torch
 
         A, B2, vec = self._prep(A, B)
         X = torch.empty_like(B2)
-        work = self.workspace(OP_DGESV, FP64, A.shape[0], B2.shape[1])
-        info = mixlu_dgesv(self.ctx, A, B2, X, work)
+        work = self.workspace(op, FP64, A.shape[0], B2.shape[1])
+        info = fn(self.ctx, A, B2, X, work)
         return Result(X.reshape(-1) if vec else X, {"info": info})
+
+    def dgesv(self, A, B) -> Result:
+        return self._d(OP_DGESV, mixlu_dgesv, A, B)
+
+    def dposv(self, A, B) -> Result:
+        return self._d(OP_DPOSV, mixlu_dposv, A, B)
