@@ -80,7 +80,12 @@ typedef struct {
                          low-precision copy only                            */
     int fallback;     /* 1 (default): on failure factor in FP64 and refine  */
     int nb;           /* outer block width of the factorization, 0 = auto   */
-    int layout;       /* mixlu_layout of A, B and X                          */
+    int layout;       /* mixlu_layout of A, B and X.  Row-major (default):
+                         element (i, j) at A[i * lda + j], B, X n x nrhs with
+                         ld >= nrhs.  Column-major (LAPACK): A[i + j * lda],
+                         B, X with ld >= n; the factorization then works on
+                         the row-major matrix M = A^T that the memory holds
+                         and the solves with A are transposed solves with M */
     double stall;     /* stall ratio: refinement is declared stalled when
                          ||r_k|| >= stall * ||r_{k-1}|| twice in a row
                          (k >= 2) or ||r_k|| >= ||r_{k-1}|| once (k >= 3);
@@ -109,7 +114,7 @@ typedef struct {
                       zero pivot in column k (A singular; X undefined)     */
     int prec;      /* mixlu_prec of the factors that produced X           */
     int fallback_iter; /* corrections applied by the FP64 refinement      */
-    double anorm;  /* ||A||_inf                                          */
+    double anorm;  /* ||op(A)||_inf (||A||_1 for a transposed solve)      */
     double rnorm;  /* max over columns of ||b - A x||_inf (FP64, final x) */
     double xnorm;  /* max over columns of ||x||_inf                       */
     double berr;   /* max over columns of ||r|| / (||A|| ||x||)           */
@@ -153,7 +158,8 @@ typedef struct {
     int layout;        /* layout of the A it was computed from             */
     int equilibrated;  /* 1 when R, C scaling was applied                  */
     int lowp_status;   /* 0 ok; -2 conversion overflow; -3 breakdown       */
-    int nrhs_max;      /* right-hand sides the workspace was sized for     */
+    int nrhs_max;      /* most right-hand sides one solve may have: what
+                          the workspace given to the factorization holds  */
     void *work;        /* the workspace (device)                           */
     size_t lwork;
     size_t off[16];    /* internal offsets into work                       */
@@ -186,7 +192,10 @@ int mixlu_potrf(mixlu_ctx_t ctx, int prec, int n, const double *A, int lda,
 
 /* Low-precision solve only (Algorithm 1 steps 2-3): X = op(A)^{-1} B with
    the stored factors, computed in the factor's precision and promoted to
-   FP64.  trans = 1 solves A^T X = B.  B, X device, n x nrhs. */
+   FP64.  trans = 1 solves A^T X = B with the same factors (W = R A C,
+   P W = L U: X = R P^T L^{-T} U^{-T} C B), as the adjoint of a solve needs.
+   B, X device, n x nrhs (nrhs <= the nrhs the workspace was sized for), in
+   the factor's layout.  Asynchronous on the context's stream. */
 int mixlu_getrs(mixlu_ctx_t ctx, const mixlu_factor *F, int trans, int nrhs,
                 const double *B, int ldb, double *X, int ldx);
 
@@ -194,11 +203,13 @@ int mixlu_getrs(mixlu_ctx_t ctx, const mixlu_factor *F, int trans, int nrhs,
    r = B - op(A) X in FP64 with the original A, correction solved with the
    factors, X += Z in FP64, until the stopping test holds for every column
    or the policy declares failure (then, when o->fallback is set, an FP64
-   factorization in the workspace finishes the job).  rep (host) is filled;
-   the stream is synchronized. */
-int mixlu_refine(mixlu_ctx_t ctx, mixlu_factor *F, int trans, const double *A,
-                 int lda, const double *B, int ldb, double *X, int ldx,
-                 const mixlu_opts *o, mixlu_report *rep);
+   factorization in the workspace finishes the job).  trans = 1 refines
+   A^T X = B (residual B - A^T X in FP64, stopping test with ||A||_1).
+   B and X are n x nrhs, nrhs <= F->nrhs_max.  rep (host) is filled; the
+   stream is synchronized. */
+int mixlu_refine(mixlu_ctx_t ctx, mixlu_factor *F, int trans, int nrhs,
+                 const double *A, int lda, const double *B, int ldb, double *X,
+                 int ldx, const mixlu_opts *o, mixlu_report *rep);
 
 /* One-shot mixed-precision solve A X = B (DSGESV-style): factor in prec,
    x_0, refinement, FP64 fallback.  A, B (const) and X are device memory. */

@@ -421,33 +421,39 @@ int convert_and_factor(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t wof
     return factor_lu<T>(s, work, L, woff, trail_prec);
 }
 
-// Low-precision solve: X (=|+=) C * U^{-1} L^{-1} P (R * rhs), rhs FP64.
+// Low-precision solve with the factors of W = R M C, P W = L U:
+//   trans = 0: X (=|+=) C U^{-1} L^{-1} P (R rhs)          (M X = rhs)
+//   trans = 1: X (=|+=) R P^T L^{-T} U^{-T} (C rhs)        (M^T X = rhs)
+// rhs FP64; the factor's precision Tw inside.
 template <typename Tw>
 int lu_solve(hipStream_t s, void *work, const Layout &L, size_t woff, int nrhs,
-             const double *rhs, int ldr, int rhs_cm, double *X, int ldx, int x_cm, int assign) {
+             const double *rhs, int ldr, int rhs_cm, double *X, int ldx, int x_cm, int assign,
+             int trans) {
     const int n = L.n, np = L.npad;
     const Tw *W = at<Tw>(work, woff);
     Tw *Y = at<Tw>(work, L.vec_y);
     int *status = at<int>(work, L.status);
     double *xnorm = at<double>(work, L.norms) + 4 + L.nrhs;
     auto *ybuf = at<unsigned long long>(work, L.ybuf);
-    HIPCK(launch_rhs_gather<Tw>(n, np, nrhs, rhs, ldr, rhs_cm, at<int>(work, L.perm),
-                                at<double>(work, L.R), Y, nrhs, s));
+    const int *perm = at<int>(work, L.perm);
+    const double *R = at<double>(work, L.R), *C = at<double>(work, L.C);
+    HIPCK(launch_rhs_gather<Tw>(n, np, nrhs, rhs, ldr, rhs_cm, trans ? nullptr : perm,
+                                trans ? C : R, Y, nrhs, s));
     for (int c0 = 0; c0 < nrhs; c0 += kTrsvNRT) {
         const int nc = nrhs - c0 < kTrsvNRT ? nrhs - c0 : kTrsvNRT;
         const double tb = 0.5 * np * (np + 64.0) * sizeof(Tw) + 2.0 * np * nc * sizeof(Tw);
         {
             ProfScope ps(PC_TRSV, (double)np * np * nc, tb, s);
-            HIPCK(launch_trsv<Tw>(0, W, np, np, Y + c0, nrhs, nc, ybuf, status, s));
+            HIPCK(launch_trsv<Tw>(0, trans, W, np, np, Y + c0, nrhs, nc, ybuf, status, s));
         }
         {
             ProfScope ps(PC_TRSV, (double)np * np * nc, tb, s);
-            HIPCK(launch_trsv<Tw>(1, W, np, np, Y + c0, nrhs, nc, ybuf, status, s));
+            HIPCK(launch_trsv<Tw>(1, trans, W, np, np, Y + c0, nrhs, nc, ybuf, status, s));
         }
     }
     HIPCK(launch_fill_f64(xnorm, 0.0, nrhs, s));
-    HIPCK(launch_x_update<Tw>(n, nrhs, assign, Y, nrhs, at<double>(work, L.C), X, ldx, x_cm,
-                              xnorm, s));
+    HIPCK(launch_x_update<Tw>(n, np, nrhs, assign, Y, nrhs, trans ? perm : nullptr, trans ? R : C,
+                              X, ldx, x_cm, xnorm, s));
     return MIXLU_OK;
 }
 
@@ -463,7 +469,7 @@ struct LoopResult {
 template <typename Tw>
 int refine_loop(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t woff, const double *A,
                 int lda, const double *B, int ldb, double *X, int ldx, int cm, int nrhs,
-                double anorm, const mixlu_opts &o, LoopResult &res) {
+                double anorm, const mixlu_opts &o, LoopResult &res, int trans) {
     hipStream_t s = ctx->stream;
     const int n = L.n;
     double *Rv = at<double>(work, L.vec_r);
@@ -477,20 +483,28 @@ int refine_loop(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t woff, cons
     res = LoopResult{0, 0, 0.0, 0.0, 0.0};
     for (int k = 0;; ++k) {
         HIPCK(launch_fill_f64(rnorm, 0.0, nrhs, s));
+        HIPCK(launch_fill_f64(xnorm, 0.0, nrhs, s));
         {
             ProfScope ps(PC_RESID, 2.0 * n * n * nrhs,
                          8.0 * n * n + 8.0 * n * nrhs * 3.0, s);
-            HIPCK(launch_residual(n, nrhs, A, lda, X, ldx, B, ldb, cm, Rv, nrhs, rnorm, s));
+            if (trans)
+                HIPCK(launch_residual_t(n, nrhs, A, lda, X, ldx, B, ldb, cm, Rv, nrhs, rnorm,
+                                        xnorm, at<double>(work, L.tmp), s));
+            else
+                HIPCK(launch_residual(n, nrhs, A, lda, X, ldx, B, ldb, cm, Rv, nrhs, rnorm, xnorm,
+                                      s));
         }
-        HIPCK(hipMemcpyAsync(ctx->hbuf, rnorm, (size_t)2 * L.nrhs * 8, hipMemcpyDeviceToHost, s));
-        HIPCK(hipMemcpyAsync(ctx->hbuf + 2 * L.nrhs, status, ST_COUNT * 4, hipMemcpyDeviceToHost,
+        // hbuf: ||r|| of the nrhs columns, their ||x||, then the status words
+        HIPCK(hipMemcpyAsync(ctx->hbuf, rnorm, (size_t)nrhs * 8, hipMemcpyDeviceToHost, s));
+        HIPCK(hipMemcpyAsync(ctx->hbuf + nrhs, xnorm, (size_t)nrhs * 8, hipMemcpyDeviceToHost, s));
+        HIPCK(hipMemcpyAsync(ctx->hbuf + 2 * nrhs, status, ST_COUNT * 4, hipMemcpyDeviceToHost,
                              s));
         HIPCK(hipStreamSynchronize(s));
         int stl[ST_COUNT];
-        std::memcpy(stl, ctx->hbuf + 2 * L.nrhs, ST_COUNT * 4);
+        std::memcpy(stl, ctx->hbuf + 2 * nrhs, ST_COUNT * 4);
         if (stl[ST_TIMEOUT]) return MIXLU_ERR_DEVICE_TIMEOUT;
         const double *rn = ctx->hbuf;
-        const double *xn = ctx->hbuf + L.nrhs;
+        const double *xn = ctx->hbuf + nrhs;
         bool all_ok = true, nonfinite = false, stalled = false;
         res.rnorm = 0.0;
         res.xnorm = 0.0;
@@ -525,7 +539,7 @@ int refine_loop(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t woff, cons
             res.iters = -(o.itermax + 1);
             return MIXLU_OK;
         }
-        RETCK(lu_solve<Tw>(s, work, L, woff, nrhs, Rv, nrhs, 0, X, ldx, cm, 0));
+        RETCK(lu_solve<Tw>(s, work, L, woff, nrhs, Rv, nrhs, 0, X, ldx, cm, 0, trans));
     }
 }
 
@@ -533,18 +547,24 @@ int refine_loop(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t woff, cons
 // position of n in the caller's signature, followed by nrhs, A, lda, B, ldb,
 // X, ldx.
 int check_common(mixlu_ctx_s *ctx, int pn, int n, int nrhs, int lda, int ldb, int ldx,
-                 const void *A, const void *B, const void *X) {
+                 const void *A, const void *B, const void *X, int cm = 0) {
     if (!ctx) return -1;
     if (n < 0) return -pn;
     if (nrhs < 0) return -(pn + 1);
     if (n > 0 && !A) return -(pn + 2);
     if (lda < (n > 1 ? n : 1)) return -(pn + 3);
+    const int ldmin = cm ? (n > 1 ? n : 1) : (nrhs > 1 ? nrhs : 1);
     if (n > 0 && nrhs > 0 && !B) return -(pn + 4);
-    if (ldb < (nrhs > 1 ? nrhs : 1)) return -(pn + 5);
+    if (ldb < ldmin) return -(pn + 5);
     if (n > 0 && nrhs > 0 && !X) return -(pn + 6);
-    if (ldx < (nrhs > 1 ? nrhs : 1)) return -(pn + 7);
+    if (ldx < ldmin) return -(pn + 7);
     return MIXLU_OK;
 }
+
+// Effective operation on the stored matrix M: a column-major A is read as
+// the row-major M = A^T, so op(A) X = B becomes M^T X = B for op = identity.
+// A symmetric (Cholesky) factor needs no transposition.
+int eff_trans(const Layout &L, int trans, int cm) { return L.kind == 1 ? 0 : (trans ^ cm); }
 
 mixlu_opts opts_or_default(const mixlu_opts *o) {
     mixlu_opts d;
@@ -558,10 +578,10 @@ int equil_for(int prec, const mixlu_opts &o) {
 }
 
 // FP64 factor of A in the W64 region (or W when the factor itself is FP64),
-// x solve, and (optionally) FP64 refinement.
+// x solve, and (optionally) FP64 refinement; trans/cm as for lu_solve.
 int fp64_path(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t woff, const double *A,
               int lda, const double *B, int ldb, double *X, int ldx, int nrhs,
-              const mixlu_opts &o, bool refine, int *info, LoopResult *res, double *anorm_out) {
+              const mixlu_opts &o, bool refine, int *info, LoopResult *res, int trans, int cm) {
     hipStream_t s = ctx->stream;
     RETCK(convert_and_factor<double>(ctx, work, L, woff, A, lda, 0, MIXLU_FP64));
     int st[ST_COUNT];
@@ -569,11 +589,10 @@ int fp64_path(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t woff, const 
     RETCK(read_status(ctx, L, work, st, nrm));
     if (st[ST_TIMEOUT]) return MIXLU_ERR_DEVICE_TIMEOUT;
     *info = breakdown_of(L, st) == INT_MAX ? 0 : breakdown_of(L, st);
-    if (anorm_out) *anorm_out = nrm[0];
     if (*info) return MIXLU_OK;
-    RETCK(lu_solve<double>(s, work, L, woff, nrhs, B, ldb, 0, X, ldx, 0, 1));
-    if (refine) RETCK(refine_loop<double>(ctx, work, L, woff, A, lda, B, ldb, X, ldx, 0, nrhs,
-                                          nrm[0], o, *res));
+    RETCK(lu_solve<double>(s, work, L, woff, nrhs, B, ldb, cm, X, ldx, cm, 1, trans));
+    if (refine) RETCK(refine_loop<double>(ctx, work, L, woff, A, lda, B, ldb, X, ldx, cm, nrhs,
+                                          trans ? nrm[1] : nrm[0], o, *res, trans));
     return MIXLU_OK;
 }
 
@@ -613,11 +632,26 @@ int factor_entry(mixlu_ctx_s *ctx, int op, int prec, int n, const double *A, int
     if (!F) return -9;
     if (!info) return -10;
     const mixlu_opts op_ = opts_or_default(o);
-    if (op_.layout != MIXLU_ROW_MAJOR) return MIXLU_ERR_NOT_IMPLEMENTED;
+    if (op_.layout != MIXLU_ROW_MAJOR && op_.layout != MIXLU_COL_MAJOR) return -8;
     Layout L{};
     plan_layout(L, op, prec, n, 1, op_);
     if (lwork < L.total) return MIXLU_ERR_WORKSPACE;
     if (L.npad > kPanelMaxWG * kPanelRowsPerWG) return MIXLU_ERR_NOT_IMPLEMENTED;
+    {
+        // the factor serves as many right-hand sides as the workspace holds
+        int lo = 1, hi = 2;
+        Layout T{};
+        while (hi <= (1 << 16) && plan_layout(T, op, prec, n, hi, op_) <= lwork) {
+            lo = hi;
+            hi *= 2;
+        }
+        while (hi - lo > 1) {
+            const int mid = lo + (hi - lo) / 2;
+            if (plan_layout(T, op, prec, n, mid, op_) <= lwork) lo = mid;
+            else hi = mid;
+        }
+        plan_layout(L, op, prec, n, lo, op_);
+    }
     if (n == 0) {
         fill_factor(F, L, work, lwork, op_.layout);
         *info = 0;
@@ -631,11 +665,12 @@ int dx_entry(mixlu_ctx_s *ctx, int op, int prec, int n, int nrhs, const double *
              const double *B, int ldb, double *X, int ldx, void *work, size_t lwork,
              const mixlu_opts *o, mixlu_report *rep) {
     if (!prec_valid(prec)) return -2;
-    RETCK(check_common(ctx, 3, n, nrhs, lda, ldb, ldx, A, B, X));
+    const mixlu_opts op_ = opts_or_default(o);
+    if (op_.layout != MIXLU_ROW_MAJOR && op_.layout != MIXLU_COL_MAJOR) return -13;
+    const int cm = op_.layout == MIXLU_COL_MAJOR;
+    RETCK(check_common(ctx, 3, n, nrhs, lda, ldb, ldx, A, B, X, cm));
     if (!work) return -11;
     if (!rep) return -14;
-    const mixlu_opts op_ = opts_or_default(o);
-    if (op_.layout != MIXLU_ROW_MAJOR) return MIXLU_ERR_NOT_IMPLEMENTED;
     std::memset(rep, 0, sizeof(*rep));
     Layout L{};
     plan_layout(L, op, prec, n, nrhs, op_);
@@ -656,12 +691,13 @@ int dx_entry(mixlu_ctx_s *ctx, int op, int prec, int n, int nrhs, const double *
         return MIXLU_OK;
     }
     if (F.lowp_status == 0) {
+        const int tr = eff_trans(L, 0, cm);
         if (prec == MIXLU_FP64)
-            RETCK(lu_solve<double>(ctx->stream, work, L, L.W, nrhs, B, ldb, 0, X, ldx, 0, 1));
+            RETCK(lu_solve<double>(ctx->stream, work, L, L.W, nrhs, B, ldb, cm, X, ldx, cm, 1, tr));
         else
-            RETCK(lu_solve<float>(ctx->stream, work, L, L.W, nrhs, B, ldb, 0, X, ldx, 0, 1));
+            RETCK(lu_solve<float>(ctx->stream, work, L, L.W, nrhs, B, ldb, cm, X, ldx, cm, 1, tr));
     }
-    return mixlu_refine(ctx, &F, 0, A, lda, B, ldb, X, ldx, &op_, rep);
+    return mixlu_refine(ctx, &F, 0, nrhs, A, lda, B, ldb, X, ldx, &op_, rep);
 }
 
 // FP64 factorization and solve without refinement (op DGESV or DPOSV).
@@ -679,8 +715,8 @@ int d_entry(mixlu_ctx_s *ctx, int op, int n, int nrhs, const double *A, int lda,
     if (n == 0 || nrhs == 0) return MIXLU_OK;
     if (L.npad > kPanelMaxWG * kPanelRowsPerWG) return MIXLU_ERR_NOT_IMPLEMENTED;
     LoopResult res{};
-    return fp64_path(ctx, work, L, L.W, A, lda, B, ldb, X, ldx, nrhs, op_, false, info, &res,
-                     nullptr);
+    return fp64_path(ctx, work, L, L.W, A, lda, B, ldb, X, ldx, nrhs, op_, false, info, &res, 0,
+                     0);
 }
 
 }  // namespace
@@ -780,57 +816,62 @@ int mixlu_getrs(mixlu_ctx_t ctx, const mixlu_factor *F, int trans, const int nrh
     ProfCall pc_(ctx);
     if (!F || !F->work) return -2;
     if (trans != 0 && trans != 1) return -3;
+    const int cm = F->layout == MIXLU_COL_MAJOR;
+    const int ldmin = cm ? (F->n > 1 ? F->n : 1) : (nrhs > 1 ? nrhs : 1);
     if (nrhs < 0 || nrhs > F->nrhs_max) return -4;
     if (nrhs > 0 && F->n > 0 && !B) return -5;
-    if (ldb < (nrhs > 1 ? nrhs : 1)) return -6;
+    if (ldb < ldmin) return -6;
     if (nrhs > 0 && F->n > 0 && !X) return -7;
-    if (ldx < (nrhs > 1 ? nrhs : 1)) return -8;
-    if (trans) return MIXLU_ERR_NOT_IMPLEMENTED;
+    if (ldx < ldmin) return -8;
     if (F->n == 0 || nrhs == 0) return MIXLU_OK;
     const Layout L = layout_of(F);
+    const int tr = eff_trans(L, trans, cm);
     if (F->prec == MIXLU_FP64)
-        return lu_solve<double>(ctx->stream, F->work, L, L.W, nrhs, B, ldb, 0, X, ldx, 0, 1);
-    return lu_solve<float>(ctx->stream, F->work, L, L.W, nrhs, B, ldb, 0, X, ldx, 0, 1);
+        return lu_solve<double>(ctx->stream, F->work, L, L.W, nrhs, B, ldb, cm, X, ldx, cm, 1, tr);
+    return lu_solve<float>(ctx->stream, F->work, L, L.W, nrhs, B, ldb, cm, X, ldx, cm, 1, tr);
 }
 
-int mixlu_refine(mixlu_ctx_t ctx, mixlu_factor *F, int trans, const double *A, int lda,
-                 const double *B, int ldb, double *X, int ldx, const mixlu_opts *o,
+int mixlu_refine(mixlu_ctx_t ctx, mixlu_factor *F, int trans, int nrhs, const double *A,
+                 int lda, const double *B, int ldb, double *X, int ldx, const mixlu_opts *o,
                  mixlu_report *rep) {
     if (!ctx) return -1;
     ProfCall pc_(ctx);
     if (!F || !F->work) return -2;
     if (trans != 0 && trans != 1) return -3;
-    if (F->n > 0 && !A) return -4;
-    if (lda < (F->n > 1 ? F->n : 1)) return -5;
-    if (!rep) return -11;
-    if (trans) return MIXLU_ERR_NOT_IMPLEMENTED;
+    if (nrhs < 0 || nrhs > F->nrhs_max) return -4;
+    if (F->n > 0 && !A) return -5;
+    if (lda < (F->n > 1 ? F->n : 1)) return -6;
+    if (!rep) return -12;
     const mixlu_opts op_ = opts_or_default(o);
-    const int nrhs = F->nrhs_max;
-    if (!B && F->n > 0) return -6;
-    if (ldb < (nrhs > 1 ? nrhs : 1)) return -7;
-    if (!X && F->n > 0) return -8;
-    if (ldx < (nrhs > 1 ? nrhs : 1)) return -9;
+    const int cm = F->layout == MIXLU_COL_MAJOR;
+    const int ldmin = cm ? (F->n > 1 ? F->n : 1) : (nrhs > 1 ? nrhs : 1);
+    if (!B && F->n > 0 && nrhs > 0) return -7;
+    if (ldb < ldmin) return -8;
+    if (!X && F->n > 0 && nrhs > 0) return -9;
+    if (ldx < ldmin) return -10;
     std::memset(rep, 0, sizeof(*rep));
     rep->prec = F->prec;
-    if (F->n == 0) {
+    if (F->n == 0 || nrhs == 0) {
         rep->converged = 1;
         return MIXLU_OK;
     }
     const Layout L = layout_of(F);
+    const int tr = eff_trans(L, trans, cm);
     int st[ST_COUNT];
     double nrm[2];
     RETCK(read_status(ctx, L, F->work, st, nrm));
-    const double anorm = nrm[0];
+    // ||M^T||_inf = ||M||_1 when the solve is with the transposed matrix
+    const double anorm = tr ? nrm[1] : nrm[0];
     rep->anorm = anorm;
     LoopResult res{};
     int reason = F->lowp_status;
     if (reason == 0) {
         if (F->prec == MIXLU_FP64)
-            RETCK(refine_loop<double>(ctx, F->work, L, L.W, A, lda, B, ldb, X, ldx, 0, nrhs,
-                                      anorm, op_, res));
+            RETCK(refine_loop<double>(ctx, F->work, L, L.W, A, lda, B, ldb, X, ldx, cm, nrhs,
+                                      anorm, op_, res, tr));
         else
-            RETCK(refine_loop<float>(ctx, F->work, L, L.W, A, lda, B, ldb, X, ldx, 0, nrhs,
-                                     anorm, op_, res));
+            RETCK(refine_loop<float>(ctx, F->work, L, L.W, A, lda, B, ldb, X, ldx, cm, nrhs,
+                                     anorm, op_, res, tr));
         reason = res.converged ? 0 : res.iters;
     }
     if (reason == 0) {
@@ -851,7 +892,7 @@ int mixlu_refine(mixlu_ctx_t ctx, mixlu_factor *F, int trans, const double *A, i
     int info = 0;
     LoopResult fres{};
     RETCK(fp64_path(ctx, F->work, L, L.W64, A, lda, B, ldb, X, ldx, nrhs, op_, true, &info, &fres,
-                    nullptr));
+                    tr, cm));
     rep->info = info;
     rep->prec = MIXLU_FP64;
     rep->fallback_iter = fres.iters;

@@ -183,14 +183,19 @@ template <typename Tw>
 hipError_t launch_rhs_gather(int n, int npad, int nrhs, const double *B, int ldb, int b_col_major,
                              const int *perm, const double *R, Tw *Y, int ldy, hipStream_t s);
 template <typename Tw>
-hipError_t launch_trsv(int upper, const Tw *W, int ldw, int npad, Tw *Y, int ldy, int nrhs,
-                       unsigned long long *ybuf, int *status, hipStream_t s);
+hipError_t launch_trsv(int upper, int trans, const Tw *W, int ldw, int npad, Tw *Y, int ldy,
+                       int nrhs, unsigned long long *ybuf, int *status, hipStream_t s);
 template <typename Tw>
-hipError_t launch_x_update(int n, int nrhs, int assign, const Tw *Y, int ldy, const double *C,
-                           double *X, int ldx, int x_col_major, double *xnorm, hipStream_t s);
+hipError_t launch_x_update(int n, int npad, int nrhs, int assign, const Tw *Y, int ldy,
+                           const int *perm, const double *C, double *X, int ldx, int x_col_major,
+                           double *xnorm, hipStream_t s);
 hipError_t launch_residual(int n, int nrhs, const double *A, int lda, const double *X, int ldx,
                            const double *B, int ldb, int bx_col_major, double *Rv, int ldr,
-                           double *rnorm, hipStream_t s);
+                           double *rnorm, double *xnorm, hipStream_t s);
+// part: scratch of 16 * n * 8 doubles
+hipError_t launch_residual_t(int n, int nrhs, const double *A, int lda, const double *X, int ldx,
+                             const double *B, int ldb, int bx_col_major, double *Rv, int ldr,
+                             double *rnorm, double *xnorm, double *part, hipStream_t s);
 hipError_t launch_fill_f64(double *p, double v, size_t count, hipStream_t s);
 hipError_t launch_iota(int *p, int count, hipStream_t s);
 hipError_t launch_outer(int n, int nrhs, const double *G, int ldg, const double *X, int ldx,

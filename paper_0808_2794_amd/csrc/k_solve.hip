@@ -30,8 +30,9 @@ __device__ inline void atomic_max_nonneg(double *p, double v) {
     atomicMax(reinterpret_cast<unsigned long long *>(p), (unsigned long long)__double_as_longlong(v));
 }
 
-// Y[i][c] = round(R[perm[i]] * B[perm[i]][c]) for rows that map into A,
-// 0 for padding rows: the permuted, row-scaled right-hand side P(R b).
+// Y[i][c] = round(S[src] * B[src][c]) with src = perm[i] (perm = NULL: the
+// identity) for rows that map into A, 0 for padding rows: the permuted,
+// scaled right-hand side P(R b) of the solve with A, or C b for A^T.
 template <typename Tw>
 __global__ __launch_bounds__(256) void k_rhs_gather(int n, int npad, int nrhs,
                                                     const double *__restrict__ B, int ldb,
@@ -40,7 +41,7 @@ __global__ __launch_bounds__(256) void k_rhs_gather(int n, int npad, int nrhs,
                                                     Tw *__restrict__ Y, int ldy) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= npad) return;
-    const int src = perm[i];
+    const int src = perm ? perm[i] : i;
     for (int c = 0; c < nrhs; ++c) {
         Tw v = (Tw)0;
         if (src < n) {
@@ -66,11 +67,14 @@ template hipError_t launch_rhs_gather<double>(int, int, int, const double *, int
                                               hipStream_t);
 
 // Chained block triangular solve, in place in Y (npad x nrhs, ldy), nrhs <=
-// NRT.  upper = 0: unit lower L (below the diagonal of W), forward.
-// upper = 1: U (on and above the diagonal), backward.  yx holds the
-// published solution words ((row * NRT + c) * PWV + word), zeroed before the
-// launch together with the ticket counter at yx[npad * NRT * PWV].
-template <typename T, int NRT>
+// NRT.  TRANS = false: upper = 0 solves with the unit lower L (below the
+// diagonal of W), forward; upper = 1 with U (on and above the diagonal),
+// backward.  TRANS = true solves with the transposed factors: upper = 0
+// with U^T (lower, non-unit), forward; upper = 1 with L^T (upper, unit),
+// backward.  yx holds the published solution words ((row * NRT + c) * PWV +
+// word), zeroed before the launch together with the ticket counter at
+// yx[npad * NRT * PWV].
+template <typename T, int NRT, bool TRANS>
 __global__ __launch_bounds__(256) void k_trsv(int upper, const T *__restrict__ W, int ldw,
                                               int nblk, T *__restrict__ Y, int ldy, int nrhs,
                                               unsigned long long *__restrict__ yx,
@@ -101,11 +105,18 @@ __global__ __launch_bounds__(256) void k_trsv(int upper, const T *__restrict__ W
     for (int c = 0; c < NRT; ++c) acc[c] = (T)0;
     // the diagonal tile is needed last but does not depend on anything:
     // request it now so its latency is off the critical path
+    // element (b*BS + r, jb*BS + q*16 + e) of the triangular matrix
+    auto tile_ptr = [&](int jb) -> const T * {
+        return TRANS ? W + (size_t)(jb * BS + q * 16) * ldw + (size_t)b * BS + r
+                     : W + (size_t)(b * BS + r) * ldw + (size_t)jb * BS + q * 16;
+    };
+    constexpr size_t ES = 1;
+    const size_t estride = TRANS ? (size_t)ldw : ES;
     T dg[16];
     {
-        const T *drow = W + (size_t)(b * BS + r) * ldw + (size_t)b * BS + q * 16;
+        const T *drow = tile_ptr(b);
 #pragma unroll
-        for (int e = 0; e < 16; ++e) dg[e] = drow[e];
+        for (int e = 0; e < 16; ++e) dg[e] = TRANS ? drow[e * estride] : drow[e];
     }
 
     const int nsteps = upper ? nblk - 1 - b : b;
@@ -119,9 +130,10 @@ __global__ __launch_bounds__(256) void k_trsv(int upper, const T *__restrict__ W
         for (int u = 0; u < JB; ++u) {
             const int st = st0 + u;
             const int j = upper ? nblk - 1 - st : st;
-            const T *lrow = W + (size_t)(b * BS + r) * ldw + (size_t)j * BS + q * 16;
+            const T *lrow = tile_ptr(j);
 #pragma unroll
-            for (int e = 0; e < 16; ++e) lv[u][e] = (u < nb_) ? lrow[e] : (T)0;
+            for (int e = 0; e < 16; ++e)
+                lv[u][e] = (u < nb_) ? (TRANS ? lrow[e * estride] : lrow[e]) : (T)0;
         }
         unsigned long long wv[WPT];
 #pragma unroll
@@ -195,13 +207,33 @@ __global__ __launch_bounds__(256) void k_trsv(int upper, const T *__restrict__ W
         T lrow[BS];
 #pragma unroll
         for (int k = 0; k < BS; ++k) lrow[k] = sL[lane][k];
-        if (!upper) {
+        if (!upper && !TRANS) {  // unit lower
 #pragma unroll
             for (int k = 0; k < BS; ++k) {
 #pragma unroll
                 for (int c = 0; c < NRT; ++c) {
                     const T yk = bcast_lane(sv[c], k);
                     if (lane > k) sv[c] -= lrow[k] * yk;
+                }
+            }
+        } else if (!upper) {  // non-unit lower (U^T)
+#pragma unroll
+            for (int k = 0; k < BS; ++k) {
+                const T dk = bcast_lane(lrow[k], k);
+#pragma unroll
+                for (int c = 0; c < NRT; ++c) {
+                    const T yk = bcast_lane(sv[c], k) / dk;
+                    if (lane == k) sv[c] = yk;
+                    else if (lane > k) sv[c] -= lrow[k] * yk;
+                }
+            }
+        } else if (TRANS) {  // unit upper (L^T)
+#pragma unroll
+            for (int k = BS - 1; k >= 0; --k) {
+#pragma unroll
+                for (int c = 0; c < NRT; ++c) {
+                    const T yk = bcast_lane(sv[c], k);
+                    if (lane < k) sv[c] -= lrow[k] * yk;
                 }
             }
         } else {
@@ -229,9 +261,9 @@ __global__ __launch_bounds__(256) void k_trsv(int upper, const T *__restrict__ W
     }
 }
 
-template <typename Tw>
-hipError_t launch_trsv(int upper, const Tw *W, int ldw, int npad, Tw *Y, int ldy, int nrhs,
-                       unsigned long long *ybuf, int *status, hipStream_t s) {
+template <typename Tw, bool TRANS>
+hipError_t launch_trsv_t(int upper, const Tw *W, int ldw, int npad, Tw *Y, int ldy, int nrhs,
+                         unsigned long long *ybuf, int *status, hipStream_t s) {
     if (npad == 0 || nrhs == 0) return hipSuccess;
     if (nrhs > kTrsvNRT || npad % kTrsvBS) return hipErrorInvalidValue;
     const int nblk = npad / kTrsvBS;
@@ -241,31 +273,43 @@ hipError_t launch_trsv(int upper, const Tw *W, int ldw, int npad, Tw *Y, int ldy
     if (e != hipSuccess) return e;
     // each instantiation lays its words (and ticket) out inside the zeroed region
     if (nrhs == 1)
-        k_trsv<Tw, 1><<<dim3(nblk), dim3(256), 0, s>>>(upper, W, ldw, nblk, Y, ldy, nrhs, ybuf,
-                                                       status);
-    else
-        k_trsv<Tw, kTrsvNRT><<<dim3(nblk), dim3(256), 0, s>>>(upper, W, ldw, nblk, Y, ldy, nrhs,
+        k_trsv<Tw, 1, TRANS><<<dim3(nblk), dim3(256), 0, s>>>(upper, W, ldw, nblk, Y, ldy, nrhs,
                                                               ybuf, status);
+    else
+        k_trsv<Tw, kTrsvNRT, TRANS><<<dim3(nblk), dim3(256), 0, s>>>(upper, W, ldw, nblk, Y, ldy,
+                                                                     nrhs, ybuf, status);
     return hipGetLastError();
 }
-template hipError_t launch_trsv<float>(int, const float *, int, int, float *, int, int,
+
+template <typename Tw>
+hipError_t launch_trsv(int upper, int trans, const Tw *W, int ldw, int npad, Tw *Y, int ldy,
+                       int nrhs, unsigned long long *ybuf, int *status, hipStream_t s) {
+    return trans ? launch_trsv_t<Tw, true>(upper, W, ldw, npad, Y, ldy, nrhs, ybuf, status, s)
+                 : launch_trsv_t<Tw, false>(upper, W, ldw, npad, Y, ldy, nrhs, ybuf, status, s);
+}
+template hipError_t launch_trsv<float>(int, int, const float *, int, int, float *, int, int,
                                        unsigned long long *, int *, hipStream_t);
-template hipError_t launch_trsv<double>(int, const double *, int, int, double *, int, int,
+template hipError_t launch_trsv<double>(int, int, const double *, int, int, double *, int, int,
                                         unsigned long long *, int *, hipStream_t);
 
-// X = C z (assign) or X += C z, z promoted to FP64; xnorm[c] = max |X[:, c]|.
+// Row i of the solve vector z goes to row d = perm[i] of X (perm = NULL: the
+// identity; the transposed solve scatters through P^T): X[d] = S[d] z[i]
+// (assign) or X[d] += S[d] z[i], z promoted to FP64, for d < n;
+// xnorm[c] = max |X[:, c]| over the rows written.
 template <typename Tw>
-__global__ __launch_bounds__(256) void k_x_update(int n, int nrhs, int assign,
+__global__ __launch_bounds__(256) void k_x_update(int n, int npad, int nrhs, int assign,
                                                   const Tw *__restrict__ Y, int ldy,
+                                                  const int *__restrict__ perm,
                                                   const double *__restrict__ C,
                                                   double *__restrict__ X, int ldx, int x_col_major,
                                                   double *__restrict__ xnorm) {
     const int i = blockIdx.x * 256 + threadIdx.x;
+    const int d = i < npad ? (perm ? perm[i] : i) : n;
     for (int c = 0; c < nrhs; ++c) {
         double v = 0.0;
-        if (i < n) {
-            double *px = x_col_major ? X + i + (size_t)c * ldx : X + (size_t)i * ldx + c;
-            v = C[i] * (double)Y[(size_t)i * ldy + c];
+        if (d < n) {
+            double *px = x_col_major ? X + d + (size_t)c * ldx : X + (size_t)d * ldx + c;
+            v = C[d] * (double)Y[(size_t)i * ldy + c];
             if (!assign) v += *px;
             *px = v;
         }
@@ -279,31 +323,44 @@ __global__ __launch_bounds__(256) void k_x_update(int n, int nrhs, int assign,
 }
 
 template <typename Tw>
-hipError_t launch_x_update(int n, int nrhs, int assign, const Tw *Y, int ldy, const double *C,
-                           double *X, int ldx, int x_col_major, double *xnorm, hipStream_t s) {
+hipError_t launch_x_update(int n, int npad, int nrhs, int assign, const Tw *Y, int ldy,
+                           const int *perm, const double *C, double *X, int ldx, int x_col_major,
+                           double *xnorm, hipStream_t s) {
     if (n == 0 || nrhs == 0) return hipSuccess;
-    k_x_update<Tw><<<dim3((n + 255) / 256), dim3(256), 0, s>>>(n, nrhs, assign, Y, ldy, C, X, ldx,
-                                                              x_col_major, xnorm);
+    const int rows = perm ? npad : n;
+    k_x_update<Tw><<<dim3((rows + 255) / 256), dim3(256), 0, s>>>(n, rows, nrhs, assign, Y, ldy,
+                                                                 perm, C, X, ldx, x_col_major,
+                                                                 xnorm);
     return hipGetLastError();
 }
-template hipError_t launch_x_update<float>(int, int, int, const float *, int, const double *,
-                                           double *, int, int, double *, hipStream_t);
-template hipError_t launch_x_update<double>(int, int, int, const double *, int, const double *,
-                                            double *, int, int, double *, hipStream_t);
+template hipError_t launch_x_update<float>(int, int, int, int, const float *, int, const int *,
+                                           const double *, double *, int, int, double *,
+                                           hipStream_t);
+template hipError_t launch_x_update<double>(int, int, int, int, const double *, int, const int *,
+                                            const double *, double *, int, int, double *,
+                                            hipStream_t);
 
 // r = b - A x in FP64 (A row-major n x n), 16 rows per workgroup (4 per
-// wave), up to NR right-hand sides; rnorm[c] = max_i |r_ic|.  VEC: rows are
-// read as 16-byte pairs (needs even n and lda and 16-byte aligned A), two
-// pairs in flight per lane and row.
+// wave), up to NR right-hand sides; rnorm[c] = max_i |r_ic| and, from the
+// first wave (which reads all of x), xnorm[c] = max_j |x_jc|: the stopping
+// test then uses the norms of exactly the x this residual belongs to.
+// VEC: rows are read as 16-byte pairs (needs even n and lda and 16-byte
+// aligned A), two pairs in flight per lane and row.
+__device__ inline double nanmax(double m, double a) { return (a > m || a != a) ? a : m; }
+
 template <int NR, bool VEC>
 __global__ __launch_bounds__(256) void k_residual(int n, int nrhs, const double *__restrict__ A,
                                                   int lda, const double *__restrict__ X, int ldx,
                                                   const double *__restrict__ B, int ldb, int bx_cm,
                                                   double *__restrict__ Rv, int ldr,
-                                                  double *__restrict__ rnorm) {
+                                                  double *__restrict__ rnorm,
+                                                  double *__restrict__ xnorm) {
     constexpr int RPW = 4;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r0 = (blockIdx.x * 4 + wave) * RPW;
+    double xm[NR];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) xm[c] = 0.0;
     double acc[RPW][NR];
 #pragma unroll
     for (int rr = 0; rr < RPW; ++rr)
@@ -323,6 +380,7 @@ __global__ __launch_bounds__(256) void k_residual(int n, int nrhs, const double 
                     for (int c = 0; c < NR; ++c) {
                         x0[c] = xat(j, c);
                         x1[c] = xat(j + 1, c);
+                        xm[c] = nanmax(nanmax(xm[c], fabs(x0[c])), fabs(x1[c]));
                     }
 #pragma unroll
                     for (int rr = 0; rr < RPW; ++rr) {
@@ -340,7 +398,10 @@ __global__ __launch_bounds__(256) void k_residual(int n, int nrhs, const double 
         for (int j = lane; j < n; j += 64) {
             double xv[NR];
 #pragma unroll
-            for (int c = 0; c < NR; ++c) xv[c] = xat(j, c);
+            for (int c = 0; c < NR; ++c) {
+                xv[c] = xat(j, c);
+                xm[c] = nanmax(xm[c], fabs(xv[c]));
+            }
 #pragma unroll
             for (int rr = 0; rr < RPW; ++rr) {
                 const int row = r0 + rr;
@@ -381,11 +442,19 @@ __global__ __launch_bounds__(256) void k_residual(int n, int nrhs, const double 
         for (int c = 0; c < NR; ++c)
             if (c < nrhs) atomic_max_nonneg(&rnorm[c], rmax[c]);
     }
+    if (blockIdx.x == 0 && wave == 0) {
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+            double v = xm[c];
+            for (int off = 32; off > 0; off >>= 1) v = nanmax(v, __shfl_xor(v, off));
+            if (lane == 0 && c < nrhs) xnorm[c] = v;
+        }
+    }
 }
 
 hipError_t launch_residual(int n, int nrhs, const double *A, int lda, const double *X, int ldx,
                            const double *B, int ldb, int bx_col_major, double *Rv, int ldr,
-                           double *rnorm, hipStream_t s) {
+                           double *rnorm, double *xnorm, hipStream_t s) {
     if (n == 0 || nrhs == 0) return hipSuccess;
     const dim3 grid((n + 15) / 16);
     const bool vec = (n % 2 == 0) && (lda % 2 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
@@ -396,18 +465,114 @@ hipError_t launch_residual(int n, int nrhs, const double *A, int lda, const doub
         if (nr == 1) {
             if (vec)
                 k_residual<1, true><<<grid, dim3(256), 0, s>>>(n, 1, A, lda, Xc, ldx, Bc, ldb,
-                                                               bx_col_major, Rv + c0, ldr, rnorm + c0);
+                                                               bx_col_major, Rv + c0, ldr, rnorm + c0, xnorm + c0);
             else
                 k_residual<1, false><<<grid, dim3(256), 0, s>>>(n, 1, A, lda, Xc, ldx, Bc, ldb,
-                                                                bx_col_major, Rv + c0, ldr, rnorm + c0);
+                                                                bx_col_major, Rv + c0, ldr, rnorm + c0, xnorm + c0);
         } else {
             if (vec)
                 k_residual<8, true><<<grid, dim3(256), 0, s>>>(n, nr, A, lda, Xc, ldx, Bc, ldb,
-                                                               bx_col_major, Rv + c0, ldr, rnorm + c0);
+                                                               bx_col_major, Rv + c0, ldr, rnorm + c0, xnorm + c0);
             else
                 k_residual<8, false><<<grid, dim3(256), 0, s>>>(n, nr, A, lda, Xc, ldx, Bc, ldb,
-                                                                bx_col_major, Rv + c0, ldr, rnorm + c0);
+                                                                bx_col_major, Rv + c0, ldr, rnorm + c0, xnorm + c0);
         }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// r = b - A^T x in FP64 for row-major A: column sums in two passes.  Pass 1:
+// workgroup (column group g of 256 columns, row chunk h) accumulates
+// part[h][j][c] = sum over its rows i of A[i][j] x[i][c] for up to 8
+// right-hand sides (one column per thread: coalesced row segments); the
+// workgroups of column group 0 also fold max |x| into xnorm (zeroed by the
+// caller).  Pass 2: r[j][c] = b[j][c] - sum_h part[h][j][c] and
+// rnorm[c] = max_j |r[j][c]| (zeroed by the caller).
+constexpr int kResTChunks = 16;
+__global__ __launch_bounds__(256) void k_residual_t_part(int n, int nrhs, int rows_per_chunk,
+                                                         const double *__restrict__ A, int lda,
+                                                         const double *__restrict__ X, int ldx,
+                                                         int x_cm, double *__restrict__ part,
+                                                         double *__restrict__ xnorm) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    const int h = blockIdx.y;
+    const int i0 = h * rows_per_chunk;
+    const int i1 = min(n, i0 + rows_per_chunk);
+    __shared__ double sx[64][8];
+    double acc[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+    // thread t always stages right-hand side c = t & 7 (256 is a multiple of 8)
+    double xm = 0.0;
+    for (int ib = i0; ib < i1; ib += 64) {
+        const int cnt = min(64, i1 - ib);
+        __syncthreads();
+        for (int t = threadIdx.x; t < 64 * 8; t += 256) {
+            const int ii = t >> 3, c = t & 7;
+            double v = 0.0;
+            if (ii < cnt && c < nrhs)
+                v = x_cm ? X[(size_t)(ib + ii) + (size_t)c * ldx] : X[(size_t)(ib + ii) * ldx + c];
+            sx[ii][c] = v;
+            xm = nanmax(xm, fabs(v));
+        }
+        __syncthreads();
+        if (j < n) {
+            for (int ii = 0; ii < cnt; ++ii) {
+                const double a = A[(size_t)(ib + ii) * lda + j];
+#pragma unroll
+                for (int c = 0; c < 8; ++c) acc[c] += a * sx[ii][c];
+            }
+        }
+    }
+    if (j < n) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+            if (c < nrhs) part[((size_t)h * n + j) * 8 + c] = acc[c];
+    }
+    if (blockIdx.x == 0 && (threadIdx.x & 7) < nrhs) atomic_max_nonneg(&xnorm[threadIdx.x & 7], xm);
+}
+
+__global__ __launch_bounds__(256) void k_residual_t_fin(int n, int nrhs, int chunks,
+                                                        const double *__restrict__ part,
+                                                        const double *__restrict__ B, int ldb,
+                                                        int b_cm, double *__restrict__ Rv, int ldr,
+                                                        double *__restrict__ rnorm) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    for (int c = 0; c < nrhs; ++c) {
+        double ar = 0.0;
+        if (j < n) {
+            double s = 0.0;
+            for (int h = 0; h < chunks; ++h) s += part[((size_t)h * n + j) * 8 + c];
+            const double b = b_cm ? B[j + (size_t)c * ldb] : B[(size_t)j * ldb + c];
+            const double r = b - s;
+            Rv[(size_t)j * ldr + c] = r;
+            ar = fabs(r);
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const double o = __shfl_xor(ar, off);
+            ar = (o > ar || o != o) ? o : ar;
+        }
+        if ((threadIdx.x & 63) == 0) atomic_max_nonneg(&rnorm[c], ar);
+    }
+}
+
+hipError_t launch_residual_t(int n, int nrhs, const double *A, int lda, const double *X, int ldx,
+                             const double *B, int ldb, int bx_col_major, double *Rv, int ldr,
+                             double *rnorm, double *xnorm, double *part, hipStream_t s) {
+    if (n == 0 || nrhs == 0) return hipSuccess;
+    const int chunks = n < kResTChunks * 64 ? (n + 63) / 64 : kResTChunks;
+    const int rpc = (n + chunks - 1) / chunks;
+    const dim3 grid((n + 255) / 256, chunks);
+    for (int c0 = 0; c0 < nrhs; c0 += 8) {
+        const int nr = nrhs - c0 < 8 ? nrhs - c0 : 8;
+        const double *Xc = bx_col_major ? X + (size_t)c0 * ldx : X + c0;
+        const double *Bc = bx_col_major ? B + (size_t)c0 * ldb : B + c0;
+        k_residual_t_part<<<grid, dim3(256), 0, s>>>(n, nr, rpc, A, lda, Xc, ldx, bx_col_major,
+                                                     part, xnorm + c0);
+        k_residual_t_fin<<<dim3((n + 255) / 256), dim3(256), 0, s>>>(
+            n, nr, chunks, part, Bc, ldb, bx_col_major, Rv + c0, ldr, rnorm + c0);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

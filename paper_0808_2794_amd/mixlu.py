@@ -85,7 +85,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "mixlu_getrf": ([P, I, I, P, I, P, S, P, P, P], I),
         "mixlu_potrf": ([P, I, I, P, I, P, S, P, P, P], I),
         "mixlu_getrs": ([P, P, I, I, P, I, P, I], I),
-        "mixlu_refine": ([P, P, I, P, I, P, I, P, I, P, P], I),
+        "mixlu_refine": ([P, P, I, I, P, I, P, I, P, I, P, P], I),
         "mixlu_dxgesv": ([P, I, I, I, P, I, P, I, P, I, P, S, P, P], I),
         "mixlu_dxposv": ([P, I, I, I, P, I, P, I, P, I, P, S, P, P], I),
         "mixlu_dgesv": ([P, I, I, P, I, P, I, P, I, P, S, P], I),
@@ -156,18 +156,37 @@ def mixlu_workspace_size(ctx, op: int, prec: int, n: int, nrhs: int, opts=None) 
     return b.value
 
 
-def _ld(t, n=None):
-    """Leading dimension of a row-major 2-D tensor (unit column stride)."""
-    if t.dim() != 2 or (t.shape[1] > 1 and t.stride(1) != 1):
+def _is_cm(t) -> bool:
+    """True when a 2-D tensor with several rows and columns is stored
+    column-major (unit row stride)."""
+    return t.dim() == 2 and t.shape[0] > 1 and t.shape[1] > 1 and t.stride(0) == 1
+
+
+def _ld(t, cm: bool = False):
+    """Leading dimension of a 2-D tensor stored row-major (cm False) or
+    column-major (cm True); raises if the storage is neither."""
+    if t.dim() != 2:
+        raise ValueError("expected a 2-D tensor")
+    r, c = t.shape
+    if cm:
+        if r > 1 and t.stride(0) != 1:
+            raise ValueError("expected a column-major 2-D tensor")
+        return max(1, r, t.stride(1) if c > 1 else r)
+    if c > 1 and t.stride(1) != 1:
         raise ValueError("expected a row-major 2-D tensor")
-    return max(1, t.stride(0), t.shape[1])
+    return max(1, c, t.stride(0) if r > 1 else c)
+
+
+def _cm(opts) -> bool:
+    return opts is not None and opts.layout == COL_MAJOR
 
 
 def mixlu_dxgesv(ctx, prec: int, A, B, X, work, opts=None) -> mixlu_report:
     rep = mixlu_report()
     n, nrhs = B.shape
-    check(load().mixlu_dxgesv(ctx, prec, n, nrhs, _p(A), _ld(A, n), _p(B), _ld(B, n), _p(X),
-                              _ld(X, n), _p(work), work.numel() * work.element_size(),
+    cm = _cm(opts)
+    check(load().mixlu_dxgesv(ctx, prec, n, nrhs, _p(A), _ld(A, cm), _p(B), _ld(B, cm), _p(X),
+                              _ld(X, cm), _p(work), work.numel() * work.element_size(),
                               None if opts is None else ctypes.byref(opts), ctypes.byref(rep)),
           "mixlu_dxgesv")
     return rep
@@ -176,8 +195,9 @@ def mixlu_dxgesv(ctx, prec: int, A, B, X, work, opts=None) -> mixlu_report:
 def mixlu_dxposv(ctx, prec: int, A, B, X, work, opts=None) -> mixlu_report:
     rep = mixlu_report()
     n, nrhs = B.shape
-    check(load().mixlu_dxposv(ctx, prec, n, nrhs, _p(A), _ld(A, n), _p(B), _ld(B, n), _p(X),
-                              _ld(X, n), _p(work), work.numel() * work.element_size(),
+    cm = _cm(opts)
+    check(load().mixlu_dxposv(ctx, prec, n, nrhs, _p(A), _ld(A, cm), _p(B), _ld(B, cm), _p(X),
+                              _ld(X, cm), _p(work), work.numel() * work.element_size(),
                               None if opts is None else ctypes.byref(opts), ctypes.byref(rep)),
           "mixlu_dxposv")
     return rep
@@ -186,8 +206,8 @@ def mixlu_dxposv(ctx, prec: int, A, B, X, work, opts=None) -> mixlu_report:
 def _d_solve(name, ctx, A, B, X, work) -> int:
     info = ctypes.c_int()
     n, nrhs = B.shape
-    check(getattr(load(), name)(ctx, n, nrhs, _p(A), _ld(A, n), _p(B), _ld(B, n), _p(X),
-                                _ld(X, n), _p(work), work.numel() * work.element_size(),
+    check(getattr(load(), name)(ctx, n, nrhs, _p(A), _ld(A), _p(B), _ld(B), _p(X),
+                                _ld(X), _p(work), work.numel() * work.element_size(),
                                 ctypes.byref(info)), name)
     return info.value
 
@@ -204,7 +224,7 @@ def _factor(name, ctx, prec: int, A, work, opts=None):
     F = mixlu_factor()
     info = ctypes.c_int()
     n = A.shape[0]
-    check(getattr(load(), name)(ctx, prec, n, _p(A), _ld(A, n), _p(work),
+    check(getattr(load(), name)(ctx, prec, n, _p(A), _ld(A, _cm(opts)), _p(work),
                                 work.numel() * work.element_size(),
                                 None if opts is None else ctypes.byref(opts), ctypes.byref(F),
                                 ctypes.byref(info)), name)
@@ -221,23 +241,26 @@ def mixlu_potrf(ctx, prec: int, A, work, opts=None):
 
 def mixlu_getrs(ctx, F: mixlu_factor, B, X, trans: int = 0) -> None:
     n, nrhs = B.shape
-    check(load().mixlu_getrs(ctx, ctypes.byref(F), trans, nrhs, _p(B), _ld(B, n), _p(X),
-                             _ld(X, n)), "mixlu_getrs")
+    cm = F.layout == COL_MAJOR
+    check(load().mixlu_getrs(ctx, ctypes.byref(F), trans, nrhs, _p(B), _ld(B, cm), _p(X),
+                             _ld(X, cm)), "mixlu_getrs")
 
 
 def mixlu_refine(ctx, F: mixlu_factor, A, B, X, opts=None, trans: int = 0) -> mixlu_report:
     rep = mixlu_report()
-    n = A.shape[0]
-    check(load().mixlu_refine(ctx, ctypes.byref(F), trans, _p(A), _ld(A, n), _p(B), _ld(B, n),
-                              _p(X), _ld(X, n), None if opts is None else ctypes.byref(opts),
+    cm = F.layout == COL_MAJOR
+    nrhs = B.shape[1]
+    check(load().mixlu_refine(ctx, ctypes.byref(F), trans, nrhs, _p(A), _ld(A, cm), _p(B),
+                              _ld(B, cm),
+                              _p(X), _ld(X, cm), None if opts is None else ctypes.byref(opts),
                               ctypes.byref(rep)), "mixlu_refine")
     return rep
 
 
 def mixlu_outer_update(ctx, G, X, GA, alpha: float = -1.0, beta: float = 0.0) -> None:
     n, nrhs = G.shape
-    check(load().mixlu_outer_update(ctx, n, nrhs, _p(G), _ld(G, n), _p(X), _ld(X, n), _p(GA),
-                                    _ld(GA, n), alpha, beta), "mixlu_outer_update")
+    check(load().mixlu_outer_update(ctx, n, nrhs, _p(G), _ld(G), _p(X), _ld(X), _p(GA),
+                                    _ld(GA), alpha, beta), "mixlu_outer_update")
 
 
 def mixlu_profile_enable(ctx, on: bool = True) -> None:
@@ -291,42 +314,46 @@ class Solver:
 
     @staticmethod
     def _prep(A, B):
+        """Keep A's storage order (row-major, or column-major as LAPACK) and
+        bring B into the same one; X is allocated in it too."""
         import torch
 
         if A.dtype != torch.float64 or B.dtype != torch.float64:
             raise TypeError("A and B must be float64")
         vec = B.dim() == 1
         B2 = B.reshape(-1, 1) if vec else B
-        return A.contiguous(), B2.contiguous(), vec
+        if _is_cm(A):
+            if not (_is_cm(B2) or B2.shape[1] == 1):
+                B2 = B2.t().contiguous().t()
+            X = torch.empty(B2.shape[1], B2.shape[0], dtype=B2.dtype, device=B2.device).t()
+            return A, B2, X, vec, COL_MAJOR
+        A = A.contiguous()
+        B2 = B2.contiguous()
+        return A, B2, torch.empty_like(B2), vec, ROW_MAJOR
 
     def dxgesv(self, A, B, prec="fp32", opts=None, **kw) -> Result:
-        import torch
-
         p = PREC[prec] if isinstance(prec, str) else prec
+        A, B2, X, vec, layout = self._prep(A, B)
         o = opts if opts is not None else default_opts(**kw)
-        A, B2, vec = self._prep(A, B)
-        X = torch.empty_like(B2)
+        o.layout = layout
         work = self.workspace(OP_GESV, p, A.shape[0], B2.shape[1], o)
         rep = mixlu_dxgesv(self.ctx, p, A, B2, X, work, o)
         return Result(X.reshape(-1) if vec else X, rep.as_dict())
 
     def dxposv(self, A, B, prec="fp32", opts=None, **kw) -> Result:
         """Symmetric positive definite A: Cholesky in prec + FP64 refinement."""
-        import torch
-
         p = PREC[prec] if isinstance(prec, str) else prec
+        A, B2, X, vec, layout = self._prep(A, B)
         o = opts if opts is not None else default_opts(**kw)
-        A, B2, vec = self._prep(A, B)
-        X = torch.empty_like(B2)
+        o.layout = layout
         work = self.workspace(OP_POSV, p, A.shape[0], B2.shape[1], o)
         rep = mixlu_dxposv(self.ctx, p, A, B2, X, work, o)
         return Result(X.reshape(-1) if vec else X, rep.as_dict())
 
     def _d(self, op, fn, A, B) -> Result:
-        import torch
-
-        A, B2, vec = self._prep(A, B)
-        X = torch.empty_like(B2)
+        A, B2, X, vec, layout = self._prep(A, B)
+        if layout != ROW_MAJOR:
+            raise ValueError("the FP64 comparators take row-major A")
         work = self.workspace(op, FP64, A.shape[0], B2.shape[1])
         info = fn(self.ctx, A, B2, X, work)
         return Result(X.reshape(-1) if vec else X, {"info": info})

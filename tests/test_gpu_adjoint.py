@@ -1,0 +1,209 @@
+"""GPU parity of the transposed solves, the column-major layout and the
+differentiable solve (adjoint G_B = A^{-T} G_X, G_A = -G_B X^T) against the
+CPU oracle, through the C ABI.
+
+Bar: the stopping rule for A^T x = b with the residual recomputed on the CPU
+in extended precision, forward error <= 1e-12 kappa against the oracle's
+FP64 transposed refinement; gradients within 1e-12 kappa of the oracle's
+reference gradient and within 1e-6 of central finite differences.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from synth import gen
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def solver():
+    import torch
+
+    from paper_0808_2794_amd import mixlu
+
+    torch.cuda.init()
+    s = mixlu.Solver()
+    yield s
+    s.close()
+
+
+def _dev(a):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _check(A, b, x, kappa, x_ref):
+    m = O.metrics(A, x, b, x_ref=x_ref)
+    assert m["passes"], f"stopping rule fails: rnorm={m['rnorm']} anorm={m['anorm']} xnorm={m['xnorm']}"
+    assert float(np.max(m["fwd_ref"])) <= 1e-12 * kappa, m["fwd_ref"]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64", "fp16"])
+@pytest.mark.parametrize("n,nrhs", [(1, 1), (17, 2), (200, 1), (513, 5), (1100, 1)])
+def test_transposed_solve_and_refine(solver, n, nrhs, prec):
+    """getrf, then getrs and refine with trans = 1: A^T X = B with the same
+    factors (equilibrated for FP16)."""
+    import torch
+
+    from paper_0808_2794_amd import mixlu
+
+    kappa = 1e3
+    A, _, _ = gen.prescribed_cond_system(n, kappa, 4000 + n)
+    B = np.random.default_rng(n).uniform(-1, 1, (n, nrhs))
+    _say(f"trans solve n={n} nrhs={nrhs} prec={prec}")
+    Ad, Bd = _dev(A), _dev(B)
+    p = mixlu.PREC[prec]
+    o = mixlu.default_opts()
+    work = solver.workspace(mixlu.OP_GESV, p, n, nrhs, o)
+    F, info = mixlu.mixlu_getrf(solver.ctx, p, Ad, work, o)
+    assert info == 0
+    X = torch.empty_like(Bd)
+    mixlu.mixlu_getrs(solver.ctx, F, Bd, X, trans=1)
+    torch.cuda.synchronize()
+    x0 = X.cpu().numpy()
+    rep = mixlu.mixlu_refine(solver.ctx, F, Ad, Bd, X, o, trans=1).as_dict()
+    ref = O.gesv_ir(A, B, trans=True)
+    k = kappa if n > 1 else 1.0
+    _check(A.T.copy(), B, X.cpu().numpy(), k, ref.x)
+    assert rep["converged"], rep
+    # x_0 alone is a low-precision solve of A^T x = b
+    eps_s = {"fp32": 2.0 ** -24, "fp64": 2.0 ** -53, "fp16": 2.0 ** -11}[prec]
+    err0 = np.abs(x0 - ref.x).max() / np.abs(ref.x).max()
+    assert err0 <= 50 * n * eps_s * k, err0
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+@pytest.mark.parametrize("n,nrhs", [(65, 1), (300, 3), (700, 2)])
+def test_column_major_layout(solver, n, nrhs, prec):
+    """LAPACK (column-major) storage of A, B and X: the library factors the
+    row-major matrix the memory holds (A^T) and solves transposed."""
+    kappa = 1e3
+    A, b, _ = gen.prescribed_cond_system(n, kappa, 5000 + n, nrhs=nrhs)
+    _say(f"col-major n={n} nrhs={nrhs} prec={prec}")
+    Acm = _dev(A.T).t()          # storage of A column by column
+    Bcm = _dev(b.T).t()
+    assert Acm.stride(0) == 1
+    r = solver.dxgesv(Acm, Bcm, prec)
+    X = r.x
+    assert (nrhs == 1) or X.stride(0) == 1
+    ref = O.gesv_ir(A, b)
+    _check(A, b, X.cpu().numpy(), kappa, ref.x)
+    assert r.report["converged"]
+
+
+def test_outer_update(solver):
+    from paper_0808_2794_amd import mixlu
+
+    n, nrhs = 130, 7
+    g = np.random.default_rng(9)
+    G, X, GA0 = g.standard_normal((n, nrhs)), g.standard_normal((n, nrhs)), g.standard_normal((n, n))
+    _say("outer update")
+    GAd = _dev(GA0)
+    mixlu.mixlu_outer_update(solver.ctx, _dev(G), _dev(X), GAd, -1.0, 0.5)
+    expect = 0.5 * GA0 - G @ X.T
+    assert np.abs(GAd.cpu().numpy() - expect).max() <= 1e-13 * np.abs(expect).max()
+
+
+def _reference_grads(A, B, Wt):
+    """Oracle gradient of L = sum(W * X), X = A^{-1} B: G_B = A^{-T} W,
+    G_A = -G_B X^T, both from FP64 oracle solves."""
+    X = O.gesv_ir(A, B).x
+    GB = O.gesv_ir(A, Wt, trans=True).x
+    return X, GB, -GB @ X.T
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "fp64"])
+def test_autograd_vs_reference_gradient(solver, prec):
+    import torch
+
+    from paper_0808_2794_amd.autograd import solve
+
+    n, nrhs, kappa = 300, 4, 1e3
+    A, B, Wt = gen.grad_problem(n, nrhs, kappa, seed=502)
+    _say(f"autograd n={n} prec={prec}")
+    Ad = _dev(A).requires_grad_(True)
+    Bd = _dev(B).requires_grad_(True)
+    X = solve(Ad, Bd, prec, solver)
+    loss = (X * _dev(Wt)).sum()
+    loss.backward()
+    Xr, GBr, GAr = _reference_grads(A, B, Wt)
+    assert np.abs(X.detach().cpu().numpy() - Xr).max() <= 1e-12 * kappa * np.abs(Xr).max()
+    gb = Bd.grad.cpu().numpy()
+    ga = Ad.grad.cpu().numpy()
+    assert np.abs(gb - GBr).max() <= 1e-12 * kappa * np.abs(GBr).max()
+    assert np.abs(ga - GAr).max() <= 1e-12 * kappa * np.abs(GAr).max()
+
+
+def test_autograd_finite_differences(solver):
+    """Directional derivatives of L = sum(W * X) against central differences
+    of FP64 oracle solves, for a random direction in A and in B."""
+    from paper_0808_2794_amd.autograd import solve
+
+    n, nrhs, kappa = 40, 2, 1e2
+    A, B, Wt = gen.grad_problem(n, nrhs, kappa, seed=503)
+    _say("autograd finite differences")
+    Ad = _dev(A).requires_grad_(True)
+    Bd = _dev(B).requires_grad_(True)
+    loss = (solve(Ad, Bd, "fp32", solver) * _dev(Wt)).sum()
+    loss.backward()
+    g = np.random.default_rng(11)
+    E, F = g.standard_normal((n, n)), g.standard_normal((n, nrhs))
+
+    def L(Am, Bm):
+        return float((O.gesv_ir(Am, Bm).x * Wt).sum())
+
+    h = 1e-6 * np.abs(A).sum(1).max() / np.abs(E).sum(1).max()
+    fd_a = (L(A + h * E, B) - L(A - h * E, B)) / (2 * h)
+    an_a = float((Ad.grad.cpu().numpy() * E).sum())
+    assert abs(fd_a - an_a) <= 1e-6 * max(1.0, abs(an_a)), (fd_a, an_a)
+    hb = 1e-6 * np.abs(B).max() / np.abs(F).max()
+    fd_b = (L(A, B + hb * F) - L(A, B - hb * F)) / (2 * hb)
+    an_b = float((Bd.grad.cpu().numpy() * F).sum())
+    assert abs(fd_b - an_b) <= 1e-6 * max(1.0, abs(an_b)), (fd_b, an_b)
+
+
+def test_autograd_n1_closed_form(solver):
+    """n = 1: x = b / a, dL/da = -w b / a^2, dL/db = w / a."""
+    from paper_0808_2794_amd.autograd import solve
+
+    a, b, w = 0.75, -1.25, 2.0
+    Ad = _dev(np.array([[a]])).requires_grad_(True)
+    Bd = _dev(np.array([[b]])).requires_grad_(True)
+    _say("autograd n=1")
+    (solve(Ad, Bd, "fp32", solver) * w).sum().backward()
+    assert abs(float(Ad.grad.item()) - (-w * b / a ** 2)) <= 1e-15 * abs(w * b / a ** 2)
+    assert abs(float(Bd.grad.item()) - w / a) <= 1e-15 * abs(w / a)
+
+
+def test_adjoint_full_size(solver):
+    """The differentiable-solve workload at full size: n = 4096, 64
+    right-hand sides, kappa = 1e3, FP16 trailing-update operands; forward and
+    adjoint against the oracle's FP64 solves."""
+    import torch
+
+    from paper_0808_2794_amd.autograd import solve
+
+    n, nrhs, kappa = 4096, 64, 1e3
+    A, B, Wt = gen.grad_problem(n, nrhs, kappa, seed=501)
+    _say("adjoint n=4096 nrhs=64 fp16")
+    Ad = _dev(A).requires_grad_(True)
+    Bd = _dev(B).requires_grad_(True)
+    X = solve(Ad, Bd, "fp16", solver)
+    (X * _dev(Wt)).sum().backward()
+    torch.cuda.synchronize()
+    Xr, GBr, _ = _reference_grads(A, B, Wt)
+    assert np.abs(X.detach().cpu().numpy() - Xr).max() <= 1e-12 * kappa * np.abs(Xr).max()
+    gb = Bd.grad.cpu().numpy()
+    assert np.abs(gb - GBr).max() <= 1e-12 * kappa * np.abs(GBr).max()
+    # G_A = -G_B X^T, checked on sampled entries
+    ga = Ad.grad
+    idx = np.random.default_rng(1).integers(0, n, (64, 2))
+    for i, j in idx:
+        expect = -float(GBr[i] @ Xr[j])
+        assert abs(float(ga[i, j]) - expect) <= 1e-11 * kappa * np.abs(GBr).max() * np.abs(Xr).max()
