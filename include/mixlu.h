@@ -248,10 +248,32 @@ int mixlu_outer_update(mixlu_ctx_t ctx, int n, int nrhs, const double *Gb,
                        int ldg, const double *X, int ldx, double *GA, int ldga,
                        double alpha, double GA_beta);
 
+/* ------------------------------------------------------------ batched */
+/* Many independent systems A_i x_i = b_i (each n_i <= 512), every one
+   solved as mixlu_dxgesv would (factor in prec with the same
+   equilibration rule, x_0, FP64 refinement, stall rule, FP64 fallback),
+   all inside one persistent launch: each workgroup takes systems from a
+   device queue ordered by decreasing n_i and solves them one at a time.
+   All pointer arrays and the reports live in device memory: d_n[i] order,
+   d_A[i] row-major n_i x n_i with leading dimension d_lda[i] (d_lda = NULL:
+   n_i), d_B[i] and d_X[i] row-major n_i x nrhs with leading dimension nrhs.
+   d_reps[i] (device) receives the report of system i; a system with
+   n_i > 512 or lda_i < n_i gets info = -1, converged = 0 and X untouched.
+   The call only enqueues work on the context's stream: no synchronization,
+   no allocation, no host reads of device data, so it can be captured in a
+   HIP graph and replayed.  Row-major layout only. */
+int mixlu_batched_workspace_size(mixlu_ctx_t ctx, int prec, int batch, int nrhs,
+                                 const mixlu_opts *o, size_t *bytes);
+int mixlu_dxgesv_batched(mixlu_ctx_t ctx, int prec, int batch, const int *d_n,
+                         const double *const *d_A, const int *d_lda,
+                         const double *const *d_B, double *const *d_X, int nrhs,
+                         void *work, size_t lwork, const mixlu_opts *o,
+                         mixlu_report *d_reps);
+
 /* ------------------------------------------------------ kernel timing */
 /* Per-kernel-class timing for measurement: with profiling enabled, the
    launches of the main kernel classes ("panel_getf2", "trailing_update",
-   "pack_operands", "trsv", "residual", "panel_potf2") are bracketed by HIP events on the
+   "pack_operands", "trsv", "residual", "panel_potf2", "batched_solve") are bracketed by HIP events on the
    context's stream, and each class accumulates its launch count, total
    device time and the algorithmic flops and bytes of its launches (the work
    the method requires, not the traffic the kernels generate).  Enabling

@@ -28,9 +28,10 @@ struct ProfPending {
     hipEvent_t a, b;
     double flops, bytes;
 };
-enum ProfClass { PC_PANEL, PC_TRAIL, PC_PACK, PC_TRSV, PC_RESID, PC_CPANEL, PC_COUNT };
+enum ProfClass { PC_PANEL, PC_TRAIL, PC_PACK, PC_TRSV, PC_RESID, PC_CPANEL, PC_BATCH, PC_COUNT };
 static const char *const kProfNames[PC_COUNT] = {"panel_getf2", "trailing_update", "pack_operands",
-                                                 "trsv", "residual", "panel_potf2"};
+                                                 "trsv", "residual", "panel_potf2",
+                                                 "batched_solve"};
 struct Prof {
     bool on = false;
     std::vector<hipEvent_t> pool;
@@ -933,6 +934,53 @@ int mixlu_dposv(mixlu_ctx_t ctx, int n, int nrhs, const double *A, int lda, cons
     if (!ctx) return -1;
     ProfCall pc_(ctx);
     return d_entry(ctx, MIXLU_OP_DPOSV, n, nrhs, A, lda, B, ldb, X, ldx, work, lwork, info);
+}
+
+int mixlu_batched_workspace_size(mixlu_ctx_t ctx, int prec, int batch, int nrhs,
+                                 const mixlu_opts *o, size_t *bytes) {
+    if (!ctx) return -1;
+    if (!prec_valid(prec) || prec == MIXLU_FP8) return -2;
+    if (batch < 0) return -3;
+    if (nrhs < 1) return -4;
+    if (!bytes) return -6;
+    (void)o;
+    const size_t slots = (size_t)(batch < kBatchedSlots ? batch : kBatchedSlots);
+    *bytes = align_up((size_t)batch * 4, 256) + 256 + slots * batched_slot_bytes();
+    return MIXLU_OK;
+}
+
+int mixlu_dxgesv_batched(mixlu_ctx_t ctx, int prec, int batch, const int *d_n,
+                         const double *const *d_A, const int *d_lda, const double *const *d_B,
+                         double *const *d_X, int nrhs, void *work, size_t lwork,
+                         const mixlu_opts *o, mixlu_report *d_reps) {
+    if (!ctx) return -1;
+    ProfCall pc_(ctx);
+    if (!prec_valid(prec)) return -2;
+    if (prec == MIXLU_FP8) return MIXLU_ERR_NOT_IMPLEMENTED;
+    if (batch < 0) return -3;
+    if (batch > 0 && !d_n) return -4;
+    if (batch > 0 && !d_A) return -5;
+    if (batch > 0 && !d_B) return -7;
+    if (batch > 0 && !d_X) return -8;
+    if (nrhs < 1) return -9;
+    if (batch > 0 && !work) return -10;
+    if (batch > 0 && !d_reps) return -13;
+    const mixlu_opts op_ = opts_or_default(o);
+    if (op_.layout != MIXLU_ROW_MAJOR) return MIXLU_ERR_NOT_IMPLEMENTED;
+    size_t need = 0;
+    RETCK(mixlu_batched_workspace_size(ctx, prec, batch, nrhs, &op_, &need));
+    if (lwork < need) return MIXLU_ERR_WORKSPACE;
+    if (batch == 0) return MIXLU_OK;
+    auto *base = static_cast<unsigned char *>(work);
+    int *order = reinterpret_cast<int *>(base);
+    int *counter = reinterpret_cast<int *>(base + align_up((size_t)batch * 4, 256));
+    void *slots = base + align_up((size_t)batch * 4, 256) + 256;
+    const int nslots = batch < kBatchedSlots ? batch : kBatchedSlots;
+    ProfScope ps(PC_BATCH, 0.0, 0.0, ctx->stream);
+    HIPCK(launch_batched(prec, batch, nrhs, equil_for(prec, op_), op_.itermax, op_.stall,
+                         prec != MIXLU_FP64 && op_.fallback, d_n, d_A, d_lda, d_B, d_X, d_reps,
+                         order, counter, slots, nslots, ctx->stream));
+    return MIXLU_OK;
 }
 
 int mixlu_profile_enable(mixlu_ctx_t ctx, int on) {

@@ -24,6 +24,8 @@ constexpr int kTrsvBS = 64;        // rows per block of the chained solves
 constexpr int kTrsvNRT = 8;        // right-hand sides per chained-solve launch
 constexpr int kColChunks = 64;   // row chunks of the column-statistics pass
 constexpr unsigned kSpinLimit = 1u << 23;  // polls before a device wait gives up
+constexpr int kBatchedNmax = 512;   // largest order of a batched system
+constexpr int kBatchedSlots = 512;  // workgroups (and workspace slots) of a batched launch
 
 // status words kept in the workspace (int32 each)
 enum StatusWord {
@@ -94,6 +96,81 @@ template <typename T> struct Vq {
     static constexpr int V = 16 / sizeof(T);
     typedef T type __attribute__((ext_vector_type(V)));
 };
+// ---------------------------------------------------------------------
+// Wave-wide reductions on DPP (no LDS traffic).  After the four in-row
+// steps every lane of a 16-lane row holds the row's result; row_bcast:15
+// and row_bcast:31 fold the rows so that lane 63 holds the wave's result,
+// which is then read into a scalar register.
+// ---------------------------------------------------------------------
+template <int CTRL, int RM>
+__device__ __forceinline__ unsigned dpp32(unsigned x) {
+    return (unsigned)__builtin_amdgcn_update_dpp((int)x, (int)x, CTRL, RM, 0xF, false);
+}
+template <int CTRL, int RM>
+__device__ __forceinline__ unsigned long long dpp64(unsigned long long x) {
+    const unsigned lo = dpp32<CTRL, RM>((unsigned)x);
+    const unsigned hi = dpp32<CTRL, RM>((unsigned)(x >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+}
+// Wave-wide maximum of a float or double with the result in every lane
+// (read back as a uniform value).  For FP32 each step is one DPP-fused
+// v_max; FP64 moves both halves and takes v_max_f64.
+template <int CTRL, int RM> __device__ __forceinline__ float dppf(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(x), __float_as_int(x), CTRL,
+                                                      RM, 0xF, false));
+}
+template <int CTRL, int RM> __device__ __forceinline__ double dppd(double x) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+    return __longlong_as_double((long long)dpp64<CTRL, RM>(u));
+}
+// Candidate values are |x| >= 0 or -1 (no candidate).  For FP32 they order
+// like their bit patterns read as signed integers, so the step is an integer
+// max, which takes a DPP operand directly (a float max would have to
+// canonicalize NaNs first).
+template <int CTRL, int RM> __device__ __forceinline__ int dpp_maxi(int x) {
+    // rows outside RM keep x: max(x, x) = x
+    return max(x, __builtin_amdgcn_update_dpp(x, x, CTRL, RM, 0xF, false));
+}
+template <typename T, int CTRL, int RM> __device__ __forceinline__ T dmax(T x) {
+    if constexpr (sizeof(T) == 4) return __int_as_float(dpp_maxi<CTRL, RM>(__float_as_int(x)));
+    else return fmax(x, dppd<CTRL, RM>(x));
+}
+// max over all 64 lanes
+template <typename T> __device__ __forceinline__ T wave_max(T x) {
+    x = dmax<T, 0xB1, 0xF>(x);   // quad_perm [1,0,3,2]
+    x = dmax<T, 0x4E, 0xF>(x);   // quad_perm [2,3,0,1]
+    x = dmax<T, 0x141, 0xF>(x);  // row_half_mirror
+    x = dmax<T, 0x140, 0xF>(x);  // row_mirror
+    x = dmax<T, 0x142, 0xA>(x);  // row_bcast:15 into rows 1, 3
+    x = dmax<T, 0x143, 0xC>(x);  // row_bcast:31 into rows 2, 3
+    return readlane_t(x, 63);
+}
+// max over lanes 0..7 (the other lanes must hold -1)
+template <typename T> __device__ __forceinline__ T max8(T x) {
+    x = dmax<T, 0xB1, 0xF>(x);
+    x = dmax<T, 0x4E, 0xF>(x);
+    x = dmax<T, 0x141, 0xF>(x);
+    return readlane_t(x, 0);
+}
+// Index of the first lane whose predicate holds (64 if none).
+__device__ __forceinline__ int first_lane(bool pred) {
+    const unsigned long long m = __ballot(pred);
+    return m ? __ffsll((long long)m) - 1 : 64;
+}
+
+// Pivot choice inside one wave: the largest |value| among the valid lanes,
+// the smallest lane (= smallest row) on ties.  Invalid lanes hold -1.
+template <typename T> struct WaveArgmax {
+    T val;    // winning |value| (-1 if no valid lane)
+    int lane; // winning lane (64 if none)
+};
+template <typename T> __device__ __forceinline__ WaveArgmax<T> wave_argmax(T v) {
+    WaveArgmax<T> r;
+    r.val = wave_max(v);
+    r.lane = first_lane(r.val >= (T)0 && v == r.val);
+    return r;
+}
+
 template <typename T> struct Words;
 template <> struct Words<float> {
     static constexpr int n = 1;
@@ -177,6 +254,13 @@ template <typename T>
 hipError_t launch_chol_panel(T *W, int ldw, int k, int below, T *diag, int *status, hipStream_t s);
 template <typename T>
 hipError_t launch_chol_to_lu(T *W, int ldw, int npad, const T *diag, hipStream_t s);
+
+// a10: batched solves (k_batched.hip)
+size_t batched_slot_bytes();
+hipError_t launch_batched(int prec, int batch, int nrhs, int equil, int itermax, double stall,
+                          int fallback, const int *n, const double *const *A, const int *lda,
+                          const double *const *B, double *const *X, mixlu_report *rep,
+                          int *order, int *counter, void *slots, int nslots, hipStream_t s);
 
 // a4-a8: solves and refinement (k_solve.hip)
 template <typename Tw>

@@ -1,0 +1,663 @@
+// Batched mixed-precision solves: many independent systems of order <= 512,
+// each solved completely (Algorithm 1 with its FP64 fallback) by one
+// workgroup of a persistent launch.  Workgroups take systems from an atomic
+// queue ordered largest first, so the launch needs no host synchronization
+// and allocates nothing (it can be captured in a HIP graph).
+//
+// Per system, inside one 512-thread workgroup (thread i owns row i):
+//   scales   row sums (||A||_inf), power-of-two row and column scales for
+//            BF16/FP16 factors, W = fl(R A C) into the workgroup's slot
+//   getrf    right-looking LU with partial pivoting, panels of 32 columns
+//            held one row per thread, pivot search by wave argmax; row
+//            interchanges outside the panel as one composed move list;
+//            U12 by forward substitution and the rank-32 trailing update in
+//            column chunks staged through LDS (BF16/FP16 operands rounded
+//            before the FP32 multiply-add, as on the MFMA path)
+//   getrs    P, then blocked forward/backward substitution (64 x 64 diagonal
+//            blocks in one wave, row updates by all threads)
+//   refine   r = b - A x in FP64 with the original A, stopping test,
+//            stall rule, x += z; FP64 LU of the same system on failure.
+#include <climits>
+
+#include "common.h"
+
+namespace mixlu {
+
+constexpr int kBT = 512;      // threads per workgroup = largest order
+constexpr int kBW = kBT / 64; // waves
+constexpr int kBB = 16;       // panel width
+constexpr int kBC = 128;      // trailing-update chunk (columns)
+constexpr int kBDiag = 32;    // diagonal block of the triangular solves
+constexpr int kSUP = kBB + 4; // pitch of a staged U12 column (16-byte aligned)
+
+struct BShared {
+    double x[kBatchedNmax];   // solution column (FP64)
+    double r[kBatchedNmax];   // right-hand side / residual (FP64)
+    double R[kBatchedNmax], C[kBatchedNmax];
+    double y[kBatchedNmax];   // solve vector (float or double storage)
+    double L11[kBB * (kBB + 4)]; // unit lower block of the current panel (T storage)
+    double sU[kBC * kSUP];    // staged U12 chunk, column-major (float or double storage)
+    double prow[kBB], drow[kBB];
+    double valw[kBW];
+    double red[kBW][2];
+    int pivw[kBW];
+    int piv[kBatchedNmax];
+    int src[kBatchedNmax];
+    int mv_dst[2 * kBB], mv_src[2 * kBB];
+    int nmoves;
+    int bad;                  // first failing pivot column + 1 (INT_MAX: none)
+    int overflow;
+    int sys;
+};
+
+// Value of a trailing-update operand after rounding to the operand format
+// (identity for FP32/FP64 factors).
+template <int LP, typename T> __device__ __forceinline__ T lowp_round(T v) {
+    if constexpr (LP == MIXLU_FP16) return (T)(_Float16)v;
+    else if constexpr (LP == MIXLU_BF16) return (T)(__bf16)v;
+    else return v;
+}
+
+// ---------------------------------------------------------------- scales
+// ||A||_inf -> return value (all threads); R, C in LDS (power-of-two
+// equilibration when equil, else 1); W = fl(R A C) with ld = n.
+template <typename T>
+__device__ __noinline__ double sys_convert(const double *__restrict__ A, int lda, int n, int equil,
+                              T *__restrict__ W, BShared &sh) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double anorm = 0.0;
+    // row max and row sum: one wave per row, lanes along the row
+    for (int i = wave; i < n; i += kBW) {
+        double mx = 0.0, sm = 0.0;
+        for (int j = lane; j < n; j += 64) {
+            const double v = fabs(A[(size_t)i * lda + j]);
+            mx = (v > mx || v != v) ? v : mx;
+            sm += v;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const double o = __shfl_xor(mx, off);
+            mx = (o > mx || o != o) ? o : mx;
+            sm += __shfl_xor(sm, off);
+        }
+        if (lane == 0) {
+            double s = 1.0;
+            if (equil && mx > 0.0 && mx <= 1.79769313486231570815e308) s = ldexp(1.0, -ilogb(mx));
+            sh.R[i] = s;
+            sh.x[i] = sm;  // row sums, reduced below
+        }
+    }
+    __syncthreads();
+    {
+        double m = 0.0;
+        for (int i = tid; i < n; i += kBT) {
+            const double v = sh.x[i];
+            m = (v > m || v != v) ? v : m;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const double o = __shfl_xor(m, off);
+            m = (o > m || o != o) ? o : m;
+        }
+        if (lane == 0) sh.red[wave][0] = m;
+    }
+    // column scales from the R-scaled column max: one thread per column
+    for (int j = tid; j < n; j += kBT) {
+        double s = 1.0;
+        if (equil) {
+            double mx = 0.0;
+            for (int i = 0; i < n; ++i) {
+                const double v = fabs(A[(size_t)i * lda + j]) * sh.R[i];
+                mx = (v > mx || v != v) ? v : mx;
+            }
+            if (mx > 0.0 && mx <= 1.79769313486231570815e308) s = ldexp(1.0, -ilogb(mx));
+        }
+        sh.C[j] = s;
+    }
+    __syncthreads();
+    for (int q = 0; q < kBW; ++q) {
+        const double v = sh.red[q][0];
+        anorm = (v > anorm || v != v) ? v : anorm;
+    }
+    // conversion, one thread per column (coalesced rows)
+    int bad = 0;
+    for (int j = tid; j < n; j += kBT) {
+        const double cj = sh.C[j];
+        for (int i = 0; i < n; ++i) {
+            const T w = (T)(sh.R[i] * A[(size_t)i * lda + j] * cj);
+            if (!(fabs((double)w) <= 1.79769313486231570815e308)) ++bad;
+            W[(size_t)i * n + j] = w;
+        }
+    }
+    if (bad) atomicAdd(&sh.overflow, bad);
+    __syncthreads();
+    return anorm;
+}
+
+// ------------------------------------------------------------------ getrf
+// In-place LU with partial pivoting of the n x n W (ld = n) by the whole
+// workgroup; pivots in sh.piv; the first zero / non-finite pivot column is
+// recorded in sh.bad.  tmp: scratch of 2 * kBB * n elements for row moves.
+template <typename T, int LP>
+__device__ __noinline__ void sys_getrf(T *__restrict__ W, int n, T *__restrict__ tmp, BShared &sh) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int row = tid;
+    T *prow = reinterpret_cast<T *>(sh.prow);
+    T *drow = reinterpret_cast<T *>(sh.drow);
+    T *sU = reinterpret_cast<T *>(sh.sU);
+    T *L11 = reinterpret_cast<T *>(sh.L11);
+    T *valw = reinterpret_cast<T *>(sh.valw);
+    constexpr int LP11 = kBB + 4;  // 16-byte aligned rows
+    for (int k = 0; k < n; k += kBB) {
+        const int w = n - k < kBB ? n - k : kBB;
+        T a[kBB];
+        const bool mine = row >= k && row < n;
+#pragma unroll
+        for (int c = 0; c < kBB; ++c) a[c] = (mine && c < w) ? W[(size_t)row * n + k + c] : (T)0;
+        sfor<0, kBB>([&](auto J) {
+            constexpr int j = decltype(J)::value;
+            if (j < w) {
+                const int kj = k + j;
+                const T av = fabs(a[j]);
+                const T v = (row >= kj && row < n && av == av) ? av : (T)-1;
+                const WaveArgmax<T> wa = wave_argmax(v);
+                if (lane == 0) {
+                    valw[wave] = wa.val;
+                    sh.pivw[wave] = wa.lane < 64 ? wave * 64 + wa.lane : -1;
+                }
+                __syncthreads();
+                T best = (T)-1;
+                int p = -1;
+#pragma unroll
+                for (int q = 0; q < kBW; ++q) {
+                    const T vq = valw[q];
+                    if (vq > best) {
+                        best = vq;
+                        p = sh.pivw[q];
+                    }
+                }
+                if (!(best > (T)0) || !(best < (T)INFINITY)) {
+                    if (tid == 0) sh.bad = min(sh.bad, kj + 1);
+                    p = kj;
+                }
+                if (row == p) {
+#pragma unroll
+                    for (int c = 0; c < kBB; ++c) prow[c] = a[c];
+                }
+                if (row == kj) {
+#pragma unroll
+                    for (int c = 0; c < kBB; ++c) drow[c] = a[c];
+                }
+                if (tid == 0) sh.piv[kj] = p;
+                __syncthreads();
+                if (row == kj) {
+#pragma unroll
+                    for (int c = 0; c < kBB; ++c) a[c] = prow[c];
+                } else if (row == p) {
+#pragma unroll
+                    for (int c = 0; c < kBB; ++c) a[c] = drow[c];
+                }
+                if (row > kj && row < n) {
+                    const T pv = prow[j];
+                    const T l = a[j] / pv;
+                    a[j] = l;
+#pragma unroll
+                    for (int c = j + 1; c < kBB; ++c) a[c] -= l * prow[c];
+                }
+            }
+        });
+        if (mine) {
+#pragma unroll
+            for (int c = 0; c < kBB; ++c)
+                if (c < w) W[(size_t)row * n + k + c] = a[c];
+        }
+        // row-move composition
+        for (int r = tid; r < n; r += kBT) sh.src[r] = r;
+        if (tid == 0) sh.nmoves = 0;
+        __syncthreads();
+        // unit lower diagonal block for U12, read back from the stored panel
+        for (int e = tid; e < w * kBB; e += kBT) {
+            const int r = e / kBB, c = e - r * kBB;
+            L11[r * LP11 + c] = c < w ? W[(size_t)(k + r) * n + k + c] : (T)0;
+        }
+        if (tid == 0) {
+            for (int j = 0; j < w; ++j) {
+                const int kj = k + j, p = sh.piv[kj];
+                const int t = sh.src[kj];
+                sh.src[kj] = sh.src[p];
+                sh.src[p] = t;
+            }
+        }
+        __syncthreads();
+        if (row < n && sh.src[row] != row) {
+            const int m = atomicAdd(&sh.nmoves, 1);
+            sh.mv_dst[m] = row;
+            sh.mv_src[m] = sh.src[row];
+        }
+        __syncthreads();
+        const int nm = sh.nmoves;
+        // rows move in the columns left and right of the panel: thread t owns column t
+        const bool outside = tid < n && (tid < k || tid >= k + w);
+        if (outside) {
+            for (int m = 0; m < nm; ++m) tmp[(size_t)m * n + tid] = W[(size_t)sh.mv_src[m] * n + tid];
+        }
+        __syncthreads();
+        if (outside) {
+            for (int m = 0; m < nm; ++m) W[(size_t)sh.mv_dst[m] * n + tid] = tmp[(size_t)m * n + tid];
+        }
+        __syncthreads();
+        // U12 = L11^{-1} A12 and A22 -= L21 U12, by chunks of kBC columns;
+        // a[] now only serves as the L21 operand
+#pragma unroll
+        for (int c = 0; c < kBB; ++c) a[c] = lowp_round<LP>(a[c]);
+        for (int c0 = k + w; c0 < n; c0 += kBC) {
+            const int nc = n - c0 < kBC ? n - c0 : kBC;
+            if (tid < nc) {
+                // column c0 + tid of U12 by forward substitution; the column
+                // lives in this thread's LDS row of sU while it is solved
+                const int col = c0 + tid;
+                T *xs = sU + tid * kSUP;
+                for (int r = 0; r < w; ++r) {
+                    T s = W[(size_t)(k + r) * n + col];
+                    for (int q = 0; q < r; ++q) s -= L11[r * LP11 + q] * xs[q];
+                    xs[r] = s;
+                    W[(size_t)(k + r) * n + col] = s;
+                }
+                for (int r = 0; r < kBB; ++r) {
+                    const T x = r < w ? xs[r] : (T)0;
+                    if constexpr (LP == MIXLU_FP16)
+                        if (fabs(x) > (T)65504) atomicAdd(&sh.overflow, 1);
+                    xs[r] = lowp_round<LP>(x);
+                }
+            }
+            __syncthreads();
+            if (row >= k + w && row < n) {
+                T *wr = W + (size_t)row * n + c0;
+                for (int t = 0; t < nc; ++t) {
+                    T acc = wr[t];
+#pragma unroll
+                    for (int q = 0; q < kBB; ++q) acc -= a[q] * sU[t * kSUP + q];
+                    wr[t] = acc;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ------------------------------------------------------------------ getrs
+// z = C U^{-1} L^{-1} P (R rhs) with rhs = sh.r (FP64); z into sh.y as double.
+template <typename T>
+__device__ __noinline__ void sys_getrs(const T *__restrict__ W, int n, BShared &sh) {
+    const int tid = threadIdx.x, lane = tid & 63;
+    T *y = reinterpret_cast<T *>(sh.y);
+    for (int i = tid; i < n; i += kBT) y[i] = (T)(sh.R[i] * sh.r[i]);
+    __syncthreads();
+    if (tid == 0) {
+        for (int j = 0; j < n; ++j) {
+            const int p = sh.piv[j];
+            if (p != j) {
+                const T t = y[j];
+                y[j] = y[p];
+                y[p] = t;
+            }
+        }
+    }
+    __syncthreads();
+    // diagonal blocks are staged through LDS (the sU area is free here)
+    T *sd = reinterpret_cast<T *>(sh.sU);
+    constexpr int DP = kBDiag + 1;
+    auto stage = [&](int b0) {
+        for (int e = tid; e < kBDiag * kBDiag; e += kBT) {
+            const int r = e / kBDiag, c = e - r * kBDiag;
+            sd[r * DP + c] = (b0 + r < n && b0 + c < n) ? W[(size_t)(b0 + r) * n + b0 + c] : (T)0;
+        }
+        __syncthreads();
+    };
+    // forward: unit lower
+    for (int b0 = 0; b0 < n; b0 += kBDiag) {
+        stage(b0);
+        if (tid < kBDiag) {
+            const int i = b0 + lane;
+            T yl = i < n ? y[i] : (T)0;
+#pragma unroll
+            for (int q = 0; q < kBDiag; ++q) {
+                const T yq = readlane_t(yl, q);
+                if (lane > q) yl -= sd[lane * DP + q] * yq;
+            }
+            if (i < n) y[i] = yl;
+        }
+        __syncthreads();
+        const int e = n - b0 < kBDiag ? n - b0 : kBDiag;
+        for (int i = b0 + kBDiag + tid; i < n; i += kBT) {
+            T s = y[i];
+            const T *wr = W + (size_t)i * n + b0;
+            for (int q = 0; q < e; ++q) s -= wr[q] * y[b0 + q];
+            y[i] = s;
+        }
+        __syncthreads();
+    }
+    // backward: U
+    for (int b0 = ((n - 1) / kBDiag) * kBDiag; b0 >= 0; b0 -= kBDiag) {
+        stage(b0);
+        if (tid < kBDiag) {
+            const int i = b0 + lane;
+            T yl = i < n ? y[i] : (T)0;
+#pragma unroll
+            for (int q = kBDiag - 1; q >= 0; --q) {
+                if (b0 + q < n) {
+                    const T yq = readlane_t(yl, q) / sd[q * DP + q];
+                    if (lane == q) yl = yq;
+                    else if (lane < q) yl -= sd[lane * DP + q] * yq;
+                }
+            }
+            if (i < n) y[i] = yl;
+        }
+        __syncthreads();
+        const int e = n - b0 < kBDiag ? n - b0 : kBDiag;
+        for (int i = tid; i < b0; i += kBT) {
+            T s = y[i];
+            const T *wr = W + (size_t)i * n + b0;
+            for (int q = 0; q < e; ++q) s -= wr[q] * y[b0 + q];
+            y[i] = s;
+        }
+        __syncthreads();
+    }
+    // promote and scale in place (each thread its own entries)
+    for (int i = tid; i < n; i += kBT) {
+        sh.r[i] = sh.C[i] * (double)y[i];
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------- residual
+// sh.r = b - A x (FP64, original A); returns (||r||_inf, ||x||_inf) in
+// rn/xn on every thread.
+__device__ __noinline__ void sys_residual(const double *__restrict__ A, int lda, int n,
+                             const double *__restrict__ b, int ldb, BShared &sh, double &rn,
+                             double &xn) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double rmax = 0.0, xmax = 0.0;
+    for (int i = wave; i < n; i += kBW) {
+        double s = 0.0;
+        for (int j = lane; j < n; j += 64) s += A[(size_t)i * lda + j] * sh.x[j];
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+        if (lane == 0) {
+            const double r = b[(size_t)i * ldb] - s;
+            sh.r[i] = r;
+            const double ar = fabs(r);
+            rmax = (ar > rmax || ar != ar) ? ar : rmax;
+        }
+    }
+    for (int i = tid; i < n; i += kBT) {
+        const double ax = fabs(sh.x[i]);
+        xmax = (ax > xmax || ax != ax) ? ax : xmax;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_xor(rmax, off);
+        rmax = (o > rmax || o != o) ? o : rmax;
+        const double p = __shfl_xor(xmax, off);
+        xmax = (p > xmax || p != p) ? p : xmax;
+    }
+    if (lane == 0) {
+        sh.red[wave][0] = rmax;
+        sh.red[wave][1] = xmax;
+    }
+    __syncthreads();
+    rn = 0.0;
+    xn = 0.0;
+#pragma unroll
+    for (int q = 0; q < kBW; ++q) {
+        const double a = sh.red[q][0], c = sh.red[q][1];
+        rn = (a > rn || a != a) ? a : rn;
+        xn = (c > xn || c != c) ? c : xn;
+    }
+    __syncthreads();
+}
+
+struct RefineOut {
+    int iters;  // >= 0 converged after that many corrections; < 0 failure code
+    double rn, xn;
+};
+
+// Algorithm 1 steps 4-7 for one right-hand-side column from x = sh.x, with
+// the factor W (T storage).  Every thread takes the same decisions.
+template <typename T>
+__device__ __noinline__ RefineOut sys_refine(const double *__restrict__ A, int lda, int n,
+                                const double *__restrict__ b, int ldb, const T *__restrict__ W,
+                                double anorm, int itermax, double stall, BShared &sh) {
+    const double thr = sqrt((double)n) * 1.1102230246251565404e-16 * anorm;
+    double prev = 0.0, ratio_prev = 0.0;
+    RefineOut out{0, 0.0, 0.0};
+    for (int k = 0;; ++k) {
+        double rn, xn;
+        sys_residual(A, lda, n, b, ldb, sh, rn, xn);
+        out.rn = rn;
+        out.xn = xn;
+        const bool finite = rn == rn && xn == xn && rn <= 1.79769313486231570815e308 &&
+                            xn <= 1.79769313486231570815e308;
+        if (finite && rn <= thr * xn) {
+            out.iters = k;
+            return out;
+        }
+        if (!finite) {
+            out.iters = -4;
+            return out;
+        }
+        if (k >= 1 && prev > 0.0) {
+            const double rho = rn / prev;
+            if ((k >= 2 && rho >= stall && ratio_prev >= stall) || (k >= 3 && rho >= 1.0)) {
+                out.iters = -4;
+                return out;
+            }
+            ratio_prev = rho;
+        }
+        prev = rn;
+        if (k == itermax) {
+            out.iters = -(itermax + 1);
+            return out;
+        }
+        sys_getrs<T>(W, n, sh);  // z into sh.r
+        for (int i = threadIdx.x; i < n; i += kBT) sh.x[i] += sh.r[i];
+        __syncthreads();
+    }
+}
+
+struct BatchArgs {
+    int batch, nrhs, equil, itermax;
+    double stall;
+    const int *n;
+    const double *const *A;
+    const int *lda;
+    const double *const *B;
+    double *const *X;
+    mixlu_report *rep;
+    const int *order;
+    int *counter;
+    unsigned char *slots;
+    size_t slot_bytes;
+    int fallback;
+};
+
+// Solve one system with the factor in precision T (LP: trailing operand
+// rounding); falls back to FP64 inside the same slot.
+template <typename T, int LP>
+__device__ void sys_solve(const BatchArgs &g, int s, unsigned char *slot, BShared &sh) {
+    const int tid = threadIdx.x;
+    const int n = g.n[s];
+    const double *A = g.A[s];
+    const int lda = g.lda ? g.lda[s] : n;
+    const double *B = g.B[s];
+    double *X = g.X[s];
+    mixlu_report rep{};
+    rep.prec = sizeof(T) == 8 ? MIXLU_FP64 : (LP ? LP : MIXLU_FP32);
+    if (n <= 0 || n > kBatchedNmax || lda < n) {
+        if (tid == 0) {
+            rep.info = n == 0 ? 0 : -1;
+            rep.converged = n == 0 ? 1 : 0;
+            g.rep[s] = rep;
+        }
+        return;
+    }
+    T *W = reinterpret_cast<T *>(slot);
+    T *tmp = reinterpret_cast<T *>(slot + (size_t)kBatchedNmax * kBatchedNmax * 8);
+    if (tid == 0) {
+        sh.bad = INT_MAX;
+        sh.overflow = 0;
+    }
+    __syncthreads();
+    const double anorm = sys_convert<T>(A, lda, n, g.equil, W, sh);
+    rep.anorm = anorm;
+    if (sh.overflow == 0) sys_getrf<T, LP>(W, n, tmp, sh);
+    int reason = 0;
+    if (sh.overflow) reason = -2;
+    else if (sh.bad != INT_MAX) reason = sizeof(T) == 8 ? -1 : -3;
+    double rn_all = 0.0, xn_all = 0.0;
+    int iters_max = 0;
+    if (reason == 0) {
+        for (int c = 0; c < g.nrhs && reason == 0; ++c) {
+            for (int i = tid; i < n; i += kBT) sh.r[i] = B[(size_t)i * g.nrhs + c];
+            __syncthreads();
+            sys_getrs<T>(W, n, sh);
+            for (int i = tid; i < n; i += kBT) sh.x[i] = sh.r[i];
+            __syncthreads();
+            const RefineOut o = sys_refine<T>(A, lda, n, B + c, g.nrhs, W, anorm, g.itermax,
+                                              g.stall, sh);
+            if (o.iters < 0) {
+                reason = o.iters;
+            } else {
+                iters_max = o.iters > iters_max ? o.iters : iters_max;
+                rn_all = fmax(rn_all, o.rn);
+                xn_all = fmax(xn_all, o.xn);
+                for (int i = tid; i < n; i += kBT) X[(size_t)i * g.nrhs + c] = sh.x[i];
+            }
+            __syncthreads();
+        }
+    }
+    if (reason == 0) {
+        rep.iter = iters_max;
+        rep.converged = 1;
+        rep.rnorm = rn_all;
+        rep.xnorm = xn_all;
+        rep.berr = xn_all > 0 ? rn_all / (anorm * xn_all) : 0.0;
+        if (tid == 0) g.rep[s] = rep;
+        return;
+    }
+    rep.iter = reason;
+    if (sizeof(T) == 8 || !g.fallback) {
+        if (reason == -1) rep.info = sh.bad;
+        if (tid == 0) g.rep[s] = rep;
+        return;
+    }
+    // FP64 fallback in the same slot
+    double *W64 = reinterpret_cast<double *>(slot);
+    double *tmp64 = reinterpret_cast<double *>(slot + (size_t)kBatchedNmax * kBatchedNmax * 8);
+    if (tid == 0) {
+        sh.bad = INT_MAX;
+        sh.overflow = 0;
+    }
+    __syncthreads();
+    sys_convert<double>(A, lda, n, 0, W64, sh);
+    sys_getrf<double, 0>(W64, n, tmp64, sh);
+    rep.prec = MIXLU_FP64;
+    if (sh.bad != INT_MAX) {
+        rep.info = sh.bad;
+        if (tid == 0) g.rep[s] = rep;
+        return;
+    }
+    rn_all = xn_all = 0.0;
+    int fit = 0, conv = 1;
+    for (int c = 0; c < g.nrhs; ++c) {
+        for (int i = tid; i < n; i += kBT) sh.r[i] = B[(size_t)i * g.nrhs + c];
+        __syncthreads();
+        sys_getrs<double>(W64, n, sh);
+        for (int i = tid; i < n; i += kBT) sh.x[i] = sh.r[i];
+        __syncthreads();
+        const RefineOut o = sys_refine<double>(A, lda, n, B + c, g.nrhs, W64, anorm, g.itermax,
+                                               g.stall, sh);
+        if (o.iters < 0) conv = 0;
+        fit = o.iters > fit ? o.iters : fit;
+        rn_all = fmax(rn_all, o.rn);
+        xn_all = fmax(xn_all, o.xn);
+        for (int i = tid; i < n; i += kBT) X[(size_t)i * g.nrhs + c] = sh.x[i];
+        __syncthreads();
+    }
+    rep.fallback_iter = fit;
+    rep.converged = conv;
+    rep.rnorm = rn_all;
+    rep.xnorm = xn_all;
+    rep.berr = xn_all > 0 ? rn_all / (anorm * xn_all) : 0.0;
+    if (tid == 0) g.rep[s] = rep;
+}
+
+template <typename T, int LP>
+__global__ __launch_bounds__(kBT) void k_batched(BatchArgs g) {
+    __shared__ BShared sh;
+    unsigned char *slot = g.slots + (size_t)blockIdx.x * g.slot_bytes;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const int q = atomicAdd(g.counter, 1);
+            sh.sys = q < g.batch ? g.order[q] : -1;
+        }
+        __syncthreads();
+        const int s = sh.sys;
+        __syncthreads();
+        if (s < 0) return;  // every workgroup leaves once the queue is empty
+        sys_solve<T, LP>(g, s, slot, sh);
+        __syncthreads();
+    }
+}
+
+// order[] = system indices by decreasing n (counting sort in one workgroup);
+// out-of-range n sort last.  Also resets the queue counter.
+__global__ __launch_bounds__(1024) void k_batch_order(int batch, const int *__restrict__ n,
+                                                      int *__restrict__ order,
+                                                      int *__restrict__ counter) {
+    constexpr int NB = kBatchedNmax + 2;
+    __shared__ int cnt[NB];
+    __shared__ int start[NB];
+    for (int i = threadIdx.x; i < NB; i += 1024) cnt[i] = 0;
+    __syncthreads();
+    auto bin = [&](int v) { return (v < 0 || v > kBatchedNmax) ? kBatchedNmax + 1 : kBatchedNmax - v; };
+    for (int i = threadIdx.x; i < batch; i += 1024) atomicAdd(&cnt[bin(n[i])], 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int b = 0; b < NB; ++b) {
+            start[b] = acc;
+            acc += cnt[b];
+        }
+        *counter = 0;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < batch; i += 1024) {
+        const int pos = atomicAdd(&start[bin(n[i])], 1);
+        order[pos] = i;
+    }
+}
+
+size_t batched_slot_bytes() {
+    return align_up((size_t)kBatchedNmax * kBatchedNmax * 8 + (size_t)2 * kBB * kBatchedNmax * 8,
+                    256);
+}
+
+hipError_t launch_batched(int prec, int batch, int nrhs, int equil, int itermax, double stall,
+                          int fallback, const int *n, const double *const *A, const int *lda,
+                          const double *const *B, double *const *X, mixlu_report *rep,
+                          int *order, int *counter, void *slots, int nslots, hipStream_t s) {
+    if (batch <= 0) return hipSuccess;
+    k_batch_order<<<dim3(1), dim3(1024), 0, s>>>(batch, n, order, counter);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    BatchArgs g{batch, nrhs, equil, itermax, stall, n, A, lda, B, X, rep, order, counter,
+                static_cast<unsigned char *>(slots), batched_slot_bytes(), fallback};
+    const int grid = batch < nslots ? batch : nslots;
+    switch (prec) {
+        case MIXLU_FP32: k_batched<float, 0><<<grid, kBT, 0, s>>>(g); break;
+        case MIXLU_FP16: k_batched<float, MIXLU_FP16><<<grid, kBT, 0, s>>>(g); break;
+        case MIXLU_BF16: k_batched<float, MIXLU_BF16><<<grid, kBT, 0, s>>>(g); break;
+        case MIXLU_FP64: k_batched<double, 0><<<grid, kBT, 0, s>>>(g); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace mixlu

@@ -30,81 +30,6 @@ template <typename T, int B> struct PanelGeom {
     static constexpr int PAR = kPanelMaxWG * SLOT + B * PWV;  // words per parity
 };
 
-// ---------------------------------------------------------------------
-// Wave-wide reductions on DPP (no LDS traffic).  After the four in-row
-// steps every lane of a 16-lane row holds the row's result; row_bcast:15
-// and row_bcast:31 fold the rows so that lane 63 holds the wave's result,
-// which is then read into a scalar register.
-// ---------------------------------------------------------------------
-template <int CTRL, int RM>
-__device__ __forceinline__ unsigned dpp32(unsigned x) {
-    return (unsigned)__builtin_amdgcn_update_dpp((int)x, (int)x, CTRL, RM, 0xF, false);
-}
-template <int CTRL, int RM>
-__device__ __forceinline__ unsigned long long dpp64(unsigned long long x) {
-    const unsigned lo = dpp32<CTRL, RM>((unsigned)x);
-    const unsigned hi = dpp32<CTRL, RM>((unsigned)(x >> 32));
-    return ((unsigned long long)hi << 32) | lo;
-}
-// Wave-wide maximum of a float or double with the result in every lane
-// (read back as a uniform value).  For FP32 each step is one DPP-fused
-// v_max; FP64 moves both halves and takes v_max_f64.
-template <int CTRL, int RM> __device__ __forceinline__ float dppf(float x) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(x), __float_as_int(x), CTRL,
-                                                      RM, 0xF, false));
-}
-template <int CTRL, int RM> __device__ __forceinline__ double dppd(double x) {
-    const unsigned long long u = (unsigned long long)__double_as_longlong(x);
-    return __longlong_as_double((long long)dpp64<CTRL, RM>(u));
-}
-// Candidate values are |x| >= 0 or -1 (no candidate).  For FP32 they order
-// like their bit patterns read as signed integers, so the step is an integer
-// max, which takes a DPP operand directly (a float max would have to
-// canonicalize NaNs first).
-template <int CTRL, int RM> __device__ __forceinline__ int dpp_maxi(int x) {
-    // rows outside RM keep x: max(x, x) = x
-    return max(x, __builtin_amdgcn_update_dpp(x, x, CTRL, RM, 0xF, false));
-}
-template <typename T, int CTRL, int RM> __device__ __forceinline__ T dmax(T x) {
-    if constexpr (sizeof(T) == 4) return __int_as_float(dpp_maxi<CTRL, RM>(__float_as_int(x)));
-    else return fmax(x, dppd<CTRL, RM>(x));
-}
-// max over all 64 lanes
-template <typename T> __device__ __forceinline__ T wave_max(T x) {
-    x = dmax<T, 0xB1, 0xF>(x);   // quad_perm [1,0,3,2]
-    x = dmax<T, 0x4E, 0xF>(x);   // quad_perm [2,3,0,1]
-    x = dmax<T, 0x141, 0xF>(x);  // row_half_mirror
-    x = dmax<T, 0x140, 0xF>(x);  // row_mirror
-    x = dmax<T, 0x142, 0xA>(x);  // row_bcast:15 into rows 1, 3
-    x = dmax<T, 0x143, 0xC>(x);  // row_bcast:31 into rows 2, 3
-    return readlane_t(x, 63);
-}
-// max over lanes 0..7 (the other lanes must hold -1)
-template <typename T> __device__ __forceinline__ T max8(T x) {
-    x = dmax<T, 0xB1, 0xF>(x);
-    x = dmax<T, 0x4E, 0xF>(x);
-    x = dmax<T, 0x141, 0xF>(x);
-    return readlane_t(x, 0);
-}
-// Index of the first lane whose predicate holds (64 if none).
-__device__ __forceinline__ int first_lane(bool pred) {
-    const unsigned long long m = __ballot(pred);
-    return m ? __ffsll((long long)m) - 1 : 64;
-}
-
-// Pivot choice inside one wave: the largest |value| among the valid lanes,
-// the smallest lane (= smallest row) on ties.  Invalid lanes hold -1.
-template <typename T> struct WaveArgmax {
-    T val;    // winning |value| (-1 if no valid lane)
-    int lane; // winning lane (64 if none)
-};
-template <typename T> __device__ __forceinline__ WaveArgmax<T> wave_argmax(T v) {
-    WaveArgmax<T> r;
-    r.val = wave_max(v);
-    r.lane = first_lane(r.val >= (T)0 && v == r.val);
-    return r;
-}
-
 template <typename T, int NQ>
 __device__ __forceinline__ void row_to_lds(T *dst, const typename Vq<T>::type (&a)[NQ]) {
 #pragma unroll

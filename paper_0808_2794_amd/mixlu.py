@@ -61,7 +61,8 @@ class mixlu_kstat(ctypes.Structure):
 EXPORTS = ("mixlu_status_string", "mixlu_default_opts", "mixlu_create", "mixlu_destroy",
            "mixlu_set_stream", "mixlu_workspace_size", "mixlu_getrf", "mixlu_potrf",
            "mixlu_getrs", "mixlu_refine", "mixlu_dxgesv", "mixlu_dxposv", "mixlu_dgesv",
-           "mixlu_dposv", "mixlu_outer_update", "mixlu_profile_enable", "mixlu_profile_read")
+           "mixlu_dposv", "mixlu_outer_update", "mixlu_batched_workspace_size",
+           "mixlu_dxgesv_batched", "mixlu_profile_enable", "mixlu_profile_read")
 
 _lib = None
 
@@ -91,6 +92,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "mixlu_dgesv": ([P, I, I, P, I, P, I, P, I, P, S, P], I),
         "mixlu_dposv": ([P, I, I, P, I, P, I, P, I, P, S, P], I),
         "mixlu_outer_update": ([P, I, I, P, I, P, I, P, I, D, D], I),
+        "mixlu_batched_workspace_size": ([P, I, I, I, P, P], I),
+        "mixlu_dxgesv_batched": ([P, I, I, P, P, P, P, P, I, P, S, P, P], I),
         "mixlu_profile_enable": ([P, I], I),
         "mixlu_profile_read": ([P, P, I, P], I),
     }
@@ -263,6 +266,33 @@ def mixlu_outer_update(ctx, G, X, GA, alpha: float = -1.0, beta: float = 0.0) ->
                                     _ld(GA), alpha, beta), "mixlu_outer_update")
 
 
+def mixlu_batched_workspace_size(ctx, prec: int, batch: int, nrhs: int, opts=None) -> int:
+    b = ctypes.c_size_t()
+    check(load().mixlu_batched_workspace_size(ctx, prec, batch, nrhs,
+                                              None if opts is None else ctypes.byref(opts),
+                                              ctypes.byref(b)), "mixlu_batched_workspace_size")
+    return b.value
+
+
+def mixlu_dxgesv_batched(ctx, prec: int, d_n, d_A, d_lda, d_B, d_X, nrhs: int, work, d_reps,
+                         opts=None) -> None:
+    """All array arguments are device tensors: d_n int32 [batch], d_A / d_B /
+    d_X int64 device addresses [batch], d_lda int32 [batch] or None, d_reps
+    uint8 [batch * sizeof(mixlu_report)]."""
+    batch = d_n.numel()
+    check(load().mixlu_dxgesv_batched(ctx, prec, batch, _p(d_n), _p(d_A), _p(d_lda), _p(d_B),
+                                      _p(d_X), nrhs, _p(work), work.numel() * work.element_size(),
+                                      None if opts is None else ctypes.byref(opts), _p(d_reps)),
+          "mixlu_dxgesv_batched")
+
+
+def reports_from_bytes(buf) -> list:
+    """Decode a host copy (bytes) of a device array of mixlu_report."""
+    sz = ctypes.sizeof(mixlu_report)
+    return [mixlu_report.from_buffer_copy(buf[i * sz:(i + 1) * sz]).as_dict()
+            for i in range(len(buf) // sz)]
+
+
 def mixlu_profile_enable(ctx, on: bool = True) -> None:
     check(load().mixlu_profile_enable(ctx, int(on)), "mixlu_profile_enable")
 
@@ -349,6 +379,47 @@ class Solver:
         work = self.workspace(OP_POSV, p, A.shape[0], B2.shape[1], o)
         rep = mixlu_dxposv(self.ctx, p, A, B2, X, work, o)
         return Result(X.reshape(-1) if vec else X, rep.as_dict())
+
+    def batched_buffers(self, As, Bs, prec="fp32", opts=None):
+        """Device arrays for mixlu_dxgesv_batched over the lists As (n_i x n_i)
+        and Bs (n_i x nrhs): returns a dict of tensors, reusable for repeated
+        (or graph-captured) calls on the same buffers."""
+        import torch
+
+        p = PREC[prec] if isinstance(prec, str) else prec
+        dev = As[0].device
+        As = [a.contiguous() for a in As]
+        Bs = [(b.reshape(-1, 1) if b.dim() == 1 else b).contiguous() for b in Bs]
+        nrhs = Bs[0].shape[1]
+        Xs = [torch.empty_like(b) for b in Bs]
+        batch = len(As)
+        buf = {
+            "A": As, "B": Bs, "X": Xs, "nrhs": nrhs, "prec": p,
+            "n": torch.tensor([a.shape[0] for a in As], dtype=torch.int32, device=dev),
+            "pA": torch.tensor([a.data_ptr() for a in As], dtype=torch.int64, device=dev),
+            "pB": torch.tensor([b.data_ptr() for b in Bs], dtype=torch.int64, device=dev),
+            "pX": torch.tensor([x.data_ptr() for x in Xs], dtype=torch.int64, device=dev),
+            "reps": torch.zeros(batch * ctypes.sizeof(mixlu_report), dtype=torch.uint8, device=dev),
+            "opts": opts if opts is not None else default_opts(),
+        }
+        need = mixlu_batched_workspace_size(self.ctx, p, batch, nrhs, buf["opts"])
+        buf["work"] = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+        return buf
+
+    def run_batched(self, buf) -> None:
+        """Enqueue the batched solve on the context's stream (no sync)."""
+        mixlu_dxgesv_batched(self.ctx, buf["prec"], buf["n"], buf["pA"], None, buf["pB"],
+                             buf["pX"], buf["nrhs"], buf["work"], buf["reps"], buf["opts"])
+
+    def dxgesv_batched(self, As, Bs, prec="fp32", opts=None):
+        """Solve every A_i x_i = b_i in one persistent launch; returns the list
+        of X_i and the list of reports."""
+        import torch
+
+        buf = self.batched_buffers(As, Bs, prec, opts)
+        self.run_batched(buf)
+        torch.cuda.synchronize()
+        return buf["X"], reports_from_bytes(bytes(buf["reps"].cpu().numpy()))
 
     def _d(self, op, fn, A, B) -> Result:
         A, B2, X, vec, layout = self._prep(A, B)
