@@ -1,18 +1,29 @@
 #!/usr/bin/env python3
-"""Time to an FP64-accurate solve on one MI355X: low-precision LU + FP64
-iterative refinement (Algorithm 1 of Baboulin et al., arXiv:0808.2794)
-versus FP64 LU on the same GPU.
+"""Time to an FP64-accurate solve on one MI355X: low-precision factorization +
+FP64 iterative refinement (Algorithm 1 of Baboulin et al., arXiv:0808.2794)
+versus FP64 factorizations on the same GPU.
 
-Workload: dense nonsymmetric A = U diag(sigma) V^T, n = 16384, sigma
-geometric from 1 to 1/kappa with kappa = 1e4, U and V Haar orthogonal,
-x_true iid U[-1, 1], b = A x_true, one right-hand side (seed 221).  One
-step = one mixlu_dxgesv call (equilibration, conversion, factorization,
-x_0, refinement to the stopping test, fallback when needed) with A and b
-already in HBM.  Prints one JSON line.
+Workloads (--workload; all inputs seeded, synthetic and already in HBM when
+the timed region starts; one step = one complete solve call):
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp32|fp16|bf16|fp64]
+  dense    (default) A = U diag(sigma) V^T, n = 16384, sigma geometric from 1
+           to 1/kappa, kappa = 1e4, U, V Haar, b = A x_true, one right-hand
+           side (seed 221); mixlu_dxgesv with an FP32 factor.
+  spd      A = Q diag(lambda) Q^T, n = 16384, lambda log-uniform in [1e-3, 1],
+           16 right-hand sides (seed 301); mixlu_dxposv (Cholesky).
+  batched  4096 systems, n_i uniform in [16, 512], kappa_i log-uniform in
+           [1e1, 1e5] (seed 401); mixlu_dxgesv_batched, one launch.
+  adjoint  n = 4096, 64 right-hand sides, kappa = 1e3 (seed 501); forward
+           solve + adjoint (G_B = A^-T G_X, G_A = -G_B X^T) with the same
+           factors.
+
+Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload dense|spd|batched|adjoint]
+                    [--prec fp32|fp16|bf16|fp64]
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -27,6 +38,9 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 PEAK_MFMA_TFS = {"fp16": 2500.0, "bf16": 2500.0, "fp8": 5000.0, "fp32": 157.3, "fp64": 78.6}
 PEAK_VALU_TFS = {"fp32": 78.6, "fp64": 78.6}
+METRIC = "time to FP64-accurate solve, mixed vs FP64 LU on 1 GPU; MFMA util"
+DTYPE = {"fp32": "f32", "fp16": "f16", "bf16": "bf16", "fp64": "f64"}
+DEFAULT_PREC = {"dense": "fp32", "spd": "fp16", "batched": "fp32", "adjoint": "fp16"}
 
 
 def parse():
@@ -34,74 +48,353 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=16384)
-    ap.add_argument("--kappa", type=float, default=1e4)
-    ap.add_argument("--seed", type=int, default=221)
-    ap.add_argument("--prec", default="fp32", choices=["fp32", "fp16", "bf16", "fp64"])
+    ap.add_argument("--workload", default="dense", choices=["dense", "spd", "batched", "adjoint"])
+    ap.add_argument("--prec", default=None, choices=["fp32", "fp16", "bf16", "fp64"])
+    ap.add_argument("--n", type=int, default=None)
+    ap.add_argument("--kappa", type=float, default=None)
+    ap.add_argument("--seed", type=int, default=None)
     ap.add_argument("--compare-steps", type=int, default=2, help="timed FP64 comparator runs")
-    ap.add_argument("--cpu-steps", type=int, default=400,
-                    help="elimination steps of the CPU oracle sample (0: skip)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="target wall time of the CPU oracle sample (0: skip)")
     return ap.parse_args()
 
 
-def time_calls(fn, k):
+def sync():
     import torch
 
     torch.cuda.synchronize()
+
+
+def time_calls(fn, k):
+    sync()
     t0 = time.perf_counter()
     out = None
     for _ in range(k):
         out = fn()
-    torch.cuda.synchronize()
+    sync()
     return (time.perf_counter() - t0) / k * 1e3, out
 
 
-def roofline(kstats, prec):
+def source_digest():
+    """Digest of the kernel sources, to tie stored counter readings to them."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_0808_2794_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(workload, kernel_class):
+    """HBM bytes per launch of the dominant kernel from the rocprofv3 PMC
+    readings kept in profiles/traffic.json, only if they were taken on the
+    current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f).get(workload, {}).get(kernel_class)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("source_digest") != source_digest():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def roofline(kstats, prec, steps, workload):
     """Roofline record of the kernel class with the largest device time."""
     name, st = max(kstats.items(), key=lambda kv: kv[1]["ms"])
     if st["launches"] == 0 or st["ms"] <= 0:
-        return None, name
+        return None
     sec = st["ms"] / 1e3
     wprec = "fp64" if prec == "fp64" else "fp32"
     if name == "trailing_update":
-        peak = PEAK_MFMA_TFS["fp64" if prec == "fp64" else prec]
-        rec = {"bound": "mfma", "achieved": st["flops"] / sec / 1e12, "peak": peak,
-               "unit": "TFLOP/s"}
+        rec = {"bound": "mfma", "achieved": st["flops"] / sec / 1e12,
+               "peak": PEAK_MFMA_TFS[prec], "unit": "TFLOP/s"}
     elif name in ("trsv", "residual", "pack_operands"):
         rec = {"bound": "hbm", "achieved": st["bytes"] / sec / 1e9, "peak": PEAK_HBM_GBS,
                "unit": "GB/s"}
-    else:  # the panel: dependent per-column steps on the vector ALUs
+    else:  # panels and the batched kernel: dependent steps on the vector ALUs
         rec = {"bound": "alu", "achieved": st["flops"] / sec / 1e12, "peak": PEAK_VALU_TFS[wprec],
                "unit": "TFLOP/s"}
     rec["frac"] = rec["achieved"] / rec["peak"]
-    rec["traffic"] = None
+    rec["traffic"] = stored_traffic(workload, name)
     rec["kernel"] = name
-    rec["launches_per_step"] = None
+    rec["launches_per_step"] = st["launches"] / steps
     rec["avg_launch_us"] = st["ms"] / st["launches"] * 1e3
-    return rec, name
+    return rec
 
 
-def cpu_baseline(A_host, b_host, steps):
-    """The CPU oracle (plain FP64 Gaussian elimination with partial pivoting)
-    timed on a bounded sample: the first `steps` elimination steps on the
-    same n x n matrix, scaled by the exact ratio of elimination work."""
+def kernel_table(kst, steps):
+    return {k: {"ms_per_step": v["ms"] / steps, "launches_per_step": v["launches"] / steps}
+            for k, v in kst.items() if v["launches"]}
+
+
+def threads():
+    return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+
+def cpu_getrf_sample(A_host, target_s, label):
+    """The CPU oracle's FP64 elimination on the same matrix, stopped after as
+    many steps as fit the time budget, scaled by the exact ratio of
+    elimination work (sum over steps of (n-k-1)^2 + (n-k-1))."""
     import numpy as np
 
     from oracle import oracle as O
 
     n = A_host.shape[0]
+    k = np.arange(n, dtype=np.float64)
+    work = (n - k - 1.0) ** 2 + (n - k - 1.0)
+    cum = np.cumsum(work)
+    steps = 8
     t0 = time.perf_counter()
     O.getrf(A_host, steps=steps)
     dt = time.perf_counter() - t0
-    k = np.arange(n, dtype=np.float64)
-    work = (n - k - 1.0) ** 2 + (n - k - 1.0)
-    frac = work[:steps].sum() / work.sum()
-    projected_ms = dt / frac * 1e3
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": projected_ms, "unit": "ms", "cores": threads, "kind": "oracle",
-            "sample": f"first {steps} of {n} elimination steps of the FP64 oracle on the same "
-                      f"matrix ({dt:.1f} s wall), scaled by the exact elimination-work ratio "
-                      f"{1/frac:.1f}; refinement (O(n^2) per iteration) not included"}
+    steps = int(np.clip(np.searchsorted(cum, cum[steps - 1] * target_s / max(dt, 1e-3)), 8, n))
+    t0 = time.perf_counter()
+    O.getrf(A_host, steps=steps)
+    dt = time.perf_counter() - t0
+    frac = cum[steps - 1] / cum[-1]
+    return {"value": dt / frac * 1e3, "unit": "ms", "cores": threads(), "kind": "oracle",
+            "sample": f"{label}: first {steps} of {n} elimination steps of the FP64 oracle "
+                      f"({dt:.1f} s wall), scaled by the exact elimination-work ratio "
+                      f"{1 / frac:.1f}; refinement (O(n^2) per iteration) not included"}
+
+
+def comparator_speedup(comp, ms):
+    vals = [v for k, v in comp.items() if k.endswith("_ms")]
+    if vals:
+        comp["speedup_vs_fastest_fp64"] = min(vals) / ms
+    return comp
+
+
+# --------------------------------------------------------------- workloads
+def run_dense(args, prec):
+    import numpy as np
+    import torch
+
+    from paper_0808_2794_amd import mixlu
+    from synth import gen
+
+    n = args.n or 16384
+    kappa = args.kappa or 1e4
+    seed = args.seed or 221
+    A, b, x_true = gen.prescribed_cond_system(n, kappa, seed, backend="torch", device="cuda")
+    A, b = A.contiguous(), b.contiguous()
+    sync()
+    solver = mixlu.Solver()
+    for _ in range(args.warmup):
+        solver.dxgesv(A, b, prec)
+    mixlu.mixlu_profile_enable(solver.ctx, True)
+    ms, res = time_calls(lambda: solver.dxgesv(A, b, prec), args.steps)
+    kst = mixlu.mixlu_profile_read(solver.ctx)
+    mixlu.mixlu_profile_enable(solver.ctx, False)
+    x = res.x.double().cpu().numpy()
+    fwd = float(np.abs(x - x_true).max() / np.abs(x_true).max())
+    comp = {}
+    if args.compare_steps > 0:
+        solver.dgesv(A, b)
+        comp["mixlu_dgesv_ms"], _ = time_calls(lambda: solver.dgesv(A, b), args.compare_steps)
+        torch.linalg.solve(A, b)
+        comp["torch_linalg_solve_fp64_ms"], _ = time_calls(lambda: torch.linalg.solve(A, b),
+                                                          args.compare_steps)
+        comparator_speedup(comp, ms)
+    cpu = cpu_getrf_sample(A.cpu().numpy(), args.cpu_seconds, "same matrix") \
+        if args.cpu_seconds > 0 else None
+    solver.close()
+    rep = res.report
+    return ms, kst, cpu, comp, {
+        "config": {"workload": f"dense_nonsym_prescribed_cond_n{n}_kappa{kappa:g}_nrhs1",
+                   "n": n, "kappa": kappa, "nrhs": 1, "seed": seed, "factor_precision": prec,
+                   "refinement": "fp64"},
+        "solve": {"iter": rep["iter"], "prec_used": rep["prec"], "converged": rep["converged"],
+                  "berr": rep["berr"], "fwd_err_vs_x_true": fwd}}
+
+
+def run_spd(args, prec):
+    import numpy as np
+    import torch
+
+    from oracle import oracle as O
+    from paper_0808_2794_amd import mixlu
+    from synth import gen
+
+    n = args.n or 16384
+    kappa = args.kappa or 1e3
+    seed = args.seed or 301
+    nrhs = 16
+    A, B, X_true = gen.spd_system(n, kappa, seed, nrhs=nrhs, backend="torch", device="cuda")
+    A, B = A.contiguous(), B.contiguous()
+    sync()
+    solver = mixlu.Solver()
+    for _ in range(args.warmup):
+        solver.dxposv(A, B, prec)
+    mixlu.mixlu_profile_enable(solver.ctx, True)
+    ms, res = time_calls(lambda: solver.dxposv(A, B, prec), args.steps)
+    kst = mixlu.mixlu_profile_read(solver.ctx)
+    mixlu.mixlu_profile_enable(solver.ctx, False)
+    X = res.x.cpu().numpy()
+    fwd = float(np.abs(X - X_true).max() / np.abs(X_true).max())
+    comp = {}
+    if args.compare_steps > 0:
+        solver.dposv(A, B)
+        comp["mixlu_dposv_ms"], _ = time_calls(lambda: solver.dposv(A, B), args.compare_steps)
+
+        def torch_chol():
+            L = torch.linalg.cholesky(A)
+            return torch.cholesky_solve(B, L)
+
+        torch_chol()
+        comp["torch_cholesky_solve_fp64_ms"], _ = time_calls(torch_chol, args.compare_steps)
+        comparator_speedup(comp, ms)
+    cpu = None
+    if args.cpu_seconds > 0:
+        # the oracle's Cholesky on a leading principal block sized to the
+        # budget, scaled by the cube of the order ratio
+        A_host = A.cpu().numpy()
+        m = 1024
+        t0 = time.perf_counter()
+        O.potrf(A_host[:m, :m])
+        dt = time.perf_counter() - t0
+        m = int(min(n, m * (args.cpu_seconds / max(dt, 1e-3)) ** (1 / 3)))
+        t0 = time.perf_counter()
+        O.potrf(A_host[:m, :m])
+        dt = time.perf_counter() - t0
+        scale = (n / m) ** 3
+        cpu = {"value": dt * scale * 1e3, "unit": "ms", "cores": threads(), "kind": "oracle",
+               "sample": f"FP64 oracle Cholesky of the leading {m} x {m} block of the same "
+                         f"matrix ({dt:.1f} s wall), scaled by (n/m)^3 = {scale:.1f}; "
+                         "solves and refinement not included"}
+    solver.close()
+    rep = res.report
+    return ms, kst, cpu, comp, {
+        "config": {"workload": f"dense_spd_n{n}_kappa{kappa:g}_nrhs{nrhs}", "n": n, "kappa": kappa,
+                   "nrhs": nrhs, "seed": seed, "factor_precision": prec, "factorization": "cholesky",
+                   "refinement": "fp64"},
+        "solve": {"iter": rep["iter"], "prec_used": rep["prec"], "converged": rep["converged"],
+                  "berr": rep["berr"], "fwd_err_vs_x_true": fwd}}
+
+
+def run_batched(args, prec):
+    import numpy as np
+    import torch
+
+    from oracle import oracle as O
+    from paper_0808_2794_amd import mixlu
+    from synth import gen
+
+    seed = args.seed or 401
+    count = 4096
+    As, bs, xs, ks = gen.batched_systems(count, seed)
+    solver = mixlu.Solver()
+    dA = [torch.from_numpy(a).cuda() for a in As]
+    dB = [torch.from_numpy(b).cuda() for b in bs]
+    buf = solver.batched_buffers(dA, dB, prec)
+    sync()
+    for _ in range(args.warmup):
+        solver.run_batched(buf)
+    mixlu.mixlu_profile_enable(solver.ctx, True)
+    ms, _ = time_calls(lambda: solver.run_batched(buf), args.steps)
+    kst = mixlu.mixlu_profile_read(solver.ctx)
+    mixlu.mixlu_profile_enable(solver.ctx, False)
+    # algorithmic LU work of the batch, charged to the batched kernel class
+    flops = sum(2.0 / 3.0 * a.shape[0] ** 3 for a in As)
+    kst["batched_solve"]["flops"] = flops * args.steps
+    reps = mixlu.reports_from_bytes(bytes(buf["reps"].cpu().numpy()))
+    conv = sum(1 for r in reps if r["converged"])
+    fb = sum(1 for r in reps if r["prec"] == "fp64" and prec != "fp64")
+    fwd = max(float(np.abs(X.cpu().numpy() - x).max() / np.abs(x).max())
+              for X, x in zip(buf["X"], xs))
+    comp = {}
+    if args.compare_steps > 0:
+        buf64 = solver.batched_buffers(dA, dB, "fp64")
+        solver.run_batched(buf64)
+        comp["mixlu_batched_fp64_ms"], _ = time_calls(lambda: solver.run_batched(buf64),
+                                                      args.compare_steps)
+
+        def torch_loop():
+            for a, b in zip(dA, dB):
+                torch.linalg.solve(a, b)
+
+        torch_loop()
+        comp["torch_linalg_solve_fp64_loop_ms"], _ = time_calls(torch_loop, 1)
+        comparator_speedup(comp, ms)
+    cpu = None
+    if args.cpu_seconds > 0:
+        t0 = time.perf_counter()
+        done, work_done = 0, 0.0
+        while done < count and time.perf_counter() - t0 < args.cpu_seconds:
+            O.gesv_ir(As[done], bs[done])
+            work_done += As[done].shape[0] ** 3
+            done += 1
+        dt = time.perf_counter() - t0
+        total = sum(a.shape[0] ** 3 for a in As)
+        cpu = {"value": dt * total / work_done * 1e3, "unit": "ms", "cores": threads(),
+               "kind": "oracle",
+               "sample": f"FP64 oracle solve (GE + refinement) of the first {done} of {count} "
+                         f"systems ({dt:.1f} s wall), scaled by sum n^3 of the batch / sum n^3 "
+                         "of the sample"}
+    solver.close()
+    return ms, kst, cpu, comp, {
+        "config": {"workload": f"batched_{count}_systems_n16to512_kappa1e1to1e5_nrhs1",
+                   "systems": count, "sum_n3": float(sum(a.shape[0] ** 3 for a in As)),
+                   "seed": seed, "factor_precision": prec, "refinement": "fp64"},
+        "solve": {"converged": conv, "systems": count, "fp64_fallbacks": fb,
+                  "max_fwd_err_vs_x_true": fwd}}
+
+
+def run_adjoint(args, prec):
+    import numpy as np
+    import torch
+
+    from paper_0808_2794_amd import mixlu
+    from paper_0808_2794_amd.autograd import solve
+    from synth import gen
+
+    n = args.n or 4096
+    kappa = args.kappa or 1e3
+    seed = args.seed or 501
+    nrhs = 64
+    A_h, B_h, W_h = gen.grad_problem(n, nrhs, kappa, seed, backend="torch", device="cuda")
+    A0 = torch.from_numpy(A_h).cuda()
+    B0 = torch.from_numpy(B_h).cuda()
+    Wt = torch.from_numpy(W_h).cuda()
+    solver = mixlu.Solver()
+
+    def step():
+        A = A0.detach().requires_grad_(True)
+        B = B0.detach().requires_grad_(True)
+        X = solve(A, B, prec, solver)
+        (X * Wt).sum().backward()
+        return X, A.grad, B.grad
+
+    for _ in range(args.warmup):
+        step()
+    mixlu.mixlu_profile_enable(solver.ctx, True)
+    ms, (X, GA, GB) = time_calls(step, args.steps)
+    kst = mixlu.mixlu_profile_read(solver.ctx)
+    mixlu.mixlu_profile_enable(solver.ctx, False)
+    comp = {}
+    if args.compare_steps > 0:
+        def torch_step():
+            A = A0.detach().requires_grad_(True)
+            B = B0.detach().requires_grad_(True)
+            (torch.linalg.solve(A, B) * Wt).sum().backward()
+            return A.grad, B.grad
+
+        GA_ref, GB_ref = torch_step()
+        comp["torch_linalg_solve_fp64_autograd_ms"], _ = time_calls(torch_step, args.compare_steps)
+        comparator_speedup(comp, ms)
+        comp["rel_diff_GB_vs_torch_fp64"] = float((GB - GB_ref).abs().max() / GB_ref.abs().max())
+        comp["rel_diff_GA_vs_torch_fp64"] = float((GA - GA_ref).abs().max() / GA_ref.abs().max())
+    cpu = cpu_getrf_sample(A_h, args.cpu_seconds, "the forward matrix") \
+        if args.cpu_seconds > 0 else None
+    solver.close()
+    return ms, kst, cpu, comp, {
+        "config": {"workload": f"differentiable_solve_n{n}_nrhs{nrhs}_kappa{kappa:g}", "n": n,
+                   "nrhs": nrhs, "kappa": kappa, "seed": seed, "factor_precision": prec,
+                   "refinement": "fp64", "passes": "forward+adjoint"},
+        "solve": {}}
 
 
 def main():
@@ -110,55 +403,16 @@ def main():
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU layout is described in the design notes)", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
 
-    from paper_0808_2794_amd import mixlu
-    from synth import gen
-
     torch.cuda.set_device(0)
-    n, kappa = args.n, args.kappa
-    A, b, x_true = gen.prescribed_cond_system(n, kappa, args.seed, backend="torch", device="cuda")
-    A = A.contiguous()
-    b = b.contiguous()
-    torch.cuda.synchronize()
-    solver = mixlu.Solver()
-
-    # ---- mixed-precision solve: warmup, then K timed steps with kernel timing on
-    for _ in range(args.warmup):
-        solver.dxgesv(A, b, args.prec)
-    mixlu.mixlu_profile_enable(solver.ctx, True)
-    ms, res = time_calls(lambda: solver.dxgesv(A, b, args.prec), args.steps)
-    kst = mixlu.mixlu_profile_read(solver.ctx)
-    mixlu.mixlu_profile_enable(solver.ctx, False)
-    rep = res.report
-    x = res.x.double().cpu().numpy()
-    fwd = float(np.abs(x - x_true).max() / np.abs(x_true).max())
-
-    # ---- FP64 LU on the same GPU: ours (mixlu_dgesv) and torch.linalg.solve
-    comp = {}
-    if args.compare_steps > 0:
-        solver.dgesv(A, b)
-        comp["mixlu_dgesv_ms"], _ = time_calls(lambda: solver.dgesv(A, b), args.compare_steps)
-        torch.linalg.solve(A, b)
-        comp["torch_linalg_solve_fp64_ms"], _ = time_calls(lambda: torch.linalg.solve(A, b),
-                                                          args.compare_steps)
-        best = min(comp.values())
-        comp["speedup_vs_fastest_fp64"] = best / ms
-    rl, dom = roofline(kst, args.prec)
-    if rl is not None:
-        rl["launches_per_step"] = kst[dom]["launches"] / args.steps
-    kernels = {k: {"ms_per_step": v["ms"] / args.steps, "launches_per_step": v["launches"] / args.steps}
-               for k, v in kst.items() if v["launches"]}
-
-    cpu = None
-    if args.cpu_steps > 0:
-        A_host = A.cpu().numpy()
-        cpu = cpu_baseline(A_host, b.cpu().numpy(), args.cpu_steps)
-        del A_host
-
+    prec = args.prec or DEFAULT_PREC[args.workload]
+    fn = {"dense": run_dense, "spd": run_spd, "batched": run_batched,
+          "adjoint": run_adjoint}[args.workload]
+    ms, kst, cpu, comp, extra = fn(args, prec)
+    rl = roofline(kst, prec, args.steps, args.workload)
     line = {
-        "metric": "time to FP64-accurate solve, mixed vs FP64 LU on 1 GPU; MFMA util",
+        "metric": METRIC,
         "value": ms,
         "unit": "ms",
         "n_gpus": 1,
@@ -168,20 +422,16 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "fp16": "f16", "bf16": "bf16", "fp64": "f64"}[args.prec] + "+f64",
+        "dtype": DTYPE[prec] + "+f64",
         "data": "synthetic",
-        "config": {"workload": f"dense_nonsym_prescribed_cond_n{n}_kappa{kappa:g}_nrhs1",
-                   "n": n, "kappa": kappa, "nrhs": 1, "seed": args.seed,
-                   "factor_precision": args.prec, "refinement": "fp64"},
-        "solve": {"iter": rep["iter"], "prec_used": rep["prec"], "converged": rep["converged"],
-                  "berr": rep["berr"], "fwd_err_vs_x_true": fwd},
+        "config": extra["config"],
+        "solve": extra["solve"],
         "comparators": comp,
-        "kernels": kernels,
+        "kernels": kernel_table(kst, args.steps),
         "roofline": rl,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
-    solver.close()
 
 
 if __name__ == "__main__":

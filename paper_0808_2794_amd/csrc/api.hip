@@ -173,11 +173,11 @@ size_t mixlu::plan_layout(Layout &L, int op, int prec, int n, int nrhs, const mi
     L.Bp = take(pk);
     L.ipiv = take(np * 4);
     L.perm = take(np * 4);
-    L.perm2 = take(np * 4);
     L.R = take(np * 8);
     L.C = take(np * 8);
     L.vec_r = take(np * L.nrhs * 8);
     L.vec_y = take(np * L.nrhs * 8);
+    L.vec_z = L.nrhs > 1 ? take(np * L.nrhs * 8) : L.vec_y;
     L.xbuf = take((size_t)kXbufWords * 8);
     L.ybuf = take((np * kTrsvNRT * 2 + 64) * 8);
     L.moves = take((size_t)(4 + 2 * 1024) * 4);
@@ -201,7 +201,7 @@ void fill_factor(mixlu_factor *F, const Layout &L, void *work, size_t lwork, int
     F->nrhs_max = L.nrhs;
     F->work = work;
     F->lwork = lwork;
-    const size_t offs[16] = {L.W, L.W64, L.Ap, L.Bp, L.ipiv, L.perm, L.perm2, L.R,
+    const size_t offs[16] = {L.W, L.W64, L.Ap, L.Bp, L.ipiv, L.perm, L.vec_z, L.R,
                              L.C, L.vec_r, L.vec_y, L.xbuf, L.ybuf, L.moves, L.tmp, L.status};
     std::memcpy(F->off, offs, sizeof(offs));
 }
@@ -222,7 +222,7 @@ Layout layout_of(const mixlu_factor *F) {
     L.Bp = F->off[3];
     L.ipiv = F->off[4];
     L.perm = F->off[5];
-    L.perm2 = F->off[6];
+    L.vec_z = F->off[6];
     L.R = F->off[7];
     L.C = F->off[8];
     L.vec_r = F->off[9];
@@ -440,16 +440,28 @@ int lu_solve(hipStream_t s, void *work, const Layout &L, size_t woff, int nrhs,
     const double *R = at<double>(work, L.R), *C = at<double>(work, L.C);
     HIPCK(launch_rhs_gather<Tw>(n, np, nrhs, rhs, ldr, rhs_cm, trans ? nullptr : perm,
                                 trans ? C : R, Y, nrhs, s));
-    for (int c0 = 0; c0 < nrhs; c0 += kTrsvNRT) {
-        const int nc = nrhs - c0 < kTrsvNRT ? nrhs - c0 : kTrsvNRT;
-        const double tb = 0.5 * np * (np + 64.0) * sizeof(Tw) + 2.0 * np * nc * sizeof(Tw);
+    if (nrhs == 1) {
+        // one right-hand side: the chained single-launch solve (latency bound)
+        const double tb = 0.5 * np * (np + 64.0) * sizeof(Tw) + 2.0 * np * sizeof(Tw);
         {
-            ProfScope ps(PC_TRSV, (double)np * np * nc, tb, s);
-            HIPCK(launch_trsv<Tw>(0, trans, W, np, np, Y + c0, nrhs, nc, ybuf, status, s));
+            ProfScope ps(PC_TRSV, (double)np * np, tb, s);
+            HIPCK(launch_trsv<Tw>(0, trans, W, np, np, Y, 1, 1, ybuf, status, s));
         }
         {
-            ProfScope ps(PC_TRSV, (double)np * np * nc, tb, s);
-            HIPCK(launch_trsv<Tw>(1, trans, W, np, np, Y + c0, nrhs, nc, ybuf, status, s));
+            ProfScope ps(PC_TRSV, (double)np * np, tb, s);
+            HIPCK(launch_trsv<Tw>(1, trans, W, np, np, Y, 1, 1, ybuf, status, s));
+        }
+    } else {
+        // several: diagonal blocks one column per thread plus GEMM updates
+        const double tb = 0.5 * np * (np + 64.0) * sizeof(Tw) + 2.0 * np * nrhs * sizeof(Tw);
+        Tw *Z = at<Tw>(work, L.vec_z);
+        {
+            ProfScope ps(PC_TRSV, (double)np * np * nrhs, tb, s);
+            HIPCK(launch_trsm_blocked<Tw>(0, trans, W, np, np, Y, Z, nrhs, nrhs, s));
+        }
+        {
+            ProfScope ps(PC_TRSV, (double)np * np * nrhs, tb, s);
+            HIPCK(launch_trsm_blocked<Tw>(1, trans, W, np, np, Z, Y, nrhs, nrhs, s));
         }
     }
     HIPCK(launch_fill_f64(xnorm, 0.0, nrhs, s));
@@ -488,7 +500,10 @@ int refine_loop(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t woff, cons
         {
             ProfScope ps(PC_RESID, 2.0 * n * n * nrhs,
                          8.0 * n * n + 8.0 * n * nrhs * 3.0, s);
-            if (trans)
+            if (nrhs > 1)
+                HIPCK(launch_residual_mm(n, nrhs, A, lda, trans, X, ldx, B, ldb, cm, Rv, nrhs,
+                                         rnorm, xnorm, s));
+            else if (trans)
                 HIPCK(launch_residual_t(n, nrhs, A, lda, X, ldx, B, ldb, cm, Rv, nrhs, rnorm,
                                         xnorm, at<double>(work, L.tmp), s));
             else

@@ -196,10 +196,11 @@ struct Layout {
     size_t W;        // working factor: npad x npad, float (or double when prec = FP64)
     size_t W64;      // FP64 fallback factor (npad x npad double) or 0
     size_t Ap, Bp;   // packed low-precision GEMM operands
-    size_t ipiv, perm, perm2;     // int[npad] each
+    size_t ipiv, perm;            // int[npad] each
     size_t R, C;     // double[npad] scales
     size_t vec_r;    // double[npad * nrhs] residual
     size_t vec_y;    // double[npad * nrhs] solve vector (float or double view)
+    size_t vec_z;    // double[npad * nrhs] second solve vector (blocked solves)
     size_t xbuf;     // panel exchange words
     size_t ybuf;     // chained-solve exchange words + tickets
     size_t moves;    // int[2 * (2 * nb + 64) + 4] row-move lists
@@ -241,7 +242,7 @@ template <typename T>
 hipError_t launch_trsm_diag(const T *Ldiag, int ldl, T *X, int ldx, int ncols, hipStream_t s);
 template <typename T>
 hipError_t launch_gemm(int M, int N, int K, const T *A, int lda, const T *B, int ldb, T *C,
-                       int ldc, hipStream_t s, int transb = 0, int lower = 0);
+                       int ldc, hipStream_t s, int transb = 0, int lower = 0, int transa = 0);
 hipError_t launch_pack(int prec, const float *W, int ldw, int rows, int cols, int transpose,
                        void *dst, int *status, hipStream_t s);
 hipError_t launch_gemm_lowp(int prec, int M, int N, int K, const void *Ap, const void *Bp,
@@ -276,6 +277,18 @@ hipError_t launch_x_update(int n, int npad, int nrhs, int assign, const Tw *Y, i
 hipError_t launch_residual(int n, int nrhs, const double *A, int lda, const double *X, int ldx,
                            const double *B, int ldb, int bx_col_major, double *Rv, int ldr,
                            double *rnorm, double *xnorm, hipStream_t s);
+// Blocked triangular solve for several right-hand sides (same matrices as
+// launch_trsv): one launch per 64-row block, each solving the diagonal block
+// (one wave per right-hand side) and updating the remaining rows of Y; the
+// solution is written to Yout (Y is consumed).
+template <typename Tw>
+hipError_t launch_trsm_blocked(int upper, int trans, const Tw *W, int ldw, int npad, Tw *Y,
+                               Tw *Yout, int ldy, int nrhs, hipStream_t s);
+// R = B - op(A) X for several right-hand sides on FP64 MFMA, with the
+// column norms of R and X (rnorm, xnorm zeroed by the caller)
+hipError_t launch_residual_mm(int n, int nrhs, const double *A, int lda, int transa,
+                              const double *X, int ldx, const double *B, int ldb, int cm,
+                              double *Rv, int ldr, double *rnorm, double *xnorm, hipStream_t s);
 // part: scratch of 16 * n * 8 doubles
 hipError_t launch_residual_t(int n, int nrhs, const double *A, int lda, const double *X, int ldx,
                              const double *B, int ldb, int bx_col_major, double *Rv, int ldr,

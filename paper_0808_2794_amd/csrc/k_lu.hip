@@ -469,9 +469,11 @@ template <> struct Mfma<double> {
 // 64x64 output tile per workgroup, 4 waves of 32x32, K step 16.
 // 16x16x4 operand layout: lane l supplies A[l%16][l/16] and B[l/16][l%16].
 // TB: B is given transposed (Bm is N x K row-major, as L21 for the Cholesky
-// update C -= L21 L21^T).  lower != 0: only tiles that touch the lower
-// triangle (col <= row) of C are computed.
-template <typename T, bool TB>
+// update C -= L21 L21^T).  TA: A is given transposed (A is K x M row-major,
+// as the off-diagonal blocks of the transposed triangular solves).
+// lower != 0: only tiles that touch the lower triangle (col <= row) of C
+// are computed.
+template <typename T, bool TB, bool TA = false>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const T *__restrict__ A, int lda,
                                               const T *__restrict__ Bm, int ldb, T *__restrict__ C,
                                               int ldc, int lower) {
@@ -489,7 +491,15 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const T *__re
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
     for (int k0 = 0; k0 < K; k0 += BK) {
-        {
+        if constexpr (TA) {
+            const int kk = tid >> 4, r = (tid & 15) * 4;
+            const int gk = k0 + kk;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int gr = m0 + r + q;
+                sA[kk][r + q] = (gk < K && gr < M) ? A[(size_t)gk * lda + gr] : (T)0;
+            }
+        } else {
             const int r = tid >> 2, kk = (tid & 3) * 4;
             const int gr = m0 + r;
 #pragma unroll
@@ -544,19 +554,23 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const T *__re
 
 template <typename T>
 hipError_t launch_gemm(int M, int N, int K, const T *A, int lda, const T *B, int ldb, T *C,
-                       int ldc, hipStream_t s, int transb, int lower) {
+                       int ldc, hipStream_t s, int transb, int lower, int transa) {
     if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
     const dim3 grid((N + 63) / 64, (M + 63) / 64);
-    if (transb)
+    if (transa && transb)
+        k_gemm<T, true, true><<<grid, dim3(256), 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc, lower);
+    else if (transa)
+        k_gemm<T, false, true><<<grid, dim3(256), 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc, lower);
+    else if (transb)
         k_gemm<T, true><<<grid, dim3(256), 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc, lower);
     else
         k_gemm<T, false><<<grid, dim3(256), 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc, lower);
     return hipGetLastError();
 }
 template hipError_t launch_gemm<float>(int, int, int, const float *, int, const float *, int,
-                                       float *, int, hipStream_t, int, int);
+                                       float *, int, hipStream_t, int, int, int);
 template hipError_t launch_gemm<double>(int, int, int, const double *, int, const double *, int,
-                                        double *, int, hipStream_t, int, int);
+                                        double *, int, hipStream_t, int, int, int);
 
 // ======================================================================
 // Low-precision trailing update

@@ -292,6 +292,116 @@ template hipError_t launch_trsv<float>(int, int, const float *, int, int, float 
 template hipError_t launch_trsv<double>(int, int, const double *, int, int, double *, int, int,
                                         unsigned long long *, int *, hipStream_t);
 
+// One step of the blocked solve for several right-hand sides: workgroup
+// (x, y) takes the four columns 4y .. 4y+3 (one wave each).  Every
+// workgroup solves the 64 x 64 diagonal block at j0 for its columns (the
+// block's rows in registers, values shared with readlane); workgroup x = 0
+// stores the solved rows in Yout (never in Y, whose block rows the other
+// workgroups of the launch may still be reading), and workgroup x = 1 + t
+// updates the 64-row tile t of the rows still to be solved, in place in Y:
+// Y[rows] -= M[rows, j0:j0+64] Yj.  MODE 0: unit lower L, forward; 1: U,
+// backward; 2: U^T (lower, non-unit), forward; 3: L^T (unit upper),
+// backward.  The triangular matrix is M[r][c] = W[r][c] (modes 0, 1) or
+// W[c][r] (modes 2, 3).  Rows to update: j0+64 .. npad-1 (forward) or
+// 0 .. j0-1 (backward).
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void k_trsm_step(const T *__restrict__ W, int ldw, int j0,
+                                                   int npad, T *__restrict__ Y,
+                                                   T *__restrict__ Yout, int ldy, int nrhs) {
+    constexpr int BS = kTrsvBS;
+    constexpr bool TR = MODE >= 2;
+    constexpr bool FWD = MODE == 0 || MODE == 2;
+    constexpr bool UNIT = MODE == 0 || MODE == 3;
+    __shared__ T sd[BS][BS + 1];
+    __shared__ T sy[BS][4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int col = blockIdx.y * 4 + wave;
+    for (int e = tid; e < BS * BS; e += 256) {
+        const int r = e / BS, c = e % BS;
+        const T v = W[(size_t)(j0 + r) * ldw + j0 + c];
+        if (TR) sd[c][r] = v;
+        else sd[r][c] = v;
+    }
+    __syncthreads();
+    if (col < nrhs) {
+        T mrow[BS];
+#pragma unroll
+        for (int k = 0; k < BS; ++k) mrow[k] = sd[lane][k];
+        T y = Y[(size_t)(j0 + lane) * ldy + col];
+        if constexpr (FWD) {
+#pragma unroll
+            for (int k = 0; k < BS; ++k) {
+                if constexpr (!UNIT) {
+                    const T yk = readlane_t(y, k) / readlane_t(mrow[k], k);
+                    if (lane == k) y = yk;
+                    else if (lane > k) y -= mrow[k] * yk;
+                } else {
+                    const T yk = readlane_t(y, k);
+                    if (lane > k) y -= mrow[k] * yk;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = BS - 1; k >= 0; --k) {
+                if constexpr (!UNIT) {
+                    const T yk = readlane_t(y, k) / readlane_t(mrow[k], k);
+                    if (lane == k) y = yk;
+                    else if (lane < k) y -= mrow[k] * yk;
+                } else {
+                    const T yk = readlane_t(y, k);
+                    if (lane < k) y -= mrow[k] * yk;
+                }
+            }
+        }
+        sy[lane][wave] = y;
+        if (blockIdx.x == 0) Yout[(size_t)(j0 + lane) * ldy + col] = y;
+    }
+    if (blockIdx.x == 0) return;
+    __syncthreads();
+    // tile update: thread (row, wave) = (row, column)
+    const int t = blockIdx.x - 1;
+    const int r0 = FWD ? j0 + BS + t * BS : t * BS;
+    const int row = r0 + lane;
+    const int rows_end = FWD ? npad : j0;
+    if (row >= rows_end || col >= nrhs) return;
+    T acc = (T)0;
+#pragma unroll
+    for (int k = 0; k < BS; ++k) {
+        const T m = TR ? W[(size_t)(j0 + k) * ldw + row] : W[(size_t)row * ldw + j0 + k];
+        acc += m * sy[k][wave];
+    }
+    Y[(size_t)row * ldy + col] -= acc;
+}
+
+template <typename Tw>
+hipError_t launch_trsm_blocked(int upper, int trans, const Tw *W, int ldw, int npad, Tw *Y,
+                               Tw *Yout, int ldy, int nrhs, hipStream_t s) {
+    constexpr int BS = kTrsvBS;
+    if (npad == 0 || nrhs == 0) return hipSuccess;
+    if (npad % BS) return hipErrorInvalidValue;
+    const int nblk = npad / BS;
+    const int mode = trans ? (upper ? 3 : 2) : (upper ? 1 : 0);
+    for (int t = 0; t < nblk; ++t) {
+        const int b = upper ? nblk - 1 - t : t;
+        const int tiles = upper ? b : nblk - 1 - b;
+        const dim3 grid(1 + tiles, (nrhs + 3) / 4);
+        const int j0 = b * BS;
+        switch (mode) {
+            case 0: k_trsm_step<Tw, 0><<<grid, 256, 0, s>>>(W, ldw, j0, npad, Y, Yout, ldy, nrhs); break;
+            case 1: k_trsm_step<Tw, 1><<<grid, 256, 0, s>>>(W, ldw, j0, npad, Y, Yout, ldy, nrhs); break;
+            case 2: k_trsm_step<Tw, 2><<<grid, 256, 0, s>>>(W, ldw, j0, npad, Y, Yout, ldy, nrhs); break;
+            default: k_trsm_step<Tw, 3><<<grid, 256, 0, s>>>(W, ldw, j0, npad, Y, Yout, ldy, nrhs); break;
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+template hipError_t launch_trsm_blocked<float>(int, int, const float *, int, int, float *,
+                                               float *, int, int, hipStream_t);
+template hipError_t launch_trsm_blocked<double>(int, int, const double *, int, int, double *,
+                                                double *, int, int, hipStream_t);
+
 // Row i of the solve vector z goes to row d = perm[i] of X (perm = NULL: the
 // identity; the transposed solve scatters through P^T): X[d] = S[d] z[i]
 // (assign) or X[d] += S[d] z[i], z promoted to FP64, for d < n;
@@ -577,6 +687,58 @@ hipError_t launch_residual_t(int n, int nrhs, const double *A, int lda, const do
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+// Several right-hand sides: R = B - op(A) X as a copy of B followed by an
+// FP64 MFMA GEMM (k_gemm<double>), then the per-column norms of R and X.
+__global__ __launch_bounds__(256) void k_copy_rhs(int n, int nrhs, const double *__restrict__ B,
+                                                  int ldb, int cm, double *__restrict__ R,
+                                                  int ldr) {
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (size_t)n * nrhs) return;
+    const int i = (int)(e / nrhs), c = (int)(e % nrhs);
+    R[(size_t)i * ldr + c] = cm ? B[i + (size_t)c * ldb] : B[(size_t)i * ldb + c];
+}
+
+// rnorm[c] = max_i |R[i][c]|, xnorm[c] = max_i |X[i][c]| (both zeroed by the
+// caller): 256 rows per workgroup, one wave reduction per column.
+__global__ __launch_bounds__(256) void k_col_norms(int n, int nrhs, const double *__restrict__ R,
+                                                   int ldr, const double *__restrict__ X, int ldx,
+                                                   int x_cm, double *__restrict__ rnorm,
+                                                   double *__restrict__ xnorm) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    for (int c = 0; c < nrhs; ++c) {
+        double r = 0.0, x = 0.0;
+        if (i < n) {
+            r = fabs(R[(size_t)i * ldr + c]);
+            x = fabs(x_cm ? X[i + (size_t)c * ldx] : X[(size_t)i * ldx + c]);
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            r = nanmax(r, __shfl_xor(r, off));
+            x = nanmax(x, __shfl_xor(x, off));
+        }
+        if ((threadIdx.x & 63) == 0) {
+            atomic_max_nonneg(&rnorm[c], r);
+            atomic_max_nonneg(&xnorm[c], x);
+        }
+    }
+}
+
+hipError_t launch_residual_mm(int n, int nrhs, const double *A, int lda, int transa,
+                              const double *X, int ldx, const double *B, int ldb, int cm,
+                              double *Rv, int ldr, double *rnorm, double *xnorm, hipStream_t s) {
+    if (n == 0 || nrhs == 0) return hipSuccess;
+    const size_t cnt = (size_t)n * nrhs;
+    k_copy_rhs<<<dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s>>>(n, nrhs, B, ldb, cm, Rv,
+                                                                         ldr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // column-major X is the row-major nrhs x n matrix X^T: the "B transposed" form
+    e = launch_gemm<double>(n, nrhs, n, A, lda, X, ldx, Rv, ldr, s, cm, 0, transa);
+    if (e != hipSuccess) return e;
+    k_col_norms<<<dim3((n + 255) / 256), dim3(256), 0, s>>>(n, nrhs, Rv, ldr, X, ldx, cm, rnorm,
+                                                            xnorm);
+    return hipGetLastError();
 }
 
 // GA = beta GA + alpha G X^T (all row-major FP64; G, X are n x nrhs).
