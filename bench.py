@@ -40,7 +40,7 @@ PEAK_MFMA_TFS = {"fp16": 2500.0, "bf16": 2500.0, "fp8": 5000.0, "fp32": 157.3, "
 PEAK_VALU_TFS = {"fp32": 78.6, "fp64": 78.6}
 METRIC = "time to FP64-accurate solve, mixed vs FP64 LU on 1 GPU; MFMA util"
 DTYPE = {"fp32": "f32", "fp16": "f16", "bf16": "bf16", "fp64": "f64"}
-DEFAULT_PREC = {"dense": "fp32", "spd": "fp16", "batched": "fp32", "adjoint": "fp16"}
+DEFAULT_PREC = {"dense": "fp32", "spd": "fp16", "batched": "fp32", "adjoint": "fp32"}
 
 
 def parse():
@@ -361,11 +361,19 @@ def run_adjoint(args, prec):
     Wt = torch.from_numpy(W_h).cuda()
     solver = mixlu.Solver()
 
+    reports = {}
+
     def step():
+        from paper_0808_2794_amd.autograd import MixedSolve
+
         A = A0.detach().requires_grad_(True)
         B = B0.detach().requires_grad_(True)
         X = solve(A, B, prec, solver)
         (X * Wt).sum().backward()
+        node = X.grad_fn
+        if isinstance(node, torch.autograd.function.BackwardCFunction):
+            reports["forward"] = getattr(node, "report", None)
+            reports["adjoint"] = getattr(node, "backward_report", None)
         return X, A.grad, B.grad
 
     for _ in range(args.warmup):
@@ -394,7 +402,8 @@ def run_adjoint(args, prec):
         "config": {"workload": f"differentiable_solve_n{n}_nrhs{nrhs}_kappa{kappa:g}", "n": n,
                    "nrhs": nrhs, "kappa": kappa, "seed": seed, "factor_precision": prec,
                    "refinement": "fp64", "passes": "forward+adjoint"},
-        "solve": {}}
+        "solve": {k: ({"iter": v["iter"], "prec_used": v["prec"], "converged": v["converged"],
+                       "berr": v["berr"]} if v else None) for k, v in reports.items()}}
 
 
 def main():

@@ -42,6 +42,8 @@ struct Prof {
 struct mixlu_ctx_s {
     int device = 0;
     hipStream_t stream = nullptr;
+    hipStream_t side = nullptr;  // look-ahead: trailing updates overlapped with panels
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     double *hbuf = nullptr;  // pinned host mirror of the norms / status
     size_t hbuf_bytes = 0;
     Prof prof;
@@ -86,6 +88,16 @@ int ensure_hbuf(mixlu_ctx_s *ctx, size_t bytes) {
     ctx->hbuf_bytes = 0;
     HIPCK(hipHostMalloc(reinterpret_cast<void **>(&ctx->hbuf), bytes, hipHostMallocDefault));
     ctx->hbuf_bytes = bytes;
+    return MIXLU_OK;
+}
+
+// Second stream (default priority) and the two events that order it with
+// the context's stream, created on first use.
+int ensure_side(mixlu_ctx_s *ctx) {
+    if (ctx->side) return MIXLU_OK;
+    HIPCK(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+    HIPCK(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
+    HIPCK(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
     return MIXLU_OK;
 }
 
@@ -168,9 +180,11 @@ size_t mixlu::plan_layout(Layout &L, int op, int prec, int n, int nrhs, const mi
     };
     L.W = take(wbytes);
     L.W64 = L.fallback ? take(np * np * 8) : 0;
+    // packed trailing-update operands, two sets (look-ahead: the next block
+    // packs while the previous block's update still reads its set)
     const size_t pk = is_lowp(L.prec) ? np * L.nb * 2 : 0;
-    L.Ap = take(pk);
-    L.Bp = take(pk);
+    L.Ap = take(2 * pk);
+    L.Bp = take(2 * pk);
     L.ipiv = take(np * 4);
     L.perm = take(np * 4);
     L.R = take(np * 8);
@@ -244,8 +258,9 @@ Layout layout_of(const mixlu_factor *F) {
 // interchanges on the other columns, U12 = L11^{-1} A12 and the trailing
 // update A22 -= L21 U12 (in FP32/FP64, or with BF16/FP16 operands on MFMA).
 template <typename T>
-int factor_lu(hipStream_t s, void *work, const Layout &L, size_t woff, int trail_prec) {
+int factor_lu(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t woff, int trail_prec) {
     constexpr int B = sizeof(T) == 4 ? kPanelBF : kPanelBD;
+    hipStream_t s = ctx->stream;
     const int np = L.npad, nb = L.nb;
     T *W = at<T>(work, woff);
     int *ipiv = at<int>(work, L.ipiv);
@@ -254,11 +269,18 @@ int factor_lu(hipStream_t s, void *work, const Layout &L, size_t woff, int trail
     int *status = at<int>(work, L.status);
     auto *xbuf = at<unsigned long long>(work, L.xbuf);
     if (nb % B || nb % 64 || nb > 512) return MIXLU_ERR_NOT_IMPLEMENTED;
+    RETCK(ensure_side(ctx));
+    hipStream_t s2 = ctx->side;
     HIPCK(launch_iota(perm, np, s));
     HIPCK(launch_fill_u32(reinterpret_cast<unsigned *>(xbuf), 0u, (size_t)kXbufWords * 2, s));
     auto Wp = [&](int r, int c) { return W + (size_t)r * np + c; };
+    const size_t pk = (size_t)np * nb;  // elements of one packed operand set
+    bool side_busy = false;             // the side stream holds an update of W
+    int par = 0;
     for (int K0 = 0; K0 < np; K0 += nb) {
         const int kend = K0 + nb;
+        // panels of this block: only columns K0..kend-1, which the previous
+        // block updated first, so they overlap the rest of its update
         for (int k = K0; k < kend; k += B) {
             {
                 const double m = np - k;
@@ -275,37 +297,76 @@ int factor_lu(hipStream_t s, void *work, const Layout &L, size_t woff, int trail
                                      np, Wp(k + B, k + B), np, s));
             }
         }
+        // the interchanges reach every other column: the side stream's update
+        // of the previous block must be complete
+        if (side_busy) {
+            HIPCK(hipStreamWaitEvent(s, ctx->ev_join, 0));
+            side_busy = false;
+        }
         HIPCK(launch_perm_build(ipiv, K0, nb, np, nullptr, moves, s));
         HIPCK(launch_rows_move<T>(W, np, np, moves, 2 * nb, 0, np, K0, kend, s));
-        if (kend < np) {
-            const int nr = np - kend;
-            for (int ib = 0; ib < nb; ib += B) {
-                HIPCK(launch_trsm_diag<T>(Wp(K0 + ib, K0 + ib), np, Wp(K0 + ib, kend), np, nr, s));
-                if (ib + B < nb)
-                    HIPCK(launch_gemm<T>(nb - ib - B, nr, B, Wp(K0 + ib + B, K0 + ib), np,
-                                         Wp(K0 + ib, kend), np, Wp(K0 + ib + B, kend), np, s));
-            }
-            if (trail_prec == MIXLU_FP64 || trail_prec == MIXLU_FP32) {
-                ProfScope ps(PC_TRAIL, 2.0 * nr * nr * nb,
-                             (2.0 * nr * nr + 2.0 * nr * nb) * sizeof(T), s);
-                HIPCK(launch_gemm<T>(nr, nr, nb, Wp(kend, K0), np, Wp(K0, kend), np,
+        if (kend >= np) break;
+        const int nr = np - kend;
+        for (int ib = 0; ib < nb; ib += B) {
+            HIPCK(launch_trsm_diag<T>(Wp(K0 + ib, K0 + ib), np, Wp(K0 + ib, kend), np, nr, s));
+            if (ib + B < nb)
+                HIPCK(launch_gemm<T>(nb - ib - B, nr, B, Wp(K0 + ib + B, K0 + ib), np,
+                                     Wp(K0 + ib, kend), np, Wp(K0 + ib + B, kend), np, s));
+        }
+        // trailing update: the next block's columns now (stream s), the rest
+        // on the side stream, overlapping the next block's panels
+        const int nx = nr < nb ? nr : nb;
+        const int rest = nr - nx;
+        if (trail_prec == MIXLU_FP64 || trail_prec == MIXLU_FP32) {
+            {
+                ProfScope ps(PC_TRAIL, 2.0 * nr * nx * nb, (2.0 * nr * nx + 1.0 * (nr + nx) * nb) * sizeof(T), s);
+                HIPCK(launch_gemm<T>(nr, nx, nb, Wp(kend, K0), np, Wp(K0, kend), np,
                                      Wp(kend, kend), np, s));
-            } else {
-                if constexpr (sizeof(T) == 4) {
-                    void *Ap = at<void>(work, L.Ap), *Bp = at<void>(work, L.Bp);
-                    {
-                        ProfScope ps(PC_PACK, 0.0, 2.0 * nr * nb * (4 + 2), s);
-                        HIPCK(launch_pack(trail_prec, Wp(kend, K0), np, nr, nb, 0, Ap, status, s));
-                        HIPCK(launch_pack(trail_prec, Wp(K0, kend), np, nb, nr, 1, Bp, status, s));
-                    }
-                    ProfScope ps(PC_TRAIL, 2.0 * nr * nr * nb, 8.0 * nr * nr + 4.0 * nr * nb, s);
-                    HIPCK(launch_gemm_lowp(trail_prec, nr, nr, nb, Ap, Bp, Wp(kend, kend), np, s));
-                } else {
-                    return MIXLU_ERR_NOT_IMPLEMENTED;
+            }
+            if (rest > 0) {
+                HIPCK(hipEventRecord(ctx->ev_fork, s));
+                HIPCK(hipStreamWaitEvent(s2, ctx->ev_fork, 0));
+                {
+                    ProfScope ps(PC_TRAIL, 2.0 * nr * rest * nb,
+                                 (2.0 * nr * rest + 1.0 * (nr + rest) * nb) * sizeof(T), s2);
+                    HIPCK(launch_gemm<T>(nr, rest, nb, Wp(kend, K0), np, Wp(K0, kend + nx), np,
+                                         Wp(kend, kend + nx), np, s2, 0, 0, 0, 1));
                 }
+                HIPCK(hipEventRecord(ctx->ev_join, s2));
+                side_busy = true;
+            }
+        } else {
+            if constexpr (sizeof(T) == 4) {
+                auto *Ap = at<unsigned short>(work, L.Ap) + par * pk;
+                auto *Bp = at<unsigned short>(work, L.Bp) + par * pk;
+                par ^= 1;
+                {
+                    ProfScope ps(PC_PACK, 0.0, 2.0 * nr * nb * (4 + 2), s);
+                    HIPCK(launch_pack(trail_prec, Wp(kend, K0), np, nr, nb, 0, Ap, status, s));
+                    HIPCK(launch_pack(trail_prec, Wp(K0, kend), np, nb, nr, 1, Bp, status, s));
+                }
+                {
+                    ProfScope ps(PC_TRAIL, 2.0 * nr * nx * nb, 8.0 * nr * nx + 2.0 * (nr + nx) * nb, s);
+                    HIPCK(launch_gemm_lowp(trail_prec, nr, nx, nb, Ap, Bp, Wp(kend, kend), np, s));
+                }
+                if (rest > 0) {
+                    HIPCK(hipEventRecord(ctx->ev_fork, s));
+                    HIPCK(hipStreamWaitEvent(s2, ctx->ev_fork, 0));
+                    {
+                        ProfScope ps(PC_TRAIL, 2.0 * nr * rest * nb,
+                                     8.0 * nr * rest + 2.0 * (nr + rest) * nb, s2);
+                        HIPCK(launch_gemm_lowp(trail_prec, nr, rest, nb, Ap, Bp + (size_t)nx * nb,
+                                               Wp(kend, kend + nx), np, s2, 0, 1));
+                    }
+                    HIPCK(hipEventRecord(ctx->ev_join, s2));
+                    side_busy = true;
+                }
+            } else {
+                return MIXLU_ERR_NOT_IMPLEMENTED;
             }
         }
     }
+    if (side_busy) HIPCK(hipStreamWaitEvent(s, ctx->ev_join, 0));
     return MIXLU_OK;
 }
 
@@ -419,7 +480,7 @@ int convert_and_factor(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t wof
     }
     HIPCK(launch_convert<T>(A, lda, n, np, R, C, at<T>(work, woff), np, status, s));
     if (L.kind == 1) return factor_chol<T>(s, work, L, woff, trail_prec);
-    return factor_lu<T>(s, work, L, woff, trail_prec);
+    return factor_lu<T>(ctx, work, L, woff, trail_prec);
 }
 
 // Low-precision solve with the factors of W = R M C, P W = L U:
@@ -783,6 +844,12 @@ int mixlu_create(mixlu_ctx_t *ctx, void *stream) {
 int mixlu_destroy(mixlu_ctx_t ctx) {
     if (!ctx) return -1;
     if (ctx->hbuf) (void)hipHostFree(ctx->hbuf);
+    if (ctx->side) {
+        (void)hipStreamSynchronize(ctx->side);
+        (void)hipStreamDestroy(ctx->side);
+        (void)hipEventDestroy(ctx->ev_fork);
+        (void)hipEventDestroy(ctx->ev_join);
+    }
     for (auto &q : ctx->prof.pending) {
         (void)hipEventDestroy(q.a);
         (void)hipEventDestroy(q.b);

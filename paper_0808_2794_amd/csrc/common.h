@@ -45,6 +45,17 @@ __device__ inline void xstore(unsigned long long *p, unsigned tag, unsigned payl
     __hip_atomic_store(p, ((unsigned long long)tag << 32) | payload, __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
 }
+// Store for readers on the same XCD only: a workgroup-scope store goes
+// through the compute unit's L1 into the XCD's L2, which every compute unit
+// of that XCD shares, and the readers' agent-scope loads (xload) find it
+// there.  Cheaper than an agent-scope store, which must become visible to
+// all XCDs; used only when every participating workgroup sits on one XCD
+// (the wait that reads it is bounded, so a broken placement ends in the
+// timeout status, not a hang).
+__device__ inline void xstore_near(unsigned long long *p, unsigned tag, unsigned payload) {
+    __hip_atomic_store(p, ((unsigned long long)tag << 32) | payload, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_WORKGROUP);
+}
 __device__ inline unsigned long long xload(const unsigned long long *p) {
     return __hip_atomic_load(const_cast<unsigned long long *>(p), __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
@@ -242,11 +253,12 @@ template <typename T>
 hipError_t launch_trsm_diag(const T *Ldiag, int ldl, T *X, int ldx, int ncols, hipStream_t s);
 template <typename T>
 hipError_t launch_gemm(int M, int N, int K, const T *A, int lda, const T *B, int ldb, T *C,
-                       int ldc, hipStream_t s, int transb = 0, int lower = 0, int transa = 0);
+                       int ldc, hipStream_t s, int transb = 0, int lower = 0, int transa = 0,
+                       int spare_xcd0 = 0);
 hipError_t launch_pack(int prec, const float *W, int ldw, int rows, int cols, int transpose,
                        void *dst, int *status, hipStream_t s);
 hipError_t launch_gemm_lowp(int prec, int M, int N, int K, const void *Ap, const void *Bp,
-                            float *C, int ldc, hipStream_t s, int lower = 0);
+                            float *C, int ldc, hipStream_t s, int lower = 0, int spare_xcd0 = 0);
 
 // a3.5: Cholesky variant (k_chol.hip)
 hipError_t launch_sym_scale(const double *A, int lda, int n, int npad, double *R, double *C,

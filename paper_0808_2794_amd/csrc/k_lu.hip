@@ -62,16 +62,25 @@ template <typename T, int B>
 __device__ __noinline__ ExchangeResult panel_exchange(unsigned long long *X, lds_u32 *words, int P,
                                                       int w, unsigned tag, unsigned h0,
                                                       unsigned h1, unsigned h2, unsigned rw,
-                                                      unsigned dw, int *timeout) {
+                                                      unsigned dw, int *timeout, int near) {
     using G = PanelGeom<T, B>;
     constexpr int TPB = kPanelTPB, PWV = G::PWV, HDR = G::HDR, SLOT = G::SLOT;
     constexpr int DIAG = kPanelMaxWG * SLOT;
     const int tid = threadIdx.x;
     unsigned long long *slot = X + (size_t)w * SLOT;
-    if (tid < HDR) xstore(slot + tid, tag, tid == 0 ? h0 : (tid == 1 ? h1 : (tid == 2 ? h2 : 0u)));
-    if (tid < B * PWV) {
-        xstore(slot + HDR + tid, tag, rw);
-        if (w == 0) xstore(X + DIAG + tid, tag, dw);
+    const unsigned hword = tid == 0 ? h0 : (tid == 1 ? h1 : (tid == 2 ? h2 : 0u));
+    if (near) {
+        if (tid < HDR) xstore_near(slot + tid, tag, hword);
+        if (tid < B * PWV) {
+            xstore_near(slot + HDR + tid, tag, rw);
+            if (w == 0) xstore_near(X + DIAG + tid, tag, dw);
+        }
+    } else {
+        if (tid < HDR) xstore(slot + tid, tag, hword);
+        if (tid < B * PWV) {
+            xstore(slot + HDR + tid, tag, rw);
+            if (w == 0) xstore(X + DIAG + tid, tag, dw);
+        }
     }
     bool bad = false;
     const int nslot = P * SLOT;
@@ -203,7 +212,7 @@ __global__ __launch_bounds__(kPanelTPB) void k_panel(T *__restrict__ W, int ldw,
                 xb + (size_t)par * PAR, (lds_u32 *)&s_words[par][0], P, w,
                 (unsigned)(k0 + j + 1), Words<T>::get(gmax, 0),
                 PWV > 1 ? Words<T>::get(gmax, PWV - 1) : 0u, (unsigned)p, rw, dw,
-                &status[ST_TIMEOUT]);
+                &status[ST_TIMEOUT], stride == kXcdStride);
             if (!ex.ok) {
                 dead = true;
                 return;
@@ -468,6 +477,27 @@ template <> struct Mfma<double> {
 
 // 64x64 output tile per workgroup, 4 waves of 32x32, K step 16.
 // 16x16x4 operand layout: lane l supplies A[l%16][l/16] and B[l/16][l%16].
+// Tile of a GEMM workgroup.  spare_xcd0 = 0: the 2-D grid position.
+// spare_xcd0 = 1: a 1-D grid whose workgroups b with b % 8 == 0 (dealt to
+// XCD 0 by the round-robin dispatch) do nothing, so that a panel kernel
+// running concurrently on XCD 0 keeps its compute units; the other
+// workgroups take the tiles in order.  Returns false for no tile.
+__device__ __forceinline__ bool tile_of(int spare_xcd0, int tiles_x, int tiles_y, int &tx, int &ty) {
+    if (!spare_xcd0) return true;
+    const int b = blockIdx.x;
+    if ((b & 7) == 0) return false;
+    const int t = (b >> 3) * 7 + (b & 7) - 1;
+    if (t >= tiles_x * tiles_y) return false;
+    ty = t / tiles_x;
+    tx = t - ty * tiles_x;
+    return true;
+}
+inline dim3 gemm_grid(int spare_xcd0, int tiles_x, int tiles_y) {
+    if (!spare_xcd0) return dim3(tiles_x, tiles_y);
+    const long t = (long)tiles_x * tiles_y;
+    return dim3((unsigned)((t + 6) / 7 * 8));
+}
+
 // TB: B is given transposed (Bm is N x K row-major, as L21 for the Cholesky
 // update C -= L21 L21^T).  TA: A is given transposed (A is K x M row-major,
 // as the off-diagonal blocks of the transposed triangular solves).
@@ -476,12 +506,14 @@ template <> struct Mfma<double> {
 template <typename T, bool TB, bool TA = false>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const T *__restrict__ A, int lda,
                                               const T *__restrict__ Bm, int ldb, T *__restrict__ C,
-                                              int ldc, int lower) {
+                                              int ldc, int lower, int spare_xcd0) {
     constexpr int BM = 64, BN = 64, BK = 16;
     __shared__ T sA[BK][BM + 4];
     __shared__ T sB[BK][BN + 4];
     using acc_t = typename Mfma<T>::acc_t;
-    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    int tx = blockIdx.x, ty = blockIdx.y;
+    if (!tile_of(spare_xcd0, (N + BN - 1) / BN, (M + BM - 1) / BM, tx, ty)) return;
+    const int m0 = ty * BM, n0 = tx * BN;
     if (lower && n0 > m0 + BM - 1) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
@@ -554,23 +586,27 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const T *__re
 
 template <typename T>
 hipError_t launch_gemm(int M, int N, int K, const T *A, int lda, const T *B, int ldb, T *C,
-                       int ldc, hipStream_t s, int transb, int lower, int transa) {
+                       int ldc, hipStream_t s, int transb, int lower, int transa, int spare_xcd0) {
     if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
-    const dim3 grid((N + 63) / 64, (M + 63) / 64);
+    const dim3 grid = gemm_grid(spare_xcd0, (N + 63) / 64, (M + 63) / 64);
     if (transa && transb)
-        k_gemm<T, true, true><<<grid, dim3(256), 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc, lower);
+        k_gemm<T, true, true><<<grid, dim3(256), 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc, lower,
+                                                         spare_xcd0);
     else if (transa)
-        k_gemm<T, false, true><<<grid, dim3(256), 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc, lower);
+        k_gemm<T, false, true><<<grid, dim3(256), 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc, lower,
+                                                          spare_xcd0);
     else if (transb)
-        k_gemm<T, true><<<grid, dim3(256), 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc, lower);
+        k_gemm<T, true><<<grid, dim3(256), 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc, lower,
+                                                   spare_xcd0);
     else
-        k_gemm<T, false><<<grid, dim3(256), 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc, lower);
+        k_gemm<T, false><<<grid, dim3(256), 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc, lower,
+                                                    spare_xcd0);
     return hipGetLastError();
 }
 template hipError_t launch_gemm<float>(int, int, int, const float *, int, const float *, int,
-                                       float *, int, hipStream_t, int, int, int);
+                                       float *, int, hipStream_t, int, int, int, int);
 template hipError_t launch_gemm<double>(int, int, int, const double *, int, const double *, int,
-                                        double *, int, hipStream_t, int, int, int);
+                                        double *, int, hipStream_t, int, int, int, int);
 
 // ======================================================================
 // Low-precision trailing update
@@ -665,12 +701,14 @@ hipError_t launch_pack(int prec, const float *W, int ldw, int rows, int cols, in
 template <typename H>
 __global__ __launch_bounds__(256) void k_gemm_lowp(int M, int N, int K, const H *__restrict__ Ap,
                                                    const H *__restrict__ Bp, float *__restrict__ C,
-                                                   int ldc, int lower) {
+                                                   int ldc, int lower, int spare_xcd0) {
     constexpr int BM = 128, BN = 128, BK = 64, PITCH = BK + 8;
     using vec_t = typename LowP<H>::vec_t;
     __shared__ __attribute__((aligned(16))) H sA[BM * PITCH];
     __shared__ __attribute__((aligned(16))) H sB[BN * PITCH];
-    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    int tx = blockIdx.x, ty = blockIdx.y;
+    if (!tile_of(spare_xcd0, (N + BN - 1) / BN, (M + BM - 1) / BM, tx, ty)) return;
+    const int m0 = ty * BM, n0 = tx * BN;
     if (lower && n0 > m0 + BM - 1) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
@@ -723,16 +761,16 @@ __global__ __launch_bounds__(256) void k_gemm_lowp(int M, int N, int K, const H 
 }
 
 hipError_t launch_gemm_lowp(int prec, int M, int N, int K, const void *Ap, const void *Bp,
-                            float *C, int ldc, hipStream_t s, int lower) {
+                            float *C, int ldc, hipStream_t s, int lower, int spare_xcd0) {
     if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
     if (K % 64) return hipErrorInvalidValue;
-    dim3 grid((N + 127) / 128, (M + 127) / 128);
+    const dim3 grid = gemm_grid(spare_xcd0, (N + 127) / 128, (M + 127) / 128);
     if (prec == MIXLU_FP16)
         k_gemm_lowp<_Float16><<<grid, dim3(256), 0, s>>>(M, N, K, (const _Float16 *)Ap,
-                                                         (const _Float16 *)Bp, C, ldc, lower);
+                                                         (const _Float16 *)Bp, C, ldc, lower, spare_xcd0);
     else if (prec == MIXLU_BF16)
         k_gemm_lowp<__bf16><<<grid, dim3(256), 0, s>>>(M, N, K, (const __bf16 *)Ap,
-                                                       (const __bf16 *)Bp, C, ldc, lower);
+                                                       (const __bf16 *)Bp, C, ldc, lower, spare_xcd0);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
