@@ -419,33 +419,34 @@ template hipError_t launch_rows_move<double>(double *, int, int, const int *, in
 // ======================================================================
 // X[0:DB, :] = L^{-1} X[0:DB, :] for the DB x DB unit lower L; one thread
 // per column of X, the block of L in LDS (read by broadcast).
+// X = L^{-1} X for the unit lower DB x DB diagonal block L (row-major, ld
+// ldl) and ncols columns of X: one wave per column, lane r holding row r of
+// L in registers; the solved value of row k reaches the other lanes by
+// readlane, so the DB dependent steps touch no memory.
 template <typename T, int DB>
-__global__ __launch_bounds__(64) void k_trsm_diag(const T *__restrict__ L, int ldl,
-                                                  T *__restrict__ X, int ldx, int ncols) {
-    __shared__ T sL[DB][DB + 1];
-    const int t = threadIdx.x;
-    for (int i = 0; i < DB; ++i)
-        for (int c = t; c < DB; c += 64) sL[i][c] = L[(size_t)i * ldl + c];
-    __syncthreads();
-    const int col = blockIdx.x * 64 + t;
+__global__ __launch_bounds__(256) void k_trsm_diag(const T *__restrict__ L, int ldl,
+                                                   T *__restrict__ X, int ldx, int ncols) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = blockIdx.x * 4 + wave;
     if (col >= ncols) return;
-    T x[DB];
+    const bool act = lane < DB;
+    T lrow[DB];
 #pragma unroll
-    for (int i = 0; i < DB; ++i) x[i] = X[(size_t)i * ldx + col];
+    for (int k = 0; k < DB; ++k) lrow[k] = (act && k < lane) ? L[(size_t)lane * ldl + k] : (T)0;
+    T x = act ? X[(size_t)lane * ldx + col] : (T)0;
 #pragma unroll
-    for (int k = 0; k < DB; ++k) {
-#pragma unroll
-        for (int i = k + 1; i < DB; ++i) x[i] -= sL[i][k] * x[k];
+    for (int k = 0; k < DB - 1; ++k) {
+        const T xk = readlane_t(x, k);
+        if (lane > k) x -= lrow[k] * xk;
     }
-#pragma unroll
-    for (int i = 0; i < DB; ++i) X[(size_t)i * ldx + col] = x[i];
+    if (act) X[(size_t)lane * ldx + col] = x;
 }
 
 template <typename T>
 hipError_t launch_trsm_diag(const T *Ldiag, int ldl, T *X, int ldx, int ncols, hipStream_t s) {
     if (ncols <= 0) return hipSuccess;
     constexpr int DB = PanelWidth<T>::v;
-    k_trsm_diag<T, DB><<<dim3((ncols + 63) / 64), dim3(64), 0, s>>>(Ldiag, ldl, X, ldx, ncols);
+    k_trsm_diag<T, DB><<<dim3((ncols + 3) / 4), dim3(256), 0, s>>>(Ldiag, ldl, X, ldx, ncols);
     return hipGetLastError();
 }
 template hipError_t launch_trsm_diag<float>(const float *, int, float *, int, int, hipStream_t);
@@ -584,10 +585,135 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const T *__re
             }
 }
 
+// Large-tile GEMM C -= A B (row-major, no transposes) for the big trailing
+// updates: 128 x 128 output tile per workgroup, 4 waves of 64 x 64 (4 x 4
+// MFMA 16x16x4 blocks each), K step BK with the next K slab prefetched into
+// registers while the current one is multiplied out of LDS.  LDS pitches
+// make the MFMA operand reads conflict-free: A is kept [m][k] with pitch
+// BK + 4, B [k][n] with pitch 128 + 16.
+template <typename T, int BK>
+__global__ __launch_bounds__(256) void k_gemm_big(int M, int N, int K, const T *__restrict__ A,
+                                                  int lda, const T *__restrict__ Bm, int ldb,
+                                                  T *__restrict__ C, int ldc, int lower,
+                                                  int spare_xcd0) {
+    constexpr int BM = 128, BN = 128, PA = BK + 4, PB = BN + 16;
+    constexpr int V = 16 / sizeof(T);                 // elements per 16-byte load
+    constexpr int NLA = BM * BK / V / 256;            // A vectors per thread per slab
+    constexpr int NLB = BK * BN / V / 256;            // B vectors per thread per slab
+    typedef T vec_t __attribute__((ext_vector_type(V)));
+    __shared__ __attribute__((aligned(16))) T sA[BM * PA];
+    __shared__ __attribute__((aligned(16))) T sB[BK * PB];
+    using acc_t = typename Mfma<T>::acc_t;
+    int tx = blockIdx.x, ty = blockIdx.y;
+    if (!tile_of(spare_xcd0, (N + BN - 1) / BN, (M + BM - 1) / BM, tx, ty)) return;
+    const int m0 = ty * BM, n0 = tx * BN;
+    if (lower && n0 > m0 + BM - 1) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    acc_t acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+    vec_t ra[NLA], rb[NLB];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < NLA; ++q) {
+            const int e = tid + q * 256;            // vector index in the BM x BK slab
+            const int r = e / (BK / V), kv = (e % (BK / V)) * V;
+            const int gr = m0 + r;
+            if (gr < M && k0 + kv + V <= K) {
+                ra[q] = *reinterpret_cast<const vec_t *>(A + (size_t)gr * lda + k0 + kv);
+            } else {
+#pragma unroll
+                for (int t = 0; t < V; ++t)
+                    ra[q][t] = (gr < M && k0 + kv + t < K) ? A[(size_t)gr * lda + k0 + kv + t] : (T)0;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NLB; ++q) {
+            const int e = tid + q * 256;            // vector index in the BK x BN slab
+            const int kr = e / (BN / V), nv = (e % (BN / V)) * V;
+            const int gk = k0 + kr, gc = n0 + nv;
+            if (gk < K && gc + V <= N) {
+                rb[q] = *reinterpret_cast<const vec_t *>(Bm + (size_t)gk * ldb + gc);
+            } else {
+#pragma unroll
+                for (int t = 0; t < V; ++t)
+                    rb[q][t] = (gk < K && gc + t < N) ? Bm[(size_t)gk * ldb + gc + t] : (T)0;
+            }
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int q = 0; q < NLA; ++q) {
+            const int e = tid + q * 256;
+            const int r = e / (BK / V), kv = (e % (BK / V)) * V;
+            *reinterpret_cast<vec_t *>(&sA[r * PA + kv]) = ra[q];
+        }
+#pragma unroll
+        for (int q = 0; q < NLB; ++q) {
+            const int e = tid + q * 256;
+            const int kr = e / (BN / V), nv = (e % (BN / V)) * V;
+            *reinterpret_cast<vec_t *>(&sB[kr * PB + nv]) = rb[q];
+        }
+    };
+    // A, B row-major with 16-byte aligned rows are required for the vector
+    // loads; the launcher checks lda, ldb and the base pointers
+    load(0);
+    store();
+    __syncthreads();
+    for (int k0 = 0; k0 < K; k0 += BK) {
+        const bool more = k0 + BK < K;
+        if (more) load(k0 + BK);
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+            const int kr = kk + (lane >> 4);
+            T a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = sA[(wm * 64 + i * 16 + (lane & 15)) * PA + kr];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = sB[kr * PB + wn * 64 + j * 16 + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = Mfma<T>::mac(a[i], b[j], acc[i][j]);
+        }
+        __syncthreads();
+        if (more) {
+            store();
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = m0 + wm * 64 + i * 16 + Mfma<T>::row(lane, v);
+                const int col = n0 + wn * 64 + j * 16 + (lane & 15);
+                if (row < M && col < N) C[(size_t)row * ldc + col] -= acc[i][j][v];
+            }
+}
+
 template <typename T>
 hipError_t launch_gemm(int M, int N, int K, const T *A, int lda, const T *B, int ldb, T *C,
                        int ldc, hipStream_t s, int transb, int lower, int transa, int spare_xcd0) {
     if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
+    constexpr int V = 16 / sizeof(T);
+    const bool aligned = lda % V == 0 && ldb % V == 0 &&
+                         (reinterpret_cast<uintptr_t>(A) & 15) == 0 &&
+                         (reinterpret_cast<uintptr_t>(B) & 15) == 0;
+    if constexpr (sizeof(T) == 4) {
+        // (for FP64 the 64 x 64 kernel below measured faster)
+        if (!transa && !transb && aligned && M >= 256 && N >= 256) {
+            const dim3 g = gemm_grid(spare_xcd0, (N + 127) / 128, (M + 127) / 128);
+            k_gemm_big<T, 32><<<g, dim3(256), 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc, lower,
+                                                      spare_xcd0);
+            return hipGetLastError();
+        }
+    }
     const dim3 grid = gemm_grid(spare_xcd0, (N + 63) / 64, (M + 63) / 64);
     if (transa && transb)
         k_gemm<T, true, true><<<grid, dim3(256), 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc, lower,
