@@ -66,7 +66,9 @@ typedef enum {
     MIXLU_FP32 = 1,
     MIXLU_BF16 = 2,
     MIXLU_FP16 = 3,
-    MIXLU_FP8 = 4 /* OCP e4m3, power-of-two per-tile scales */
+    MIXLU_FP8 = 4 /* OCP E4M3 operands with one E8M0 (power-of-two) scale
+                     per 32 consecutive K values of each L21 row and U12
+                     column, on the scaled 16x16x128 MFMA (nb >= 128) */
 } mixlu_prec;
 
 typedef enum { MIXLU_ROW_MAJOR = 0, MIXLU_COL_MAJOR = 1 } mixlu_layout;

@@ -72,9 +72,10 @@ int auto_nb(int n) {
     return 512;
 }
 
-bool is_lowp(int prec) { return prec == MIXLU_BF16 || prec == MIXLU_FP16; }
+bool is_lowp(int prec) { return prec == MIXLU_BF16 || prec == MIXLU_FP16 || prec == MIXLU_FP8; }
 bool prec_valid(int prec) {
-    return prec == MIXLU_FP64 || prec == MIXLU_FP32 || prec == MIXLU_BF16 || prec == MIXLU_FP16;
+    return prec == MIXLU_FP64 || prec == MIXLU_FP32 || prec == MIXLU_BF16 ||
+           prec == MIXLU_FP16 || prec == MIXLU_FP8;
 }
 
 template <typename T> T *at(void *work, size_t off) {
@@ -168,6 +169,8 @@ size_t mixlu::plan_layout(Layout &L, int op, int prec, int n, int nrhs, const mi
     L.prec = (op == MIXLU_OP_DGESV || op == MIXLU_OP_DPOSV) ? MIXLU_FP64 : prec;
     L.kind = (op == MIXLU_OP_POSV || op == MIXLU_OP_DPOSV) ? 1 : 0;
     L.nb = o.nb > 0 ? o.nb : auto_nb(n);
+    // the FP8 update multiplies K in steps of 128
+    if (L.prec == MIXLU_FP8 && L.nb < 128) L.nb = 128;
     L.npad = round_up(n > 0 ? n : 1, L.nb);
     L.fallback = (L.prec != MIXLU_FP64) && o.fallback;
     const size_t np = (size_t)L.npad;
@@ -337,27 +340,42 @@ int factor_lu(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t woff, int tr
             }
         } else {
             if constexpr (sizeof(T) == 4) {
-                auto *Ap = at<unsigned short>(work, L.Ap) + par * pk;
-                auto *Bp = at<unsigned short>(work, L.Bp) + par * pk;
+                // one packed set: 2 * pk bytes for A (L21) and for B (U12)
+                auto *Ap = at<unsigned char>(work, L.Ap) + par * pk * 2;
+                auto *Bp = at<unsigned char>(work, L.Bp) + par * pk * 2;
                 par ^= 1;
+                const bool f8 = trail_prec == MIXLU_FP8;
+                // FP8: codes then one scale byte per 32 codes
+                auto *As = Ap + pk, *Bs = Bp + pk;
+                const int esz = f8 ? 1 : 2;
                 {
-                    ProfScope ps(PC_PACK, 0.0, 2.0 * nr * nb * (4 + 2), s);
-                    HIPCK(launch_pack(trail_prec, Wp(kend, K0), np, nr, nb, 0, Ap, status, s));
-                    HIPCK(launch_pack(trail_prec, Wp(K0, kend), np, nb, nr, 1, Bp, status, s));
+                    ProfScope ps(PC_PACK, 0.0, 1.0 * nr * nb * (4 + esz) * 2, s);
+                    if (f8) {
+                        HIPCK(launch_pack_fp8(Wp(kend, K0), np, nr, nb, 0, Ap, As, status, s));
+                        HIPCK(launch_pack_fp8(Wp(K0, kend), np, nr, nb, 1, Bp, Bs, status, s));
+                    } else {
+                        HIPCK(launch_pack(trail_prec, Wp(kend, K0), np, nr, nb, 0, Ap, status, s));
+                        HIPCK(launch_pack(trail_prec, Wp(K0, kend), np, nb, nr, 1, Bp, status, s));
+                    }
                 }
-                {
-                    ProfScope ps(PC_TRAIL, 2.0 * nr * nx * nb, 8.0 * nr * nx + 2.0 * (nr + nx) * nb, s);
-                    HIPCK(launch_gemm_lowp(trail_prec, nr, nx, nb, Ap, Bp, Wp(kend, kend), np, s));
-                }
+                auto update = [&](int ncol, int c0, hipStream_t st, int spare) -> int {
+                    ProfScope ps(PC_TRAIL, 2.0 * nr * ncol * nb,
+                                 8.0 * nr * ncol + 1.0 * esz * (nr + ncol) * nb, st);
+                    if (f8)
+                        HIPCK(launch_gemm_fp8(nr, ncol, nb, Ap, As, Bp + (size_t)c0 * nb,
+                                              Bs + (size_t)c0 * (nb / 32), Wp(kend, kend + c0), np,
+                                              st, 0, spare));
+                    else
+                        HIPCK(launch_gemm_lowp(trail_prec, nr, ncol, nb, Ap,
+                                               Bp + (size_t)c0 * nb * 2, Wp(kend, kend + c0), np,
+                                               st, 0, spare));
+                    return MIXLU_OK;
+                };
+                RETCK(update(nx, 0, s, 0));
                 if (rest > 0) {
                     HIPCK(hipEventRecord(ctx->ev_fork, s));
                     HIPCK(hipStreamWaitEvent(s2, ctx->ev_fork, 0));
-                    {
-                        ProfScope ps(PC_TRAIL, 2.0 * nr * rest * nb,
-                                     8.0 * nr * rest + 2.0 * (nr + rest) * nb, s2);
-                        HIPCK(launch_gemm_lowp(trail_prec, nr, rest, nb, Ap, Bp + (size_t)nx * nb,
-                                               Wp(kend, kend + nx), np, s2, 0, 1));
-                    }
+                    RETCK(update(rest, nx, s2, 1));
                     HIPCK(hipEventRecord(ctx->ev_join, s2));
                     side_busy = true;
                 }
@@ -410,14 +428,22 @@ int factor_chol(hipStream_t s, void *work, const Layout &L, size_t woff, int tra
                                      Wp(kend, kend), np, s, 1, 1));
             } else {
                 if constexpr (sizeof(T) == 4) {
-                    void *Ap = at<void>(work, L.Ap);
+                    auto *Ap = at<unsigned char>(work, L.Ap);
+                    auto *As = Ap + (size_t)np * nb;
+                    const bool f8 = trail_prec == MIXLU_FP8;
                     {
-                        ProfScope ps(PC_PACK, 0.0, 1.0 * nr * nb * (4 + 2), s);
-                        HIPCK(launch_pack(trail_prec, Wp(kend, K0), np, nr, nb, 0, Ap, status, s));
+                        ProfScope ps(PC_PACK, 0.0, 1.0 * nr * nb * (4 + (f8 ? 1 : 2)), s);
+                        if (f8)
+                            HIPCK(launch_pack_fp8(Wp(kend, K0), np, nr, nb, 0, Ap, As, status, s));
+                        else
+                            HIPCK(launch_pack(trail_prec, Wp(kend, K0), np, nr, nb, 0, Ap, status, s));
                     }
                     ProfScope ps(PC_TRAIL, 1.0 * nr * (nr + 1.0) * nb,
-                                 4.0 * nr * (nr + 1.0) + 2.0 * nr * nb, s);
-                    HIPCK(launch_gemm_lowp(trail_prec, nr, nr, nb, Ap, Ap, Wp(kend, kend), np, s, 1));
+                                 4.0 * nr * (nr + 1.0) + (f8 ? 1.0 : 2.0) * nr * nb, s);
+                    if (f8)
+                        HIPCK(launch_gemm_fp8(nr, nr, nb, Ap, As, Ap, As, Wp(kend, kend), np, s, 1));
+                    else
+                        HIPCK(launch_gemm_lowp(trail_prec, nr, nr, nb, Ap, Ap, Wp(kend, kend), np, s, 1));
                 } else {
                     return MIXLU_ERR_NOT_IMPLEMENTED;
                 }

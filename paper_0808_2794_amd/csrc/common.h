@@ -260,6 +260,13 @@ hipError_t launch_pack(int prec, const float *W, int ldw, int rows, int cols, in
 hipError_t launch_gemm_lowp(int prec, int M, int N, int K, const void *Ap, const void *Bp,
                             float *C, int ldc, hipStream_t s, int lower = 0, int spare_xcd0 = 0);
 
+// FP8 (E4M3 codes with one E8M0 scale per 32 K values) operands and update
+hipError_t launch_pack_fp8(const float *W, int ldw, int rows, int K, int transpose, void *codes,
+                           void *scales, int *status, hipStream_t s);
+hipError_t launch_gemm_fp8(int M, int N, int K, const void *Ac, const void *As, const void *Bc,
+                           const void *Bs, float *C, int ldc, hipStream_t s, int lower = 0,
+                           int spare_xcd0 = 0);
+
 // a3.5: Cholesky variant (k_chol.hip)
 hipError_t launch_sym_scale(const double *A, int lda, int n, int npad, double *R, double *C,
                             int equil, hipStream_t s);

@@ -14,6 +14,8 @@
 #include <climits>
 #include <type_traits>
 
+#include <hip/hip_fp8.h>
+
 #include "common.h"
 
 namespace mixlu {
@@ -899,6 +901,185 @@ hipError_t launch_gemm_lowp(int prec, int M, int N, int K, const void *Ap, const
                                                        (const __bf16 *)Bp, C, ldc, lower, spare_xcd0);
     else
         return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// ======================================================================
+// FP8 trailing update: OCP E4M3 operands with one E8M0 (power-of-two) scale
+// per 32 consecutive K values of a row of L21 / a column of U12, multiplied
+// on the gfx950 scaled MFMA (16x16x128, FP32 accumulate).
+// ======================================================================
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+
+// E4M3 (OCP, finite saturating) code of x, round to nearest even.
+__device__ __forceinline__ unsigned char to_e4m3(float x) {
+    return (unsigned char)__hip_cvt_float_to_fp8(x, __HIP_SATFINITE, __HIP_E4M3);
+}
+
+// Pack 32 values sharing one scale: the scale exponent e puts the block's
+// largest magnitude below 2^8 (E4M3 reaches 448), the E8M0 byte is e + 127.
+// Returns the scale byte; writes the 32 codes to out.  A non-finite value
+// counts as an overflow.
+__device__ __forceinline__ unsigned char pack_block32(const float (&v)[32], unsigned char *out,
+                                                      int &bad) {
+    float amax = 0.0f;
+#pragma unroll
+    for (int t = 0; t < 32; ++t) amax = fmaxf(amax, fabsf(v[t]));
+    int e = -127;
+    if (!(amax <= 3.40282347e38f)) {
+        ++bad;
+        e = 0;
+    } else if (amax > 0.0f) {
+        e = ilogbf(amax) - 7;
+        e = e < -127 ? -127 : (e > 127 ? 127 : e);
+    }
+    const float inv = ldexpf(1.0f, -e);
+#pragma unroll
+    for (int t = 0; t < 32; ++t) out[t] = to_e4m3(v[t] * inv);
+    return (unsigned char)(e + 127);
+}
+
+// rows x K row-major FP32 (ld ldw) -> codes[rows][K], scales[rows][K/32].
+// transpose = 1: the operand is the K x cols matrix W (U12) and its columns
+// are packed: codes[col][K], scales[col][K/32].  One thread per 32-value block.
+__global__ __launch_bounds__(256) void k_pack_fp8(const float *__restrict__ W, int ldw, int rows,
+                                                  int K, int transpose,
+                                                  unsigned char *__restrict__ codes,
+                                                  unsigned char *__restrict__ scales,
+                                                  int *__restrict__ status) {
+    const int kb = K / 32;
+    const long blk = (long)blockIdx.x * 256 + threadIdx.x;
+    if (blk >= (long)rows * kb) return;
+    int r, b;
+    if (transpose) {  // consecutive threads take consecutive columns (coalesced rows of W)
+        b = (int)(blk / rows);
+        r = (int)(blk % rows);
+    } else {
+        r = (int)(blk / kb);
+        b = (int)(blk % kb);
+    }
+    float v[32];
+#pragma unroll
+    for (int t = 0; t < 32; ++t)
+        v[t] = transpose ? W[(size_t)(b * 32 + t) * ldw + r] : W[(size_t)r * ldw + b * 32 + t];
+    int bad = 0;
+    unsigned char c[32];
+    const unsigned char s = pack_block32(v, c, bad);
+    uint4 *dst = reinterpret_cast<uint4 *>(codes + (size_t)r * K + b * 32);
+    dst[0] = *reinterpret_cast<const uint4 *>(&c[0]);
+    dst[1] = *reinterpret_cast<const uint4 *>(&c[16]);
+    scales[(size_t)r * kb + b] = s;
+    if (bad) atomicAdd(&status[ST_OVERFLOW], bad);
+}
+
+hipError_t launch_pack_fp8(const float *W, int ldw, int rows, int K, int transpose, void *codes,
+                           void *scales, int *status, hipStream_t s) {
+    if (rows <= 0 || K <= 0) return hipSuccess;
+    if (K % 32) return hipErrorInvalidValue;
+    const long nblk = (long)rows * (K / 32);
+    k_pack_fp8<<<dim3((unsigned)((nblk + 255) / 256)), dim3(256), 0, s>>>(
+        W, ldw, rows, K, transpose, static_cast<unsigned char *>(codes),
+        static_cast<unsigned char *>(scales), status);
+    return hipGetLastError();
+}
+
+// C[M x N] -= A B^T with A = codes/scales of M rows, B of N rows (both K
+// codes per row, K % 128 == 0).  128 x 128 tile, 4 waves of 64 x 64 (4 x 4
+// scaled MFMA blocks), K step 128.  Operand layout of the 16x16x128 scaled
+// MFMA: lane (r = l % 16, g = l / 16) supplies K values 16g .. 16g+15 and
+// 64+16g .. 64+16g+15 of its row and the scale of K block g (32 values).
+__global__ __launch_bounds__(256) void k_gemm_fp8(int M, int N, int K,
+                                                  const unsigned char *__restrict__ Ac,
+                                                  const unsigned char *__restrict__ As,
+                                                  const unsigned char *__restrict__ Bc,
+                                                  const unsigned char *__restrict__ Bs,
+                                                  float *__restrict__ C, int ldc, int lower,
+                                                  int spare_xcd0) {
+    constexpr int BM = 128, BN = 128, BK = 128, PITCH = BK + 16;
+    __shared__ __attribute__((aligned(16))) unsigned char sA[BM * PITCH];
+    __shared__ __attribute__((aligned(16))) unsigned char sB[BN * PITCH];
+    __shared__ unsigned char ssA[BM * 4], ssB[BN * 4];
+    int tx = blockIdx.x, ty = blockIdx.y;
+    if (!tile_of(spare_xcd0, (N + BN - 1) / BN, (M + BM - 1) / BM, tx, ty)) return;
+    const int m0 = ty * BM, n0 = tx * BN;
+    if (lower && n0 > m0 + BM - 1) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int kb = K / 32;
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
+    for (int k0 = 0; k0 < K; k0 += BK) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = tid + q * 256;  // 16-byte vector index in a 128 x 128-byte slab
+            const int row = e >> 3, seg = e & 7;
+            uint4 va = make_uint4(0, 0, 0, 0), vb = make_uint4(0, 0, 0, 0);
+            if (m0 + row < M) va = *reinterpret_cast<const uint4 *>(Ac + (size_t)(m0 + row) * K + k0 + seg * 16);
+            if (n0 + row < N) vb = *reinterpret_cast<const uint4 *>(Bc + (size_t)(n0 + row) * K + k0 + seg * 16);
+            *reinterpret_cast<uint4 *>(&sA[row * PITCH + seg * 16]) = va;
+            *reinterpret_cast<uint4 *>(&sB[row * PITCH + seg * 16]) = vb;
+        }
+        for (int e = tid; e < BM * 4; e += 256) {
+            const int row = e >> 2, g = e & 3;
+            ssA[e] = m0 + row < M ? As[(size_t)(m0 + row) * kb + k0 / 32 + g] : (unsigned char)127;
+            ssB[e] = n0 + row < N ? Bs[(size_t)(n0 + row) * kb + k0 / 32 + g] : (unsigned char)127;
+        }
+        __syncthreads();
+        const int g = lane >> 4;
+        i32x8 av[4], bv[4];
+        int sa[4], sb[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = wm * 64 + i * 16 + (lane & 15);
+            const uint4 lo = *reinterpret_cast<const uint4 *>(&sA[row * PITCH + 16 * g]);
+            const uint4 hi = *reinterpret_cast<const uint4 *>(&sA[row * PITCH + 64 + 16 * g]);
+            av[i] = i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w,
+                          (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+            sa[i] = ssA[row * 4 + g];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int col = wn * 64 + j * 16 + (lane & 15);
+            const uint4 lo = *reinterpret_cast<const uint4 *>(&sB[col * PITCH + 16 * g]);
+            const uint4 hi = *reinterpret_cast<const uint4 *>(&sB[col * PITCH + 64 + 16 * g]);
+            bv[j] = i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w,
+                          (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+            sb[j] = ssB[col * 4 + g];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+                    av[i], bv[j], acc[i][j], 0, 0, 0, sa[i], 0, sb[j]);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = m0 + wm * 64 + i * 16 + (lane >> 4) * 4 + v;
+                const int col = n0 + wn * 64 + j * 16 + (lane & 15);
+                if (row < M && col < N) C[(size_t)row * ldc + col] -= acc[i][j][v];
+            }
+}
+
+hipError_t launch_gemm_fp8(int M, int N, int K, const void *Ac, const void *As, const void *Bc,
+                           const void *Bs, float *C, int ldc, hipStream_t s, int lower,
+                           int spare_xcd0) {
+    if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
+    if (K % 128) return hipErrorInvalidValue;
+    const dim3 grid = gemm_grid(spare_xcd0, (N + 127) / 128, (M + 127) / 128);
+    k_gemm_fp8<<<grid, dim3(256), 0, s>>>(M, N, K, static_cast<const unsigned char *>(Ac),
+                                          static_cast<const unsigned char *>(As),
+                                          static_cast<const unsigned char *>(Bc),
+                                          static_cast<const unsigned char *>(Bs), C, ldc, lower,
+                                          spare_xcd0);
     return hipGetLastError();
 }
 

@@ -46,7 +46,7 @@ def _check(A, b, x, kappa, x_ref=None):
     return m
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp64", "bf16", "fp16"])
+@pytest.mark.parametrize("prec", ["fp32", "fp64", "bf16", "fp16", "fp8"])
 @pytest.mark.parametrize("n", [1, 2, 17, 64, 65, 200, 256, 257, 511, 700])
 def test_dxgesv_uniform_small(solver, n, prec):
     """Dense uniform[-1,1] systems, ragged sizes spanning several panels."""
@@ -207,3 +207,43 @@ def test_getrs_multi_rhs_fp64(solver, kind, n, nrhs):
     x = X.cpu().numpy()
     xr = np.linalg.solve(A, b)
     assert np.abs(x - xr).max() / np.abs(xr).max() <= 1e-12, np.abs(x - xr).max()
+
+
+@pytest.mark.parametrize("n", [300, 1100])
+def test_fp8_operands_factor_and_converge(solver, n):
+    """FP8 (E4M3 with a power-of-two scale per 32 K values) trailing-update
+    operands: the factor read back satisfies P A = L U to the operand
+    precision (a wrong operand or scale layout gives O(1) errors), and the
+    solve ends FP64-accurate.  With eps_s = 2^-4 the classical refinement
+    of Algorithm 1 does not contract at these orders (Section 4: it needs
+    kappa eps_s < 1 for the effective eps_s of the factor), so the result
+    comes from the FP64 fallback."""
+    import torch
+
+    from paper_0808_2794_amd import mixlu
+
+    A, b, _ = gen.prescribed_cond_system(n, 2.0, 700 + n)
+    _say(f"fp8 factor n={n}")
+    Ad, bd = _to_dev(A, b)
+    o = mixlu.default_opts(equilibrate=0)
+    work = solver.workspace(mixlu.OP_GESV, mixlu.FP8, n, 1, o)
+    F, info = mixlu.mixlu_getrf(solver.ctx, mixlu.FP8, Ad, work, o)
+    assert info == 0 and F.lowp_status == 0 and F.nb % 128 == 0
+    torch.cuda.synchronize()
+    npad = F.npad
+    W = work[F.off[0]:F.off[0] + npad * npad * 4].view(torch.float32).reshape(npad, npad)
+    ipiv = work[F.off[4]:F.off[4] + npad * 4].view(torch.int32)
+    LU = W[:n, :n].double().cpu().numpy()
+    piv = ipiv[:n].cpu().numpy()
+    L = np.tril(LU, -1) + np.eye(n)
+    U = np.triu(LU)
+    order = np.arange(n)
+    for k, p in enumerate(piv):
+        order[[k, p]] = order[[p, k]]
+    err = np.abs(A[order] - L @ U).max()
+    scale = (np.abs(L) @ np.abs(U)).max()
+    assert err <= 0.25 * scale, (err, scale)
+    r = solver.dxgesv(Ad, bd, "fp8")
+    ref = O.gesv_ir(A, b)
+    _check(A, b, r.x.cpu().numpy(), 2.0, ref.x)
+    assert r.report["converged"], r.report
