@@ -53,6 +53,10 @@ def parse():
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--kappa", type=float, default=None)
     ap.add_argument("--seed", type=int, default=None)
+    ap.add_argument("--matrix", default="prescribed", choices=["prescribed", "uniform"],
+                    help="dense workload input: U diag(sigma) V^T (default) or iid U[-1,1] "
+                         "entries (no QR; for counter runs, whose traffic depends on the "
+                         "shapes only)")
     ap.add_argument("--compare-steps", type=int, default=2, help="timed FP64 comparator runs")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target wall time of the CPU oracle sample (0: skip)")
@@ -179,7 +183,14 @@ def run_dense(args, prec):
     n = args.n or 16384
     kappa = args.kappa or 1e4
     seed = args.seed or 221
-    A, b, x_true = gen.prescribed_cond_system(n, kappa, seed, backend="torch", device="cuda")
+    if args.matrix == "uniform":
+        g = torch.Generator(device="cuda").manual_seed(seed)
+        A = torch.rand(n, n, dtype=torch.float64, device="cuda", generator=g) * 2 - 1
+        x_true_d = torch.rand(n, 1, dtype=torch.float64, device="cuda", generator=g) * 2 - 1
+        b = A @ x_true_d
+        x_true = x_true_d.cpu().numpy()
+    else:
+        A, b, x_true = gen.prescribed_cond_system(n, kappa, seed, backend="torch", device="cuda")
     A, b = A.contiguous(), b.contiguous()
     sync()
     solver = mixlu.Solver()
@@ -204,7 +215,8 @@ def run_dense(args, prec):
     solver.close()
     rep = res.report
     return ms, kst, cpu, comp, {
-        "config": {"workload": f"dense_nonsym_prescribed_cond_n{n}_kappa{kappa:g}_nrhs1",
+        "config": {"workload": (f"dense_nonsym_prescribed_cond_n{n}_kappa{kappa:g}_nrhs1"
+                                if args.matrix == "prescribed" else f"dense_nonsym_uniform_n{n}_nrhs1"),
                    "n": n, "kappa": kappa, "nrhs": 1, "seed": seed, "factor_precision": prec,
                    "refinement": "fp64"},
         "solve": {"iter": rep["iter"], "prec_used": rep["prec"], "converged": rep["converged"],

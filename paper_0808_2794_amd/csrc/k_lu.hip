@@ -444,11 +444,40 @@ __global__ __launch_bounds__(256) void k_trsm_diag(const T *__restrict__ L, int 
     if (act) X[(size_t)lane * ldx + col] = x;
 }
 
+// Same operation for many columns: one thread per column, L staged once per
+// 64 columns in LDS (the per-wave register copy above would re-read L for
+// every four columns).
+template <typename T, int DB>
+__global__ __launch_bounds__(64) void k_trsm_diag_wide(const T *__restrict__ L, int ldl,
+                                                       T *__restrict__ X, int ldx, int ncols) {
+    __shared__ T sL[DB][DB + 1];
+    const int t = threadIdx.x;
+    for (int i = 0; i < DB; ++i)
+        for (int c = t; c < DB; c += 64) sL[i][c] = L[(size_t)i * ldl + c];
+    __syncthreads();
+    const int col = blockIdx.x * 64 + t;
+    if (col >= ncols) return;
+    T x[DB];
+#pragma unroll
+    for (int i = 0; i < DB; ++i) x[i] = X[(size_t)i * ldx + col];
+#pragma unroll
+    for (int k = 0; k < DB; ++k) {
+#pragma unroll
+        for (int i = k + 1; i < DB; ++i) x[i] -= sL[i][k] * x[k];
+    }
+#pragma unroll
+    for (int i = 0; i < DB; ++i) X[(size_t)i * ldx + col] = x[i];
+}
+
 template <typename T>
 hipError_t launch_trsm_diag(const T *Ldiag, int ldl, T *X, int ldx, int ncols, hipStream_t s) {
     if (ncols <= 0) return hipSuccess;
     constexpr int DB = PanelWidth<T>::v;
-    k_trsm_diag<T, DB><<<dim3((ncols + 3) / 4), dim3(256), 0, s>>>(Ldiag, ldl, X, ldx, ncols);
+    if (ncols <= 1024)
+        k_trsm_diag<T, DB><<<dim3((ncols + 3) / 4), dim3(256), 0, s>>>(Ldiag, ldl, X, ldx, ncols);
+    else
+        k_trsm_diag_wide<T, DB><<<dim3((ncols + 63) / 64), dim3(64), 0, s>>>(Ldiag, ldl, X, ldx,
+                                                                             ncols);
     return hipGetLastError();
 }
 template hipError_t launch_trsm_diag<float>(const float *, int, float *, int, int, hipStream_t);
