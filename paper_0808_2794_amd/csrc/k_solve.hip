@@ -207,6 +207,9 @@ __global__ __launch_bounds__(256) void k_trsv(int upper, const T *__restrict__ W
         T lrow[BS];
 #pragma unroll
         for (int k = 0; k < BS; ++k) lrow[k] = sL[lane][k];
+        // reciprocal of this lane's diagonal entry, computed off the chain:
+        // the dependent steps then multiply instead of divide
+        const T dinv = (T)1 / sL[lane][lane];
         if (!upper && !TRANS) {  // unit lower
 #pragma unroll
             for (int k = 0; k < BS; ++k) {
@@ -219,10 +222,10 @@ __global__ __launch_bounds__(256) void k_trsv(int upper, const T *__restrict__ W
         } else if (!upper) {  // non-unit lower (U^T)
 #pragma unroll
             for (int k = 0; k < BS; ++k) {
-                const T dk = bcast_lane(lrow[k], k);
+                const T rk = bcast_lane(dinv, k);
 #pragma unroll
                 for (int c = 0; c < NRT; ++c) {
-                    const T yk = bcast_lane(sv[c], k) / dk;
+                    const T yk = bcast_lane(sv[c], k) * rk;
                     if (lane == k) sv[c] = yk;
                     else if (lane > k) sv[c] -= lrow[k] * yk;
                 }
@@ -239,10 +242,10 @@ __global__ __launch_bounds__(256) void k_trsv(int upper, const T *__restrict__ W
         } else {
 #pragma unroll
             for (int k = BS - 1; k >= 0; --k) {
-                const T dk = bcast_lane(lrow[k], k);
+                const T rk = bcast_lane(dinv, k);
 #pragma unroll
                 for (int c = 0; c < NRT; ++c) {
-                    const T yk = bcast_lane(sv[c], k) / dk;
+                    const T yk = bcast_lane(sv[c], k) * rk;
                     if (lane == k) sv[c] = yk;
                     else if (lane < k) sv[c] -= lrow[k] * yk;
                 }
