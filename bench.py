@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--kappa", type=float, default=None)
     ap.add_argument("--seed", type=int, default=None)
+    ap.add_argument("--refine", default="classic", choices=["classic", "fgmres"],
+                    help="refinement after the low-precision factor (dense workload)")
     ap.add_argument("--matrix", default="prescribed", choices=["prescribed", "uniform"],
                     help="dense workload input: U diag(sigma) V^T (default) or iid U[-1,1] "
                          "entries (no QR; for counter runs, whose traffic depends on the "
@@ -194,10 +196,11 @@ def run_dense(args, prec):
     A, b = A.contiguous(), b.contiguous()
     sync()
     solver = mixlu.Solver()
+    refine = mixlu.REFINE_FGMRES if args.refine == "fgmres" else mixlu.REFINE_CLASSIC
     for _ in range(args.warmup):
-        solver.dxgesv(A, b, prec)
+        solver.dxgesv(A, b, prec, refine=refine)
     mixlu.mixlu_profile_enable(solver.ctx, True)
-    ms, res = time_calls(lambda: solver.dxgesv(A, b, prec), args.steps)
+    ms, res = time_calls(lambda: solver.dxgesv(A, b, prec, refine=refine), args.steps)
     kst = mixlu.mixlu_profile_read(solver.ctx)
     mixlu.mixlu_profile_enable(solver.ctx, False)
     x = res.x.double().cpu().numpy()
@@ -218,7 +221,7 @@ def run_dense(args, prec):
         "config": {"workload": (f"dense_nonsym_prescribed_cond_n{n}_kappa{kappa:g}_nrhs1"
                                 if args.matrix == "prescribed" else f"dense_nonsym_uniform_n{n}_nrhs1"),
                    "n": n, "kappa": kappa, "nrhs": 1, "seed": seed, "factor_precision": prec,
-                   "refinement": "fp64"},
+                   "refinement": "fp64 " + args.refine},
         "solve": {"iter": rep["iter"], "prec_used": rep["prec"], "converged": rep["converged"],
                   "berr": rep["berr"], "fwd_err_vs_x_true": fwd}}
 

@@ -92,8 +92,21 @@ typedef struct {
                          ||r_k|| >= stall * ||r_{k-1}|| twice in a row
                          (k >= 2) or ||r_k|| >= ||r_{k-1}|| once (k >= 3);
                          default 0.9                                         */
-    int reserved[6];
+    int refine;       /* mixlu_refine_kind (default MIXLU_REFINE_CLASSIC)    */
+    int reserved[5];
 } mixlu_opts;
+
+/* Refinement after the low-precision factorization.  CLASSIC is the
+   stationary iteration of Algorithm 1.  FGMRES is the flexible GMRES outer
+   loop of Algorithm 2, with one application of the low-precision LU solve
+   as the (right) preconditioner in place of the inner single-precision
+   GMRES: FP64 Arnoldi, restarts every 30 steps, the stopping test of
+   Section 3 on the true FP64 residual at every restart; `itermax` and
+   `stall` then count restarts, and report.iter counts preconditioner
+   applications.  It keeps converging where kappa eps_s approaches or
+   exceeds 1 (BF16/FP16/FP8 factors), where CLASSIC stalls.  FGMRES applies
+   to one right-hand side of op(A) = A; other calls use CLASSIC. */
+typedef enum { MIXLU_REFINE_CLASSIC = 0, MIXLU_REFINE_FGMRES = 1 } mixlu_refine_kind;
 
 /* Fill *o with the defaults listed above. */
 void mixlu_default_opts(mixlu_opts *o);

@@ -201,6 +201,7 @@ size_t mixlu::plan_layout(Layout &L, int op, int prec, int n, int nrhs, const mi
     L.tmp = take((size_t)(2 * kColChunks + 2) * np * 8);
     L.status = take(ST_COUNT * 4);
     L.norms = take((size_t)(4 + 3 * L.nrhs) * 8);
+    L.krylov = take(((size_t)(2 * kKrylov + 2) * np + 4 * kKrylov + 16) * 8);
     L.total = off;
     return off;
 }
@@ -249,8 +250,9 @@ Layout layout_of(const mixlu_factor *F) {
     L.moves = F->off[13];
     L.tmp = F->off[14];
     L.status = F->off[15];
-    // norms follow status (same rule as plan_layout)
+    // norms and the Krylov area follow status (same rule as plan_layout)
     L.norms = align_up(L.status + ST_COUNT * 4, 256);
+    L.krylov = align_up(L.norms + (size_t)(4 + 3 * L.nrhs) * 8, 256);
     return L;
 }
 
@@ -646,6 +648,142 @@ int refine_loop(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t woff, cons
     }
 }
 
+// Flexible GMRES refinement (the outer FGMRES of Algorithm 2, with one
+// application of the low-precision LU solve M = (LU)^{-1} P as the
+// preconditioner in place of the inner single-precision GMRES): FP64
+// Arnoldi with classical Gram-Schmidt applied twice, Givens rotations on the
+// host, restarts every kKrylov steps.  At each restart the true residual is
+// formed in FP64 and the stopping test of Section 3 decides; within a cycle
+// the rotated residual norm ends the cycle early once it is below the
+// threshold.  One right-hand side, A not transposed.  res.iters counts
+// preconditioner applications; failure codes as for refine_loop, with the
+// cycle count playing the role of the iteration count (itermax cycles).
+template <typename Tw>
+int fgmres_loop(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t woff, const double *A,
+                int lda, const double *B, double *X, double anorm, const mixlu_opts &o,
+                LoopResult &res) {
+    hipStream_t s = ctx->stream;
+    const int n = L.n, np = L.npad, m = kKrylov;
+    double *Rv = at<double>(work, L.vec_r);
+    double *norms = at<double>(work, L.norms);
+    double *rnorm = norms + 4, *xnorm = norms + 4 + L.nrhs;
+    int *status = at<int>(work, L.status);
+    double *K = at<double>(work, L.krylov);
+    double *V = K;                                // m + 1 basis vectors
+    double *Z = K + (size_t)(m + 1) * np;        // m preconditioned vectors
+    double *zero = K + (size_t)(2 * m + 1) * np; // zero right-hand side
+    double *hd = K + (size_t)(2 * m + 2) * np;   // 4 * m + 16 scalars
+    double *h1 = hd, *h2 = hd + (m + 2), *yd = hd + 2 * (m + 2);
+    RETCK(ensure_hbuf(ctx, (size_t)(4 * m + 32) * 8));
+    double *hb = ctx->hbuf;
+    const double thr = std::sqrt((double)n) * kEpsD * anorm;
+    HIPCK(launch_fill_f64(zero, 0.0, (size_t)np, s));
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+    auto Hat = [&](int i, int j) -> double & { return H[(size_t)i * m + j]; };
+    res = LoopResult{0, 0, 0.0, 0.0, 0.0};
+    double prev = 0.0, ratio_prev = 0.0;
+    int its = 0;
+    for (int cyc = 0;; ++cyc) {
+        HIPCK(launch_fill_f64(rnorm, 0.0, 1, s));
+        HIPCK(launch_fill_f64(xnorm, 0.0, 1, s));
+        {
+            ProfScope ps(PC_RESID, 2.0 * n * n, 8.0 * n * n + 24.0 * n, s);
+            HIPCK(launch_residual(n, 1, A, lda, X, 1, B, 1, 0, Rv, 1, rnorm, xnorm, s));
+        }
+        HIPCK(launch_dots(n, 1, Rv, np, Rv, h1, s));
+        HIPCK(hipMemcpyAsync(hb, rnorm, 8, hipMemcpyDeviceToHost, s));
+        HIPCK(hipMemcpyAsync(hb + 1, xnorm, 8, hipMemcpyDeviceToHost, s));
+        HIPCK(hipMemcpyAsync(hb + 2, h1, 8, hipMemcpyDeviceToHost, s));
+        HIPCK(hipMemcpyAsync(hb + 4, status, ST_COUNT * 4, hipMemcpyDeviceToHost, s));
+        HIPCK(hipStreamSynchronize(s));
+        int stl[ST_COUNT];
+        std::memcpy(stl, hb + 4, ST_COUNT * 4);
+        if (stl[ST_TIMEOUT]) return MIXLU_ERR_DEVICE_TIMEOUT;
+        const double r = hb[0], xn = hb[1], beta = std::sqrt(hb[2]);
+        res.rnorm = r;
+        res.xnorm = xn;
+        res.berr = anorm * xn > 0 ? r / (anorm * xn) : (r > 0 ? INFINITY : 0.0);
+        const bool finite = std::isfinite(r) && std::isfinite(xn) && std::isfinite(beta);
+        if (finite && r <= thr * xn) {
+            res.iters = its;
+            res.converged = 1;
+            return MIXLU_OK;
+        }
+        if (!finite) {
+            res.berr = NAN;
+            res.iters = -4;
+            return MIXLU_OK;
+        }
+        if (cyc >= 1 && prev > 0) {
+            const double rho = r / prev;
+            if ((cyc >= 2 && rho >= o.stall && ratio_prev >= o.stall) || (cyc >= 3 && rho >= 1.0)) {
+                res.iters = -4;
+                return MIXLU_OK;
+            }
+            ratio_prev = rho;
+        }
+        prev = r;
+        if (cyc == o.itermax) {
+            res.iters = -(o.itermax + 1);
+            return MIXLU_OK;
+        }
+        // Arnoldi cycle from v_0 = r / beta
+        HIPCK(launch_scale_copy(n, 1.0 / beta, Rv, V, s));
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int kk = 0;
+        for (int k = 0; k < m && k < n; ++k) {
+            double *vk = V + (size_t)k * np, *zk = Z + (size_t)k * np, *w = V + (size_t)(k + 1) * np;
+            RETCK(lu_solve<Tw>(s, work, L, woff, 1, vk, 1, 0, zk, 1, 0, 1, 0));
+            {
+                ProfScope ps(PC_RESID, 2.0 * n * n, 8.0 * n * n + 24.0 * n, s);
+                HIPCK(launch_residual(n, 1, A, lda, zk, 1, zero, 1, 0, w, 1, rnorm, xnorm, s));
+            }
+            HIPCK(launch_scale_copy(n, -1.0, w, w, s));  // w = A z_k
+            HIPCK(launch_dots(n, k + 1, V, np, w, h1, s));
+            HIPCK(launch_combine(n, k + 1, V, np, h1, -1.0, w, s));
+            HIPCK(launch_dots(n, k + 1, V, np, w, h2, s));
+            HIPCK(launch_combine(n, k + 1, V, np, h2, -1.0, w, s));
+            HIPCK(launch_dots(n, 1, w, np, w, h2 + (k + 1), s));
+            HIPCK(hipMemcpyAsync(hb, h1, (size_t)(k + 1) * 8, hipMemcpyDeviceToHost, s));
+            HIPCK(hipMemcpyAsync(hb + (m + 2), h2, (size_t)(k + 2) * 8, hipMemcpyDeviceToHost, s));
+            HIPCK(hipStreamSynchronize(s));
+            for (int j = 0; j <= k; ++j) Hat(j, k) = hb[j] + hb[m + 2 + j];
+            const double hn = std::sqrt(hb[m + 2 + k + 1]);
+            Hat(k + 1, k) = hn;
+            ++its;
+            kk = k + 1;
+            if (hn > 0 && std::isfinite(hn)) HIPCK(launch_scale_copy(n, 1.0 / hn, w, w, s));
+            // Givens: rotate column k, then zero H(k+1, k)
+            for (int j = 0; j < k; ++j) {
+                const double t = cs[j] * Hat(j, k) + sn[j] * Hat(j + 1, k);
+                Hat(j + 1, k) = -sn[j] * Hat(j, k) + cs[j] * Hat(j + 1, k);
+                Hat(j, k) = t;
+            }
+            const double a = Hat(k, k), bq = Hat(k + 1, k);
+            const double d = std::hypot(a, bq);
+            cs[k] = d > 0 ? a / d : 1.0;
+            sn[k] = d > 0 ? bq / d : 0.0;
+            Hat(k, k) = d;
+            Hat(k + 1, k) = 0.0;
+            g[k + 1] = -sn[k] * g[k];
+            g[k] = cs[k] * g[k];
+            const double est = std::fabs(g[k + 1]);
+            if (!(hn > 0) || !std::isfinite(est) || est <= 0.5 * thr * xn) break;
+        }
+        // y = H^{-1} g (upper triangular kk x kk), x += Z y
+        for (int i = kk - 1; i >= 0; --i) {
+            double t = g[i];
+            for (int j = i + 1; j < kk; ++j) t -= Hat(i, j) * y[j];
+            y[i] = Hat(i, i) != 0 ? t / Hat(i, i) : 0.0;
+        }
+        std::memcpy(hb, y.data(), (size_t)kk * 8);
+        HIPCK(hipMemcpyAsync(yd, hb, (size_t)kk * 8, hipMemcpyHostToDevice, s));
+        HIPCK(launch_combine(n, kk, Z, np, yd, 1.0, X, s));
+        HIPCK(hipStreamSynchronize(s));  // hb is reused by the next residual read
+    }
+}
+
 // Argument checks shared by the solve entry points; `pn` is the 1-based
 // position of n in the caller's signature, followed by nrhs, A, lda, B, ldb,
 // X, ldx.
@@ -850,6 +988,7 @@ void mixlu_default_opts(mixlu_opts *o) {
     o->nb = 0;
     o->layout = MIXLU_ROW_MAJOR;
     o->stall = 0.9;
+    o->refine = MIXLU_REFINE_CLASSIC;
 }
 
 int mixlu_create(mixlu_ctx_t *ctx, void *stream) {
@@ -975,7 +1114,15 @@ int mixlu_refine(mixlu_ctx_t ctx, mixlu_factor *F, int trans, int nrhs, const do
     LoopResult res{};
     int reason = F->lowp_status;
     if (reason == 0) {
-        if (F->prec == MIXLU_FP64)
+        // flexible GMRES for one right-hand side of A (not A^T); otherwise
+        // the stationary refinement of Algorithm 1
+        const bool krylov = op_.refine == MIXLU_REFINE_FGMRES && nrhs == 1 && !tr && ldb == 1 &&
+                            ldx == 1;
+        if (krylov && F->prec == MIXLU_FP64)
+            RETCK(fgmres_loop<double>(ctx, F->work, L, L.W, A, lda, B, X, anorm, op_, res));
+        else if (krylov)
+            RETCK(fgmres_loop<float>(ctx, F->work, L, L.W, A, lda, B, X, anorm, op_, res));
+        else if (F->prec == MIXLU_FP64)
             RETCK(refine_loop<double>(ctx, F->work, L, L.W, A, lda, B, ldb, X, ldx, cm, nrhs,
                                       anorm, op_, res, tr));
         else

@@ -24,6 +24,7 @@ constexpr int kTrsvBS = 64;        // rows per block of the chained solves
 constexpr int kTrsvNRT = 8;        // right-hand sides per chained-solve launch
 constexpr int kColChunks = 64;   // row chunks of the column-statistics pass
 constexpr unsigned kSpinLimit = 1u << 23;  // polls before a device wait gives up
+constexpr int kKrylov = 30;         // flexible GMRES restart length
 constexpr int kBatchedNmax = 512;   // largest order of a batched system
 constexpr int kBatchedSlots = 512;  // workgroups (and workspace slots) of a batched launch
 
@@ -212,6 +213,7 @@ struct Layout {
     size_t vec_r;    // double[npad * nrhs] residual
     size_t vec_y;    // double[npad * nrhs] solve vector (float or double view)
     size_t vec_z;    // double[npad * nrhs] second solve vector (blocked solves)
+    size_t krylov;   // flexible GMRES: V (kKrylov + 1 vectors), Z (kKrylov), h, y (doubles)
     size_t xbuf;     // panel exchange words
     size_t ybuf;     // chained-solve exchange words + tickets
     size_t moves;    // int[2 * (2 * nb + 64) + 4] row-move lists
@@ -308,6 +310,12 @@ hipError_t launch_trsm_blocked(int upper, int trans, const Tw *W, int ldw, int n
 hipError_t launch_residual_mm(int n, int nrhs, const double *A, int lda, int transa,
                               const double *X, int ldx, const double *B, int ldb, int cm,
                               double *Rv, int ldr, double *rnorm, double *xnorm, hipStream_t s);
+// FP64 vector kernels of the flexible GMRES refinement (V[j * ldv + i])
+hipError_t launch_dots(int n, int k, const double *V, size_t ldv, const double *w, double *h,
+                       hipStream_t s);
+hipError_t launch_combine(int n, int k, const double *V, size_t ldv, const double *h, double sign,
+                          double *w, hipStream_t s);
+hipError_t launch_scale_copy(int n, double alpha, const double *x, double *y, hipStream_t s);
 // part: scratch of 16 * n * 8 doubles
 hipError_t launch_residual_t(int n, int nrhs, const double *A, int lda, const double *X, int ldx,
                              const double *B, int ldb, int bx_col_major, double *Rv, int ldr,

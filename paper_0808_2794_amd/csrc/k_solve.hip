@@ -744,6 +744,62 @@ hipError_t launch_residual_mm(int n, int nrhs, const double *A, int lda, int tra
     return hipGetLastError();
 }
 
+// ----------------------------------------------------------------------
+// FP64 vector kernels of the flexible GMRES refinement (Algorithm 2's outer
+// loop).  Basis vectors are stored one after another: V[j * ldv + i].
+// ----------------------------------------------------------------------
+// h[j] = sum_i V[j][i] w[i] for j < k: workgroup j reduces one dot product.
+__global__ __launch_bounds__(256) void k_dots(int n, int k, const double *__restrict__ V, size_t ldv,
+                                              const double *__restrict__ w,
+                                              double *__restrict__ h) {
+    const int j = blockIdx.x;
+    if (j >= k) return;
+    const double *v = V + (size_t)j * ldv;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) s += v[i] * w[i];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    __shared__ double part[4];
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) h[j] = (part[0] + part[1]) + (part[2] + part[3]);
+}
+
+// w[i] += sign * sum_{j<k} h[j] V[j][i]
+__global__ __launch_bounds__(256) void k_combine(int n, int k, const double *__restrict__ V,
+                                                 size_t ldv, const double *__restrict__ h,
+                                                 double sign, double *__restrict__ w) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int j = 0; j < k; ++j) s += h[j] * V[(size_t)j * ldv + i];
+    w[i] += sign * s;
+}
+
+// y[i] = alpha * x[i]
+__global__ __launch_bounds__(256) void k_scale_copy(int n, double alpha, const double *__restrict__ x,
+                                                    double *__restrict__ y) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) y[i] = alpha * x[i];
+}
+
+hipError_t launch_dots(int n, int k, const double *V, size_t ldv, const double *w, double *h,
+                       hipStream_t s) {
+    if (k <= 0) return hipSuccess;
+    k_dots<<<dim3(k), dim3(256), 0, s>>>(n, k, V, ldv, w, h);
+    return hipGetLastError();
+}
+hipError_t launch_combine(int n, int k, const double *V, size_t ldv, const double *h, double sign,
+                          double *w, hipStream_t s) {
+    if (k <= 0 || n <= 0) return hipSuccess;
+    k_combine<<<dim3((n + 255) / 256), dim3(256), 0, s>>>(n, k, V, ldv, h, sign, w);
+    return hipGetLastError();
+}
+hipError_t launch_scale_copy(int n, double alpha, const double *x, double *y, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_scale_copy<<<dim3((n + 255) / 256), dim3(256), 0, s>>>(n, alpha, x, y);
+    return hipGetLastError();
+}
+
 // GA = beta GA + alpha G X^T (all row-major FP64; G, X are n x nrhs).
 __global__ __launch_bounds__(256) void k_outer(int n, int nrhs, const double *__restrict__ G,
                                                int ldg, const double *__restrict__ X, int ldx,

@@ -20,6 +20,7 @@ FP64, FP32, BF16, FP16, FP8 = 0, 1, 2, 3, 4
 PREC = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "fp16": FP16, "fp8": FP8}
 PREC_NAME = {v: k for k, v in PREC.items()}
 OP_GESV, OP_POSV, OP_DGESV, OP_DPOSV = 0, 1, 2, 3
+REFINE_CLASSIC, REFINE_FGMRES = 0, 1
 ROW_MAJOR, COL_MAJOR = 0, 1
 
 OK = 0
@@ -29,7 +30,8 @@ ERR_HIP, ERR_WORKSPACE, ERR_NOT_IMPLEMENTED, ERR_UNSUPPORTED_ARCH, ERR_DEVICE_TI
 class mixlu_opts(ctypes.Structure):
     _fields_ = [("itermax", ctypes.c_int), ("equilibrate", ctypes.c_int),
                 ("fallback", ctypes.c_int), ("nb", ctypes.c_int), ("layout", ctypes.c_int),
-                ("stall", ctypes.c_double), ("reserved", ctypes.c_int * 6)]
+                ("stall", ctypes.c_double), ("refine", ctypes.c_int),
+                ("reserved", ctypes.c_int * 5)]
 
 
 class mixlu_report(ctypes.Structure):
