@@ -270,7 +270,6 @@ int factor_lu(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t woff, int tr
     T *W = at<T>(work, woff);
     int *ipiv = at<int>(work, L.ipiv);
     int *perm = at<int>(work, L.perm);
-    int *moves = at<int>(work, L.moves);
     int *status = at<int>(work, L.status);
     auto *xbuf = at<unsigned long long>(work, L.xbuf);
     if (nb % B || nb % 64 || nb > 512) return MIXLU_ERR_NOT_IMPLEMENTED;
@@ -294,8 +293,7 @@ int factor_lu(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t woff, int tr
                 ProfScope ps(PC_PANEL, fl, 2.0 * m * B * sizeof(T), s);
                 HIPCK(launch_panel<T>(W, np, k, np - k, ipiv, xbuf, status, s));
             }
-            HIPCK(launch_perm_build(ipiv, k, B, np, perm, moves, s));
-            HIPCK(launch_rows_move<T>(W, np, np, moves, 2 * B, K0, kend, k, k + B, s));
+            HIPCK(launch_row_swaps<T>(ipiv, k, B, np, perm, W, np, K0, kend, k, k + B, s));
             if (k + B < kend) {
                 HIPCK(launch_trsm_diag<T>(Wp(k, k), np, Wp(k, k + B), np, kend - k - B, s));
                 HIPCK(launch_gemm<T>(np - k - B, kend - k - B, B, Wp(k + B, k), np, Wp(k, k + B),
@@ -308,8 +306,7 @@ int factor_lu(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t woff, int tr
             HIPCK(hipStreamWaitEvent(s, ctx->ev_join, 0));
             side_busy = false;
         }
-        HIPCK(launch_perm_build(ipiv, K0, nb, np, nullptr, moves, s));
-        HIPCK(launch_rows_move<T>(W, np, np, moves, 2 * nb, 0, np, K0, kend, s));
+        HIPCK(launch_row_swaps<T>(ipiv, K0, nb, np, nullptr, W, np, 0, np, K0, kend, s));
         if (kend >= np) break;
         const int nr = np - kend;
         for (int ib = 0; ib < nb; ib += B) {

@@ -246,10 +246,10 @@ hipError_t launch_convert(const double *A, int lda, int n, int npad, const doubl
 template <typename T>
 hipError_t launch_panel(T *W, int ldw, int k0, int m, int *ipiv, unsigned long long *xb,
                         int *status, hipStream_t s);
-hipError_t launch_perm_build(const int *ipiv, int k0, int cnt, int npad, int *perm, int *moves,
-                             hipStream_t s);
+// pivots ipiv[k0 .. k0+cnt-1] applied to the columns [c0, c1) minus
+// [skip0, skip1) of W, and to perm when given, in one launch
 template <typename T>
-hipError_t launch_rows_move(T *W, int ldw, int npad, const int *moves, int max_moves,
+hipError_t launch_row_swaps(const int *ipiv, int k0, int cnt, int npad, int *perm, T *W, int ldw,
                             int c0, int c1, int skip0, int skip1, hipStream_t s);
 template <typename T>
 hipError_t launch_trsm_diag(const T *Ldiag, int ldl, T *X, int ldx, int ncols, hipStream_t s);

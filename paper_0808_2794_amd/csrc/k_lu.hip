@@ -5,8 +5,7 @@
 //                 in registers across up to 32 workgroups placed on one XCD;
 //                 per column: wavefront argmax (first index on ties), one
 //                 tagged cross-workgroup exchange, swap, scale, rank-1 update.
-//   k_perm_build  composes a block of swaps into a list of row moves
-//   k_rows_move   applies the moves to the columns outside the panel
+//   k_row_swaps   applies a block of pivots to the columns outside the panel
 //   k_trsm_diag   X = L^{-1} X with a unit lower diagonal block in LDS
 //   k_gemm        C -= A B on MFMA (f32 16x16x4, f64 16x16x4)
 //   k_pack_*      rounds L21 / U12 to FP16 or BF16 for the trailing update
@@ -289,19 +288,23 @@ template hipError_t launch_panel<double>(double *, int, int, int, int *, unsigne
 // ======================================================================
 // Row interchanges outside the panel
 // ======================================================================
-// One workgroup.  Composes the swaps ipiv[k0 .. k0+cnt) (absolute rows) on
-// positions [k0, npad) and emits moves = {count, pad, (dst, src)...}: after
-// the swaps, row dst holds what row src held before.  When perm is given it
-// is updated the same way (perm[dst] = old perm[src]).  cnt <= 512, so at most
-// 1024 positions move.
-__global__ __launch_bounds__(1024) void k_perm_build(const int *__restrict__ ipiv, int k0, int cnt,
-                                                     int npad, int *__restrict__ perm,
-                                                     int *__restrict__ moves) {
-    extern __shared__ int cur[];
-    __shared__ int s_count;
-    __shared__ int s_dst[1024], s_src[1024];
+// Row interchanges of pivots ipiv[k0 .. k0+cnt-1] applied in one launch:
+// every workgroup composes the swaps into a move list in LDS (cur[i] = the
+// row whose content ends at row k0 + i), then moves the rows of its CW
+// columns of [c0, c1) minus [skip0, skip1) (staged in LDS, so the moves may
+// form cycles).  Workgroup 0 also applies the moves to perm (when given).
+template <typename T, int CW>
+__global__ __launch_bounds__(256) void k_row_swaps(const int *__restrict__ ipiv, int k0, int cnt,
+                                                   int npad, int *__restrict__ perm,
+                                                   T *__restrict__ W, int ldw, int c0, int nleft,
+                                                   int gap, int ncols) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const int m = npad - k0;
-    for (int i = threadIdx.x; i < m; i += blockDim.x) cur[i] = i;
+    int *cur = reinterpret_cast<int *>(smem);                 // m
+    int *mv = cur + m;                                        // 2 * (2 * cnt)
+    T *buf = reinterpret_cast<T *>(mv + 4 * cnt + 4);        // 2 * cnt * CW
+    __shared__ int s_count;
+    for (int i = threadIdx.x; i < m; i += 256) cur[i] = i;
     if (threadIdx.x == 0) s_count = 0;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -316,62 +319,37 @@ __global__ __launch_bounds__(1024) void k_perm_build(const int *__restrict__ ipi
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    for (int i = threadIdx.x; i < m; i += 256) {
         const int src = cur[i];
         if (src != i) {
             const int q = atomicAdd(&s_count, 1);
-            s_dst[q] = k0 + i;
-            s_src[q] = k0 + src;
+            mv[2 * q] = k0 + i;
+            mv[2 * q + 1] = k0 + src;
         }
     }
     __syncthreads();
     const int count = s_count;
-    const int t = threadIdx.x;
-    int keep = 0;
-    if (t < count) {
-        moves[2 + 2 * t] = s_dst[t];
-        moves[3 + 2 * t] = s_src[t];
-        if (perm) keep = perm[s_src[t]];
+    if (perm && blockIdx.x == 0) {
+        int keep[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int q = threadIdx.x + u * 256;
+            keep[u] = q < count ? perm[mv[2 * q + 1]] : 0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int q = threadIdx.x + u * 256;
+            if (q < count) perm[mv[2 * q]] = keep[u];
+        }
     }
-    __syncthreads();
-    if (perm && t < count) perm[s_dst[t]] = keep;
-    if (t == 0) moves[0] = count;
-}
-
-hipError_t launch_perm_build(const int *ipiv, int k0, int cnt, int npad, int *perm, int *moves,
-                             hipStream_t s) {
-    const int m = npad - k0;
-    const size_t lds = (size_t)m * sizeof(int);
-    if (cnt > 512 || lds > 120 * 1024) return hipErrorInvalidValue;
-    static bool attr_done = false;
-    if (!attr_done) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_perm_build),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 120 * 1024);
-        if (e != hipSuccess) return e;
-        attr_done = true;
-    }
-    k_perm_build<<<dim3(1), dim3(1024), lds, s>>>(ipiv, k0, cnt, npad, perm,
-                                                                     moves);
-    return hipGetLastError();
-}
-
-// Apply the moves to columns [c0, c1) minus [skip0, skip1).  Each workgroup
-// owns CW consecutive columns (after removing the skipped range), stages the
-// source segments of every move in LDS, then writes the destinations.
-template <typename T, int CW>
-__global__ __launch_bounds__(256) void k_rows_move(T *__restrict__ W, int ldw,
-                                                   const int *__restrict__ moves, int c0,
-                                                   int nleft, int gap, int ncols) {
-    extern __shared__ unsigned char smem[];
-    T *buf = reinterpret_cast<T *>(smem);
-    const int count = moves[0];
     const int lc0 = blockIdx.x * CW;
     for (int e = threadIdx.x; e < count * CW; e += 256) {
         const int q = e / CW, cc = e % CW;
         const int lc = lc0 + cc;
         if (lc < ncols) {
             const int col = c0 + lc + (lc >= nleft ? gap : 0);
-            buf[e] = W[(size_t)moves[3 + 2 * q] * ldw + col];
+            buf[e] = W[(size_t)mv[2 * q + 1] * ldw + col];
         }
     }
     __syncthreads();
@@ -380,41 +358,44 @@ __global__ __launch_bounds__(256) void k_rows_move(T *__restrict__ W, int ldw,
         const int lc = lc0 + cc;
         if (lc < ncols) {
             const int col = c0 + lc + (lc >= nleft ? gap : 0);
-            W[(size_t)moves[2 + 2 * q] * ldw + col] = buf[e];
+            W[(size_t)mv[2 * q] * ldw + col] = buf[e];
         }
     }
 }
 
 template <typename T>
-hipError_t launch_rows_move(T *W, int ldw, int npad, const int *moves, int max_moves, int c0,
-                            int c1, int skip0, int skip1, hipStream_t s) {
-    (void)npad;
+hipError_t launch_row_swaps(const int *ipiv, int k0, int cnt, int npad, int *perm, T *W, int ldw,
+                            int c0, int c1, int skip0, int skip1, hipStream_t s) {
     constexpr int CW = sizeof(T) == 4 ? 16 : 8;
-    // skipped range clipped to [c0, c1)
+    constexpr size_t kMaxLds = 152 * 1024;  // of the 160 KiB, leaving room for static LDS
+    if (cnt > 512) return hipErrorInvalidValue;
     if (skip0 < c0) skip0 = c0;
     if (skip1 > c1) skip1 = c1;
     if (skip1 < skip0) skip1 = skip0;
     const int nleft = skip0 - c0;
     const int gap = skip1 - skip0;
-    const int ncols = (c1 - c0) - gap;
-    if (ncols <= 0) return hipSuccess;
-    const size_t lds = (size_t)max_moves * CW * sizeof(T);
-    if (lds > 64 * 1024) return hipErrorInvalidValue;
+    int ncols = (c1 - c0) - gap;
+    const int m = npad - k0;
+    const size_t lds = align_up((size_t)(m + 4 * cnt + 4) * 4, 16) + (size_t)2 * cnt * CW * sizeof(T);
+    if (lds > kMaxLds) return hipErrorInvalidValue;
     static bool attr_done = false;
     if (!attr_done) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rows_move<T, CW>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024);
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_row_swaps<T, CW>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds);
         if (e != hipSuccess) return e;
         attr_done = true;
     }
-    k_rows_move<T, CW><<<dim3((ncols + CW - 1) / CW), dim3(256), lds, s>>>(W, ldw, moves, c0, nleft,
-                                                                          gap, ncols);
+    if (ncols < 0) ncols = 0;
+    // at least one workgroup, so that perm is updated even with no columns
+    const int grid = ncols > 0 ? (ncols + CW - 1) / CW : 1;
+    k_row_swaps<T, CW><<<dim3(grid), dim3(256), lds, s>>>(ipiv, k0, cnt, npad, perm, W, ldw, c0,
+                                                          nleft, gap, ncols);
     return hipGetLastError();
 }
-template hipError_t launch_rows_move<float>(float *, int, int, const int *, int, int, int, int,
-                                            int, hipStream_t);
-template hipError_t launch_rows_move<double>(double *, int, int, const int *, int, int, int,
-                                             int, int, hipStream_t);
+template hipError_t launch_row_swaps<float>(const int *, int, int, int, int *, float *, int, int,
+                                            int, int, int, hipStream_t);
+template hipError_t launch_row_swaps<double>(const int *, int, int, int, int *, double *, int, int,
+                                             int, int, int, hipStream_t);
 
 // ======================================================================
 // Triangular solve with a unit lower diagonal block (LDS-staged)
