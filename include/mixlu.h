@@ -152,7 +152,8 @@ typedef enum {
     MIXLU_OP_GESV = 0,  /* mixlu_dxgesv, or mixlu_getrf + getrs/refine      */
     MIXLU_OP_POSV = 1,  /* mixlu_dxposv, or mixlu_potrf + getrs/refine      */
     MIXLU_OP_DGESV = 2, /* mixlu_dgesv (FP64 LU, no refinement)             */
-    MIXLU_OP_DPOSV = 3  /* mixlu_dposv (FP64 Cholesky, no refinement)       */
+    MIXLU_OP_DPOSV = 3, /* mixlu_dposv (FP64 Cholesky, no refinement)       */
+    MIXLU_OP_SGESV = 4  /* mixlu_sgesv (FP32 LU, no refinement)             */
 } mixlu_op;
 
 /* Bytes of device workspace the operation needs for (prec, n, nrhs) with
@@ -248,6 +249,18 @@ int mixlu_dgesv(mixlu_ctx_t ctx, int n, int nrhs, const double *A, int lda,
                 const double *B, int ldb, double *X, int ldx, void *work,
                 size_t lwork, int *info);
 
+/* FP32 LU with partial pivoting and FP32 triangular solves, no refinement
+   and no equilibration: the single-precision solve of Section 2.1 alone
+   (what Algorithm 1 steps 1-3 give before any correction; the SGESV
+   baseline).  A and B are FP64 (const), rounded to FP32 on the device; X
+   (FP64) receives the FP32 solution.  Row-major, like mixlu_dgesv;
+   workspace from mixlu_workspace_size(op MIXLU_OP_SGESV).  *info (host): 0,
+   k+1 for an exact zero or non-finite pivot in column k (X untouched), or
+   n+1 when an entry of A lies outside the FP32 range.  Synchronizes. */
+int mixlu_sgesv(mixlu_ctx_t ctx, int n, int nrhs, const double *A, int lda,
+                const double *B, int ldb, double *X, int ldx, void *work,
+                size_t lwork, int *info);
+
 /* FP64 Cholesky and FP64 triangular solves, no refinement (the DPOSV
    comparator, and the factorization the Cholesky fallback uses).  *info
    (host): 0, or k+1 when the leading minor of order k+1 is not positive
@@ -284,6 +297,12 @@ int mixlu_dxgesv_batched(mixlu_ctx_t ctx, int prec, int batch, const int *d_n,
                          const double *const *d_B, double *const *d_X, int nrhs,
                          void *work, size_t lwork, const mixlu_opts *o,
                          mixlu_report *d_reps);
+
+/* Copy count reports from device memory (d, as filled by
+   mixlu_dxgesv_batched) to host memory h, in order on the context's stream;
+   synchronizes the stream. */
+int mixlu_report_read(mixlu_ctx_t ctx, const mixlu_report *d, int count,
+                      mixlu_report *h);
 
 /* ------------------------------------------------------ kernel timing */
 /* Per-kernel-class timing for measurement: with profiling enabled, the

@@ -166,13 +166,15 @@ struct ProfCall {  // binds the context's profiler to this thread for one API ca
 size_t mixlu::plan_layout(Layout &L, int op, int prec, int n, int nrhs, const mixlu_opts &o) {
     L.n = n;
     L.nrhs = nrhs < 1 ? 1 : nrhs;
-    L.prec = (op == MIXLU_OP_DGESV || op == MIXLU_OP_DPOSV) ? MIXLU_FP64 : prec;
+    L.prec = (op == MIXLU_OP_DGESV || op == MIXLU_OP_DPOSV) ? MIXLU_FP64
+             : op == MIXLU_OP_SGESV                         ? MIXLU_FP32
+                                                            : prec;
     L.kind = (op == MIXLU_OP_POSV || op == MIXLU_OP_DPOSV) ? 1 : 0;
     L.nb = o.nb > 0 ? o.nb : auto_nb(n);
     // the FP8 update multiplies K in steps of 128
     if (L.prec == MIXLU_FP8 && L.nb < 128) L.nb = 128;
     L.npad = round_up(n > 0 ? n : 1, L.nb);
-    L.fallback = (L.prec != MIXLU_FP64) && o.fallback;
+    L.fallback = (L.prec != MIXLU_FP64) && o.fallback && op != MIXLU_OP_SGESV;
     const size_t np = (size_t)L.npad;
     const size_t wbytes = np * np * (L.prec == MIXLU_FP64 ? 8 : 4);
     size_t off = 0;
@@ -957,6 +959,39 @@ int d_entry(mixlu_ctx_s *ctx, int op, int n, int nrhs, const double *A, int lda,
                      0);
 }
 
+
+// FP32 factorization and FP32 solves, no equilibration and no refinement.
+int s_entry(mixlu_ctx_s *ctx, int n, int nrhs, const double *A, int lda, const double *B,
+            int ldb, double *X, int ldx, void *work, size_t lwork, int *info) {
+    RETCK(check_common(ctx, 2, n, nrhs, lda, ldb, ldx, A, B, X));
+    if (!work) return -9;
+    if (!info) return -11;
+    mixlu_opts op_;
+    mixlu_default_opts(&op_);
+    Layout L{};
+    plan_layout(L, MIXLU_OP_SGESV, MIXLU_FP32, n, nrhs, op_);
+    if (lwork < L.total) return MIXLU_ERR_WORKSPACE;
+    *info = 0;
+    if (n == 0 || nrhs == 0) return MIXLU_OK;
+    if (L.npad > kPanelMaxWG * kPanelRowsPerWG) return MIXLU_ERR_NOT_IMPLEMENTED;
+    RETCK(convert_and_factor<float>(ctx, work, L, L.W, A, lda, 0, MIXLU_FP32));
+    int st[ST_COUNT];
+    double nrm[2];
+    RETCK(read_status(ctx, L, work, st, nrm));
+    if (st[ST_TIMEOUT]) return MIXLU_ERR_DEVICE_TIMEOUT;
+    if (st[ST_OVERFLOW]) {
+        *info = n + 1;
+        return MIXLU_OK;
+    }
+    const int brk = breakdown_of(L, st);
+    if (brk != INT_MAX) {
+        *info = brk;
+        return MIXLU_OK;
+    }
+    RETCK(lu_solve<float>(ctx->stream, work, L, L.W, nrhs, B, ldb, 0, X, ldx, 0, 1, 0));
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    return MIXLU_OK;
+}
 }  // namespace
 
 // ======================================================================
@@ -1030,7 +1065,7 @@ int mixlu_set_stream(mixlu_ctx_t ctx, void *stream) {
 int mixlu_workspace_size(mixlu_ctx_t ctx, int op, int prec, int n, int nrhs,
                          const mixlu_opts *o, size_t *bytes) {
     if (!ctx) return -1;
-    if (op < MIXLU_OP_GESV || op > MIXLU_OP_DPOSV) return -2;
+    if (op < MIXLU_OP_GESV || op > MIXLU_OP_SGESV) return -2;
     if (!prec_valid(prec)) return -3;
     if (n < 0) return -4;
     if (nrhs < 0) return -5;
@@ -1179,6 +1214,25 @@ int mixlu_dgesv(mixlu_ctx_t ctx, int n, int nrhs, const double *A, int lda, cons
     if (!ctx) return -1;
     ProfCall pc_(ctx);
     return d_entry(ctx, MIXLU_OP_DGESV, n, nrhs, A, lda, B, ldb, X, ldx, work, lwork, info);
+}
+
+int mixlu_sgesv(mixlu_ctx_t ctx, int n, int nrhs, const double *A, int lda, const double *B,
+                int ldb, double *X, int ldx, void *work, size_t lwork, int *info) {
+    if (!ctx) return -1;
+    ProfCall pc_(ctx);
+    return s_entry(ctx, n, nrhs, A, lda, B, ldb, X, ldx, work, lwork, info);
+}
+
+int mixlu_report_read(mixlu_ctx_t ctx, const mixlu_report *d, int count, mixlu_report *h) {
+    if (!ctx) return -1;
+    if (count < 0) return -3;
+    if (count > 0 && !d) return -2;
+    if (count > 0 && !h) return -4;
+    if (count == 0) return MIXLU_OK;
+    HIPCK(hipMemcpyAsync(h, d, (size_t)count * sizeof(mixlu_report), hipMemcpyDeviceToHost,
+                         ctx->stream));
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    return MIXLU_OK;
 }
 
 int mixlu_dposv(mixlu_ctx_t ctx, int n, int nrhs, const double *A, int lda, const double *B,

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libmixlu.so")
 FP64, FP32, BF16, FP16, FP8 = 0, 1, 2, 3, 4
 PREC = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "fp16": FP16, "fp8": FP8}
 PREC_NAME = {v: k for k, v in PREC.items()}
-OP_GESV, OP_POSV, OP_DGESV, OP_DPOSV = 0, 1, 2, 3
+OP_GESV, OP_POSV, OP_DGESV, OP_DPOSV, OP_SGESV = 0, 1, 2, 3, 4
 REFINE_CLASSIC, REFINE_FGMRES = 0, 1
 ROW_MAJOR, COL_MAJOR = 0, 1
 
@@ -64,7 +64,8 @@ EXPORTS = ("mixlu_status_string", "mixlu_default_opts", "mixlu_create", "mixlu_d
            "mixlu_set_stream", "mixlu_workspace_size", "mixlu_getrf", "mixlu_potrf",
            "mixlu_getrs", "mixlu_refine", "mixlu_dxgesv", "mixlu_dxposv", "mixlu_dgesv",
            "mixlu_dposv", "mixlu_outer_update", "mixlu_batched_workspace_size",
-           "mixlu_dxgesv_batched", "mixlu_profile_enable", "mixlu_profile_read")
+           "mixlu_dxgesv_batched", "mixlu_profile_enable", "mixlu_profile_read",
+           "mixlu_sgesv", "mixlu_report_read")
 
 _lib = None
 
@@ -98,6 +99,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "mixlu_dxgesv_batched": ([P, I, I, P, P, P, P, P, I, P, S, P, P], I),
         "mixlu_profile_enable": ([P, I], I),
         "mixlu_profile_read": ([P, P, I, P], I),
+        "mixlu_sgesv": ([P, I, I, P, I, P, I, P, I, P, S, P], I),
+        "mixlu_report_read": ([P, P, I, P], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -223,6 +226,18 @@ def mixlu_dgesv(ctx, A, B, X, work) -> int:
 
 def mixlu_dposv(ctx, A, B, X, work) -> int:
     return _d_solve("mixlu_dposv", ctx, A, B, X, work)
+
+
+def mixlu_sgesv(ctx, A, B, X, work) -> int:
+    return _d_solve("mixlu_sgesv", ctx, A, B, X, work)
+
+
+def mixlu_report_read(ctx, d_reps, count: int) -> list:
+    """Copy count device reports (a device buffer, e.g. the batched d_reps)
+    to the host and decode them."""
+    out = (mixlu_report * max(count, 1))()
+    check(load().mixlu_report_read(ctx, _p(d_reps), count, out), "mixlu_report_read")
+    return [out[i].as_dict() for i in range(count)]
 
 
 def _factor(name, ctx, prec: int, A, work, opts=None):
@@ -436,3 +451,13 @@ class Solver:
 
     def dposv(self, A, B) -> Result:
         return self._d(OP_DPOSV, mixlu_dposv, A, B)
+
+    def sgesv(self, A, B) -> Result:
+        """FP32 LU and FP32 solves only (no refinement): the single-precision
+        accuracy baseline."""
+        A, B2, X, vec, layout = self._prep(A, B)
+        if layout != ROW_MAJOR:
+            raise ValueError("sgesv takes row-major A")
+        work = self.workspace(OP_SGESV, FP32, A.shape[0], B2.shape[1])
+        info = mixlu_sgesv(self.ctx, A, B2, X, work)
+        return Result(X.reshape(-1) if vec else X, {"info": info})

@@ -116,6 +116,7 @@ def test_batched_failures(solver):
     solver.run_batched(buf)
     torch.cuda.synchronize()
     reps = mixlu.reports_from_bytes(bytes(buf["reps"].cpu().numpy()))
+    assert mixlu.mixlu_report_read(solver.ctx, buf["reps"], len(As)) == reps
     assert reps[0]["converged"]
     assert reps[1]["info"] == 14 and reps[1]["prec"] == "fp64" and not reps[1]["converged"], reps[1]
     assert reps[2]["info"] == -1 and not reps[2]["converged"], reps[2]

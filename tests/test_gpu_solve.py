@@ -107,6 +107,64 @@ def test_dgesv_fp64_comparator(solver):
     assert np.abs(x - ref.x).max() / np.abs(ref.x).max() <= 1e-12 * 1e3
 
 
+@pytest.mark.parametrize("n,nrhs", [(1, 1), (65, 1), (700, 1), (300, 5)])
+def test_sgesv_fp32_baseline(solver, n, nrhs):
+    """The FP32-only solve (no refinement): equal bit for bit to getrf in FP32
+    without equilibration followed by getrs (the same factor and solve), and
+    as close to the oracle's unblocked FP32 LU solve as two FP32 solves of a
+    kappa = 1e2 system can be (each within about n u_s kappa of x)."""
+    import torch
+
+    from paper_0808_2794_amd import mixlu
+
+    A, b, _ = gen.prescribed_cond_system(n, 1e2, 500 + n, nrhs=nrhs)
+    _say(f"sgesv n={n} nrhs={nrhs}")
+    Ad, bd = _to_dev(A, b)
+    r = solver.sgesv(Ad, bd)
+    assert r.report["info"] == 0
+    x = r.x.cpu().numpy().reshape(n, nrhs)
+    o = mixlu.default_opts(equilibrate=0, fallback=0)
+    work = solver.workspace(mixlu.OP_GESV, mixlu.FP32, n, nrhs, o)
+    F, info = mixlu.mixlu_getrf(solver.ctx, mixlu.FP32, Ad, work, o)
+    assert info == 0 and F.lowp_status == 0
+    X2 = torch.empty_like(bd)
+    mixlu.mixlu_getrs(solver.ctx, F, bd, X2)
+    torch.cuda.synchronize()
+    assert np.array_equal(x, X2.cpu().numpy().reshape(n, nrhs))
+    LU, ipiv, _ = O.sgetrf(A)
+    xo = O.sgetrs(LU, ipiv, b).reshape(n, nrhs)
+    xt = np.linalg.solve(A, b).reshape(n, nrhs)
+    scale = np.abs(xt).max()
+    tol = max(n, 8) * 1e2 * 2.0 ** -24
+    assert np.abs(x - xt).max() / scale <= tol
+    assert np.abs(x - xo).max() / scale <= 2 * tol
+    # and FP32 accuracy is all it has: the refined solve is far closer
+    if n >= 65:
+        assert np.abs(x - xt).max() / scale > 1e-12
+
+
+def test_sgesv_info(solver):
+    """A zero column gives info = its index + 1; an entry beyond the FP32
+    range gives info = n + 1; X is left untouched in both cases."""
+    import torch
+
+    g = np.random.default_rng(5)
+    n = 150
+    A = g.uniform(-1, 1, (n, n))
+    A[:, 77] = 0.0
+    b = np.ones((n, 1))
+    Ad, bd = _to_dev(A, b)
+    _say("sgesv singular")
+    r = solver.sgesv(Ad, bd)
+    assert r.report["info"] == 78
+    A2 = g.uniform(-1, 1, (n, n))
+    A2[3, 9] = 1e300
+    Ad2, _ = _to_dev(A2, b)
+    _say("sgesv out of FP32 range")
+    r2 = solver.sgesv(Ad2, bd)
+    assert r2.report["info"] == n + 1
+
+
 def test_multiple_rhs(solver):
     n, nrhs = 400, 11
     A, b, _ = gen.prescribed_cond_system(n, 1e3, 41, nrhs=nrhs)
