@@ -7,14 +7,19 @@
 // Per system, inside one 512-thread workgroup (thread i owns row i):
 //   scales   row sums (||A||_inf), power-of-two row and column scales for
 //            BF16/FP16 factors, W = fl(R A C) into the workgroup's slot
-//   getrf    right-looking LU with partial pivoting, panels of 32 columns
+//   getrf    right-looking LU with partial pivoting, panels of 16 columns
 //            held one row per thread, pivot search by wave argmax; row
 //            interchanges outside the panel as one composed move list;
-//            U12 by forward substitution and the rank-32 trailing update in
+//            U12 by forward substitution and the rank-16 trailing update in
 //            column chunks staged through LDS (BF16/FP16 operands rounded
 //            before the FP32 multiply-add, as on the MFMA path)
-//   getrs    P, then blocked forward/backward substitution (64 x 64 diagonal
+//   getrs    P, then blocked forward/backward substitution (32 x 32 diagonal
 //            blocks in one wave, row updates by all threads)
+//
+// The factor is stored column-major in the workgroup's slot (element (i, j)
+// at j n + i): with one row per thread, every sweep over a column (panel
+// loads, trailing update, triangular-solve updates) is then a contiguous
+// access across the lanes of a wave.
 //   refine   r = b - A x in FP64 with the original A, stopping test,
 //            stall rule, x += z; FP64 LU of the same system on failure.
 #include <climits>
@@ -117,14 +122,30 @@ __device__ __noinline__ double sys_convert(const double *__restrict__ A, int lda
         const double v = sh.red[q][0];
         anorm = (v > anorm || v != v) ? v : anorm;
     }
-    // conversion, one thread per column (coalesced rows)
+    // conversion into the column-major W through a 32 x 64 LDS tile: rows of
+    // A are read along the lanes, columns of W written along the lanes
+    T *tile = reinterpret_cast<T *>(sh.sU);
+    constexpr int TR = 32, TC = 64, TP = TC + 1;
+    static_assert(TR * TP * sizeof(T) <= sizeof(BShared::sU), "conversion tile");
     int bad = 0;
-    for (int j = tid; j < n; j += kBT) {
-        const double cj = sh.C[j];
-        for (int i = 0; i < n; ++i) {
-            const T w = (T)(sh.R[i] * A[(size_t)i * lda + j] * cj);
-            if (!(fabs((double)w) <= 1.79769313486231570815e308)) ++bad;
-            W[(size_t)i * n + j] = w;
+    for (int I = 0; I < n; I += TR) {
+        for (int J = 0; J < n; J += TC) {
+            for (int e = tid; e < TR * TC; e += kBT) {
+                const int r = e / TC, c = e - r * TC;
+                const int i = I + r, j = J + c;
+                if (i < n && j < n) {
+                    const T w = (T)(sh.R[i] * A[(size_t)i * lda + j] * sh.C[j]);
+                    if (!(fabs((double)w) <= 1.79769313486231570815e308)) ++bad;
+                    tile[r * TP + c] = w;
+                }
+            }
+            __syncthreads();
+            for (int e = tid; e < TR * TC; e += kBT) {
+                const int c = e / TR, r = e - c * TR;
+                const int i = I + r, j = J + c;
+                if (i < n && j < n) W[(size_t)j * n + i] = tile[r * TP + c];
+            }
+            __syncthreads();
         }
     }
     if (bad) atomicAdd(&sh.overflow, bad);
@@ -133,11 +154,12 @@ __device__ __noinline__ double sys_convert(const double *__restrict__ A, int lda
 }
 
 // ------------------------------------------------------------------ getrf
-// In-place LU with partial pivoting of the n x n W (ld = n) by the whole
-// workgroup; pivots in sh.piv; the first zero / non-finite pivot column is
-// recorded in sh.bad.  tmp: scratch of 2 * kBB * n elements for row moves.
+// In-place LU with partial pivoting of the n x n column-major W (ld = n) by
+// the whole workgroup; pivots in sh.piv; the first zero / non-finite pivot
+// column is recorded in sh.bad.  The trailing update runs in chunks of
+// `chunk` (<= kBC) columns.
 template <typename T, int LP>
-__device__ __noinline__ void sys_getrf(T *__restrict__ W, int n, T *__restrict__ tmp, BShared &sh) {
+__device__ __noinline__ void sys_getrf(T *__restrict__ W, int n, int chunk, BShared &sh) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int row = tid;
     T *prow = reinterpret_cast<T *>(sh.prow);
@@ -145,14 +167,15 @@ __device__ __noinline__ void sys_getrf(T *__restrict__ W, int n, T *__restrict__
     T *sU = reinterpret_cast<T *>(sh.sU);
     T *L11 = reinterpret_cast<T *>(sh.L11);
     T *valw = reinterpret_cast<T *>(sh.valw);
+    constexpr int BB = kBB;
     constexpr int LP11 = kBB + 4;  // 16-byte aligned rows
-    for (int k = 0; k < n; k += kBB) {
-        const int w = n - k < kBB ? n - k : kBB;
-        T a[kBB];
+    for (int k = 0; k < n; k += BB) {
+        const int w = n - k < BB ? n - k : BB;
+        T a[BB];
         const bool mine = row >= k && row < n;
 #pragma unroll
-        for (int c = 0; c < kBB; ++c) a[c] = (mine && c < w) ? W[(size_t)row * n + k + c] : (T)0;
-        sfor<0, kBB>([&](auto J) {
+        for (int c = 0; c < BB; ++c) a[c] = (mine && c < w) ? W[(size_t)(k + c) * n + row] : (T)0;
+        sfor<0, BB>([&](auto J) {
             constexpr int j = decltype(J)::value;
             if (j < w) {
                 const int kj = k + j;
@@ -180,43 +203,43 @@ __device__ __noinline__ void sys_getrf(T *__restrict__ W, int n, T *__restrict__
                 }
                 if (row == p) {
 #pragma unroll
-                    for (int c = 0; c < kBB; ++c) prow[c] = a[c];
+                    for (int c = 0; c < BB; ++c) prow[c] = a[c];
                 }
                 if (row == kj) {
 #pragma unroll
-                    for (int c = 0; c < kBB; ++c) drow[c] = a[c];
+                    for (int c = 0; c < BB; ++c) drow[c] = a[c];
                 }
                 if (tid == 0) sh.piv[kj] = p;
                 __syncthreads();
                 if (row == kj) {
 #pragma unroll
-                    for (int c = 0; c < kBB; ++c) a[c] = prow[c];
+                    for (int c = 0; c < BB; ++c) a[c] = prow[c];
                 } else if (row == p) {
 #pragma unroll
-                    for (int c = 0; c < kBB; ++c) a[c] = drow[c];
+                    for (int c = 0; c < BB; ++c) a[c] = drow[c];
                 }
                 if (row > kj && row < n) {
                     const T pv = prow[j];
                     const T l = a[j] / pv;
                     a[j] = l;
 #pragma unroll
-                    for (int c = j + 1; c < kBB; ++c) a[c] -= l * prow[c];
+                    for (int c = j + 1; c < BB; ++c) a[c] -= l * prow[c];
                 }
             }
         });
         if (mine) {
 #pragma unroll
-            for (int c = 0; c < kBB; ++c)
-                if (c < w) W[(size_t)row * n + k + c] = a[c];
+            for (int c = 0; c < BB; ++c)
+                if (c < w) W[(size_t)(k + c) * n + row] = a[c];
         }
         // row-move composition
         for (int r = tid; r < n; r += kBT) sh.src[r] = r;
         if (tid == 0) sh.nmoves = 0;
         __syncthreads();
         // unit lower diagonal block for U12, read back from the stored panel
-        for (int e = tid; e < w * kBB; e += kBT) {
-            const int r = e / kBB, c = e - r * kBB;
-            L11[r * LP11 + c] = c < w ? W[(size_t)(k + r) * n + k + c] : (T)0;
+        for (int e = tid; e < w * BB; e += kBT) {
+            const int c = e / w, r = e - c * w;
+            L11[r * LP11 + c] = c < w ? W[(size_t)(k + c) * n + k + r] : (T)0;
         }
         if (tid == 0) {
             for (int j = 0; j < w; ++j) {
@@ -233,35 +256,38 @@ __device__ __noinline__ void sys_getrf(T *__restrict__ W, int n, T *__restrict__
             sh.mv_src[m] = sh.src[row];
         }
         __syncthreads();
-        const int nm = sh.nmoves;
-        // rows move in the columns left and right of the panel: thread t owns column t
-        const bool outside = tid < n && (tid < k || tid >= k + w);
-        if (outside) {
-            for (int m = 0; m < nm; ++m) tmp[(size_t)m * n + tid] = W[(size_t)sh.mv_src[m] * n + tid];
+        const int nm = sh.nmoves;  // <= 2 BB <= 64: one lane per move
+        // rows move in the columns left and right of the panel: one wave per
+        // column, lane m carries move m (all loads of a column before its
+        // stores, so cycles of moves are safe)
+        if (lane < nm) {
+            const int dst = sh.mv_dst[lane], srow = sh.mv_src[lane];
+            for (int col = wave; col < n; col += kBW) {
+                if (col >= k && col < k + w) continue;
+                T *wc = W + (size_t)col * n;
+                const T v = wc[srow];
+                wc[dst] = v;
+            }
         }
         __syncthreads();
-        if (outside) {
-            for (int m = 0; m < nm; ++m) W[(size_t)sh.mv_dst[m] * n + tid] = tmp[(size_t)m * n + tid];
-        }
-        __syncthreads();
-        // U12 = L11^{-1} A12 and A22 -= L21 U12, by chunks of kBC columns;
+        // U12 = L11^{-1} A12 and A22 -= L21 U12, by chunks of columns;
         // a[] now only serves as the L21 operand
 #pragma unroll
-        for (int c = 0; c < kBB; ++c) a[c] = lowp_round<LP>(a[c]);
-        for (int c0 = k + w; c0 < n; c0 += kBC) {
-            const int nc = n - c0 < kBC ? n - c0 : kBC;
+        for (int c = 0; c < BB; ++c) a[c] = lowp_round<LP>(a[c]);
+        for (int c0 = k + w; c0 < n; c0 += chunk) {
+            const int nc = n - c0 < chunk ? n - c0 : chunk;
             if (tid < nc) {
                 // column c0 + tid of U12 by forward substitution; the column
                 // lives in this thread's LDS row of sU while it is solved
-                const int col = c0 + tid;
+                T *wc = W + (size_t)(c0 + tid) * n + k;
                 T *xs = sU + tid * kSUP;
                 for (int r = 0; r < w; ++r) {
-                    T s = W[(size_t)(k + r) * n + col];
+                    T s = wc[r];
                     for (int q = 0; q < r; ++q) s -= L11[r * LP11 + q] * xs[q];
                     xs[r] = s;
-                    W[(size_t)(k + r) * n + col] = s;
+                    wc[r] = s;
                 }
-                for (int r = 0; r < kBB; ++r) {
+                for (int r = 0; r < BB; ++r) {
                     const T x = r < w ? xs[r] : (T)0;
                     if constexpr (LP == MIXLU_FP16)
                         if (fabs(x) > (T)65504) atomicAdd(&sh.overflow, 1);
@@ -270,12 +296,13 @@ __device__ __noinline__ void sys_getrf(T *__restrict__ W, int n, T *__restrict__
             }
             __syncthreads();
             if (row >= k + w && row < n) {
-                T *wr = W + (size_t)row * n + c0;
+                T *wr = W + (size_t)c0 * n + row;
+#pragma unroll(sizeof(T) == 8 ? 1 : 2)
                 for (int t = 0; t < nc; ++t) {
-                    T acc = wr[t];
+                    T acc = wr[(size_t)t * n];
 #pragma unroll
-                    for (int q = 0; q < kBB; ++q) acc -= a[q] * sU[t * kSUP + q];
-                    wr[t] = acc;
+                    for (int q = 0; q < BB; ++q) acc -= a[q] * sU[t * kSUP + q];
+                    wr[(size_t)t * n] = acc;
                 }
             }
             __syncthreads();
@@ -307,8 +334,8 @@ __device__ __noinline__ void sys_getrs(const T *__restrict__ W, int n, BShared &
     constexpr int DP = kBDiag + 1;
     auto stage = [&](int b0) {
         for (int e = tid; e < kBDiag * kBDiag; e += kBT) {
-            const int r = e / kBDiag, c = e - r * kBDiag;
-            sd[r * DP + c] = (b0 + r < n && b0 + c < n) ? W[(size_t)(b0 + r) * n + b0 + c] : (T)0;
+            const int c = e / kBDiag, r = e - c * kBDiag;
+            sd[r * DP + c] = (b0 + r < n && b0 + c < n) ? W[(size_t)(b0 + c) * n + b0 + r] : (T)0;
         }
         __syncthreads();
     };
@@ -318,7 +345,7 @@ __device__ __noinline__ void sys_getrs(const T *__restrict__ W, int n, BShared &
         if (tid < kBDiag) {
             const int i = b0 + lane;
             T yl = i < n ? y[i] : (T)0;
-#pragma unroll
+#pragma unroll 4
             for (int q = 0; q < kBDiag; ++q) {
                 const T yq = readlane_t(yl, q);
                 if (lane > q) yl -= sd[lane * DP + q] * yq;
@@ -329,8 +356,9 @@ __device__ __noinline__ void sys_getrs(const T *__restrict__ W, int n, BShared &
         const int e = n - b0 < kBDiag ? n - b0 : kBDiag;
         for (int i = b0 + kBDiag + tid; i < n; i += kBT) {
             T s = y[i];
-            const T *wr = W + (size_t)i * n + b0;
-            for (int q = 0; q < e; ++q) s -= wr[q] * y[b0 + q];
+            const T *wc = W + (size_t)b0 * n + i;
+#pragma unroll 8
+            for (int q = 0; q < e; ++q) s -= wc[(size_t)q * n] * y[b0 + q];
             y[i] = s;
         }
         __syncthreads();
@@ -341,7 +369,7 @@ __device__ __noinline__ void sys_getrs(const T *__restrict__ W, int n, BShared &
         if (tid < kBDiag) {
             const int i = b0 + lane;
             T yl = i < n ? y[i] : (T)0;
-#pragma unroll
+#pragma unroll 4
             for (int q = kBDiag - 1; q >= 0; --q) {
                 if (b0 + q < n) {
                     const T yq = readlane_t(yl, q) / sd[q * DP + q];
@@ -355,8 +383,9 @@ __device__ __noinline__ void sys_getrs(const T *__restrict__ W, int n, BShared &
         const int e = n - b0 < kBDiag ? n - b0 : kBDiag;
         for (int i = tid; i < b0; i += kBT) {
             T s = y[i];
-            const T *wr = W + (size_t)i * n + b0;
-            for (int q = 0; q < e; ++q) s -= wr[q] * y[b0 + q];
+            const T *wc = W + (size_t)b0 * n + i;
+#pragma unroll 8
+            for (int q = 0; q < e; ++q) s -= wc[(size_t)q * n] * y[b0 + q];
             y[i] = s;
         }
         __syncthreads();
@@ -475,6 +504,7 @@ struct BatchArgs {
     unsigned char *slots;
     size_t slot_bytes;
     int fallback;
+    int chunk;
 };
 
 // Solve one system with the factor in precision T (LP: trailing operand
@@ -498,7 +528,6 @@ __device__ void sys_solve(const BatchArgs &g, int s, unsigned char *slot, BShare
         return;
     }
     T *W = reinterpret_cast<T *>(slot);
-    T *tmp = reinterpret_cast<T *>(slot + (size_t)kBatchedNmax * kBatchedNmax * 8);
     if (tid == 0) {
         sh.bad = INT_MAX;
         sh.overflow = 0;
@@ -506,7 +535,7 @@ __device__ void sys_solve(const BatchArgs &g, int s, unsigned char *slot, BShare
     __syncthreads();
     const double anorm = sys_convert<T>(A, lda, n, g.equil, W, sh);
     rep.anorm = anorm;
-    if (sh.overflow == 0) sys_getrf<T, LP>(W, n, tmp, sh);
+    if (sh.overflow == 0) sys_getrf<T, LP>(W, n, g.chunk, sh);
     int reason = 0;
     if (sh.overflow) reason = -2;
     else if (sh.bad != INT_MAX) reason = sizeof(T) == 8 ? -1 : -3;
@@ -541,29 +570,45 @@ __device__ void sys_solve(const BatchArgs &g, int s, unsigned char *slot, BShare
         if (tid == 0) g.rep[s] = rep;
         return;
     }
+    // failure: the report says why; with a low-precision factor and the
+    // fallback on, k_batched_fallback finishes the system in FP64
     rep.iter = reason;
-    if (sizeof(T) == 8 || !g.fallback) {
-        if (reason == -1) rep.info = sh.bad;
-        if (tid == 0) g.rep[s] = rep;
-        return;
-    }
-    // FP64 fallback in the same slot
+    if (reason == -1) rep.info = sh.bad;
+    if (tid == 0) g.rep[s] = rep;
+}
+
+// True when system s failed in the low precision and awaits the FP64 path.
+__device__ __forceinline__ bool needs_fallback(const mixlu_report &r) {
+    return r.converged == 0 && r.iter < 0 && r.prec != MIXLU_FP64;
+}
+
+// FP64 factorization and FP64 refinement of system s (Section 4: the
+// double-precision solve used when refinement with the low-precision factor
+// fails), in the workgroup's slot; completes the system's report.
+__device__ void sys_fallback(const BatchArgs &g, int s, unsigned char *slot, BShared &sh) {
+    const int tid = threadIdx.x;
+    const int n = g.n[s];
+    const double *A = g.A[s];
+    const int lda = g.lda ? g.lda[s] : n;
+    const double *B = g.B[s];
+    double *X = g.X[s];
+    mixlu_report rep = g.rep[s];
+    const double anorm = rep.anorm;
     double *W64 = reinterpret_cast<double *>(slot);
-    double *tmp64 = reinterpret_cast<double *>(slot + (size_t)kBatchedNmax * kBatchedNmax * 8);
     if (tid == 0) {
         sh.bad = INT_MAX;
         sh.overflow = 0;
     }
     __syncthreads();
     sys_convert<double>(A, lda, n, 0, W64, sh);
-    sys_getrf<double, 0>(W64, n, tmp64, sh);
+    sys_getrf<double, 0>(W64, n, g.chunk, sh);
     rep.prec = MIXLU_FP64;
     if (sh.bad != INT_MAX) {
         rep.info = sh.bad;
         if (tid == 0) g.rep[s] = rep;
         return;
     }
-    rn_all = xn_all = 0.0;
+    double rn_all = 0.0, xn_all = 0.0;
     int fit = 0, conv = 1;
     for (int c = 0; c < g.nrhs; ++c) {
         for (int i = tid; i < n; i += kBT) sh.r[i] = B[(size_t)i * g.nrhs + c];
@@ -589,8 +634,7 @@ __device__ void sys_solve(const BatchArgs &g, int s, unsigned char *slot, BShare
 }
 
 template <typename T, int LP>
-__global__ __launch_bounds__(kBT) void k_batched(BatchArgs g) {
-    __shared__ BShared sh;
+__device__ __forceinline__ void batched_loop(const BatchArgs &g, BShared &sh) {
     unsigned char *slot = g.slots + (size_t)blockIdx.x * g.slot_bytes;
     for (;;) {
         if (threadIdx.x == 0) {
@@ -602,6 +646,52 @@ __global__ __launch_bounds__(kBT) void k_batched(BatchArgs g) {
         __syncthreads();
         if (s < 0) return;  // every workgroup leaves once the queue is empty
         sys_solve<T, LP>(g, s, slot, sh);
+        __syncthreads();
+    }
+}
+
+// FP32-storage factors: two workgroups per CU, so at most 128 VGPRs (4
+// waves per SIMD), which these code paths meet without spilling.
+template <int LP>
+__global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k_batched(
+    BatchArgs g) {
+    __shared__ BShared sh;
+    batched_loop<float, LP>(g, sh);
+}
+
+// FP64 factors (the FP64 comparator): the FP64 LU needs more registers; one
+// workgroup per CU.
+__global__ __launch_bounds__(kBT) void k_batched_fp64(BatchArgs g) {
+    __shared__ BShared sh;
+    batched_loop<double, 0>(g, sh);
+}
+
+// Second pass over the same queue (its own counter): the systems whose
+// low-precision solve failed get the FP64 path; the others are skipped.  A
+// launch of its own, so the registers of the FP64 code do not limit the
+// occupancy of the low-precision pass.
+__global__ __launch_bounds__(kBT) void k_batched_fallback(BatchArgs g) {
+    __shared__ BShared sh;
+    unsigned char *slot = g.slots + (size_t)blockIdx.x * g.slot_bytes;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            int sys = -1;
+            for (;;) {
+                const int q = atomicAdd(g.counter + 1, 1);
+                if (q >= g.batch) break;
+                const int cand = g.order[q];
+                if (needs_fallback(g.rep[cand])) {
+                    sys = cand;
+                    break;
+                }
+            }
+            sh.sys = sys;
+        }
+        __syncthreads();
+        const int s = sh.sys;
+        __syncthreads();
+        if (s < 0) return;
+        sys_fallback(g, s, slot, sh);
         __syncthreads();
     }
 }
@@ -625,7 +715,8 @@ __global__ __launch_bounds__(1024) void k_batch_order(int batch, const int *__re
             start[b] = acc;
             acc += cnt[b];
         }
-        *counter = 0;
+        counter[0] = 0;
+        counter[1] = 0;
     }
     __syncthreads();
     for (int i = threadIdx.x; i < batch; i += 1024) {
@@ -634,10 +725,7 @@ __global__ __launch_bounds__(1024) void k_batch_order(int batch, const int *__re
     }
 }
 
-size_t batched_slot_bytes() {
-    return align_up((size_t)kBatchedNmax * kBatchedNmax * 8 + (size_t)2 * kBB * kBatchedNmax * 8,
-                    256);
-}
+size_t batched_slot_bytes() { return align_up((size_t)kBatchedNmax * kBatchedNmax * 8, 256); }
 
 hipError_t launch_batched(int prec, int batch, int nrhs, int equil, int itermax, double stall,
                           int fallback, const int *n, const double *const *A, const int *lda,
@@ -648,15 +736,18 @@ hipError_t launch_batched(int prec, int batch, int nrhs, int equil, int itermax,
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     BatchArgs g{batch, nrhs, equil, itermax, stall, n, A, lda, B, X, rep, order, counter,
-                static_cast<unsigned char *>(slots), batched_slot_bytes(), fallback};
+                static_cast<unsigned char *>(slots), batched_slot_bytes(), fallback, kBC};
     const int grid = batch < nslots ? batch : nslots;
     switch (prec) {
-        case MIXLU_FP32: k_batched<float, 0><<<grid, kBT, 0, s>>>(g); break;
-        case MIXLU_FP16: k_batched<float, MIXLU_FP16><<<grid, kBT, 0, s>>>(g); break;
-        case MIXLU_BF16: k_batched<float, MIXLU_BF16><<<grid, kBT, 0, s>>>(g); break;
-        case MIXLU_FP64: k_batched<double, 0><<<grid, kBT, 0, s>>>(g); break;
+        case MIXLU_FP32: k_batched<0><<<grid, kBT, 0, s>>>(g); break;
+        case MIXLU_FP16: k_batched<MIXLU_FP16><<<grid, kBT, 0, s>>>(g); break;
+        case MIXLU_BF16: k_batched<MIXLU_BF16><<<grid, kBT, 0, s>>>(g); break;
+        case MIXLU_FP64: k_batched_fp64<<<grid, kBT, 0, s>>>(g); break;
         default: return hipErrorInvalidValue;
     }
+    e = hipGetLastError();
+    if (e != hipSuccess || prec == MIXLU_FP64 || !fallback) return e;
+    k_batched_fallback<<<grid, kBT, 0, s>>>(g);
     return hipGetLastError();
 }
 
