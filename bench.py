@@ -306,6 +306,9 @@ def run_batched(args, prec):
     dB = [torch.from_numpy(b).cuda() for b in bs]
     buf = solver.batched_buffers(dA, dB, prec)
     sync()
+    # tile sets chosen by the autotuner on this batch (outside the timed region)
+    tiles, tile_ms = solver.tune_batched(buf)
+    sync()
     for _ in range(args.warmup):
         solver.run_batched(buf)
     mixlu.mixlu_profile_enable(solver.ctx, True)
@@ -323,6 +326,7 @@ def run_batched(args, prec):
     comp = {}
     if args.compare_steps > 0:
         buf64 = solver.batched_buffers(dA, dB, "fp64")
+        comp["mixlu_batched_fp64_tiles"], _ = solver.tune_batched(buf64)
         solver.run_batched(buf64)
         comp["mixlu_batched_fp64_ms"], _ = time_calls(lambda: solver.run_batched(buf64),
                                                       args.compare_steps)
@@ -353,7 +357,10 @@ def run_batched(args, prec):
     return ms, kst, cpu, comp, {
         "config": {"workload": f"batched_{count}_systems_n16to512_kappa1e1to1e5_nrhs1",
                    "systems": count, "sum_n3": float(sum(a.shape[0] ** 3 for a in As)),
-                   "seed": seed, "factor_precision": prec, "refinement": "fp64"},
+                   "seed": seed, "factor_precision": prec, "refinement": "fp64",
+                   "tiles": tiles,
+                   "tile_candidates_ms": {f"panel{p}_chunk{c}_groups{g}": round(v, 3)
+                                          for (p, c, g), v in tile_ms.items()}},
         "solve": {"converged": conv, "systems": count, "fp64_fallbacks": fb,
                   "max_fwd_err_vs_x_true": fwd}}
 

@@ -52,6 +52,8 @@ extern "C" {
 #define MIXLU_ERR_UNSUPPORTED_ARCH 4
 #define MIXLU_ERR_DEVICE_TIMEOUT 5  /* a bounded cross-workgroup wait on the
                                        device gave up (results invalid)   */
+#define MIXLU_ERR_CAPTURING 6       /* a call that synchronizes was made on
+                                       a stream under HIP graph capture   */
 
 /* Human-readable name of a status code (static string, never NULL). */
 const char *mixlu_status_string(int status);
@@ -297,6 +299,39 @@ int mixlu_dxgesv_batched(mixlu_ctx_t ctx, int prec, int batch, const int *d_n,
                          const double *const *d_B, double *const *d_X, int nrhs,
                          void *work, size_t lwork, const mixlu_opts *o,
                          mixlu_report *d_reps);
+
+/* Tile choices of the batched launch: the panel width of each system's LU
+   (8 or 16 columns), the column chunk of its trailing update (32, 64 or
+   128) and the number of persistent workgroups per compute unit (1 or 2).
+   The context keeps one set per precision; mixlu_dxgesv_batched uses it.
+   Defaults: panel 16, chunk 128, groups 2 (FP64: groups 1). */
+typedef struct {
+    int panel;
+    int chunk;
+    int groups;
+    int tuned;  /* 1 when the set came from mixlu_batched_tune */
+} mixlu_batched_tiles;
+
+/* Autotuner: runs the batched solve of the given batch (same arguments as
+   mixlu_dxgesv_batched) once with every candidate tile set, timed with HIP
+   events on the context's stream (each candidate once untimed, then the
+   faster of two timed runs), and keeps the fastest set in the context for
+   prec.  The last run leaves X and d_reps as a normal call would (each
+   candidate solves the same systems completely).  best (host, may be NULL)
+   receives the chosen set; ms (host, may be NULL) the time of candidate i
+   for i < max_ms, in the order panel {16, 8} x chunk {128, 64, 32} x groups
+   {2, 1}.  Synchronizes; returns MIXLU_ERR_CAPTURING if the stream is being
+   captured (tune before capturing, then capture the tuned launch). */
+int mixlu_batched_tune(mixlu_ctx_t ctx, int prec, int batch, const int *d_n,
+                       const double *const *d_A, const int *d_lda,
+                       const double *const *d_B, double *const *d_X, int nrhs,
+                       void *work, size_t lwork, const mixlu_opts *o,
+                       mixlu_report *d_reps, mixlu_batched_tiles *best,
+                       float *ms, int max_ms);
+/* Read or set the tile set the context uses for prec (set: -3 if the set is
+   not one of the candidates). */
+int mixlu_batched_get_tiles(mixlu_ctx_t ctx, int prec, mixlu_batched_tiles *t);
+int mixlu_batched_set_tiles(mixlu_ctx_t ctx, int prec, const mixlu_batched_tiles *t);
 
 /* Copy count reports from device memory (d, as filled by
    mixlu_dxgesv_batched) to host memory h, in order on the context's stream;

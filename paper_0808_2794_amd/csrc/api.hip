@@ -46,6 +46,10 @@ struct mixlu_ctx_s {
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     double *hbuf = nullptr;  // pinned host mirror of the norms / status
     size_t hbuf_bytes = 0;
+    int num_cu = 256;
+    mixlu::BatchedTiles btiles[5] = {{16, 128, 2}, {16, 128, 2}, {16, 128, 2}, {16, 128, 2},
+                                     {16, 128, 1}};  // by mixlu_prec; FP64 last
+    int btuned[5] = {0, 0, 0, 0, 0};
     Prof prof;
 };
 
@@ -812,6 +816,9 @@ mixlu_opts opts_or_default(const mixlu_opts *o) {
     return o ? *o : d;
 }
 
+// Index of a precision's batched tile set in the context.
+int tile_slot(int prec) { return prec == MIXLU_FP64 ? 4 : (prec >= 0 && prec < 4 ? prec : 0); }
+
 int equil_for(int prec, const mixlu_opts &o) {
     if (o.equilibrate >= 0) return o.equilibrate ? 1 : 0;
     return is_lowp(prec) ? 1 : 0;
@@ -1007,6 +1014,7 @@ const char *mixlu_status_string(int status) {
         case MIXLU_ERR_NOT_IMPLEMENTED: return "MIXLU_ERR_NOT_IMPLEMENTED";
         case MIXLU_ERR_UNSUPPORTED_ARCH: return "MIXLU_ERR_UNSUPPORTED_ARCH: needs gfx950";
         case MIXLU_ERR_DEVICE_TIMEOUT: return "MIXLU_ERR_DEVICE_TIMEOUT: a device wait gave up";
+        case MIXLU_ERR_CAPTURING: return "MIXLU_ERR_CAPTURING: synchronizing call during capture";
         default: return status < 0 ? "invalid argument" : "unknown status";
     }
 }
@@ -1033,6 +1041,7 @@ int mixlu_create(mixlu_ctx_t *ctx, void *stream) {
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return MIXLU_ERR_UNSUPPORTED_ARCH;
     auto *c = new mixlu_ctx_s;
     c->device = dev;
+    c->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     c->stream = static_cast<hipStream_t>(stream);
     *ctx = c;
     return MIXLU_OK;
@@ -1285,7 +1294,103 @@ int mixlu_dxgesv_batched(mixlu_ctx_t ctx, int prec, int batch, const int *d_n,
     ProfScope ps(PC_BATCH, 0.0, 0.0, ctx->stream);
     HIPCK(launch_batched(prec, batch, nrhs, equil_for(prec, op_), op_.itermax, op_.stall,
                          prec != MIXLU_FP64 && op_.fallback, d_n, d_A, d_lda, d_B, d_X, d_reps,
-                         order, counter, slots, nslots, ctx->stream));
+                         order, counter, slots, nslots, ctx->btiles[tile_slot(prec)],
+                         ctx->num_cu, ctx->stream));
+    return MIXLU_OK;
+}
+
+int mixlu_batched_get_tiles(mixlu_ctx_t ctx, int prec, mixlu_batched_tiles *t) {
+    if (!ctx) return -1;
+    if (!prec_valid(prec) || prec == MIXLU_FP8) return -2;
+    if (!t) return -3;
+    const BatchedTiles &b = ctx->btiles[tile_slot(prec)];
+    t->panel = b.panel;
+    t->chunk = b.chunk;
+    t->groups = b.groups;
+    t->tuned = ctx->btuned[tile_slot(prec)];
+    return MIXLU_OK;
+}
+
+int mixlu_batched_set_tiles(mixlu_ctx_t ctx, int prec, const mixlu_batched_tiles *t) {
+    if (!ctx) return -1;
+    if (!prec_valid(prec) || prec == MIXLU_FP8) return -2;
+    if (!t) return -3;
+    const BatchedTiles b{t->panel, t->chunk, t->groups};
+    if (!batched_tiles_valid(b)) return -3;
+    ctx->btiles[tile_slot(prec)] = b;
+    ctx->btuned[tile_slot(prec)] = t->tuned ? 1 : 0;
+    return MIXLU_OK;
+}
+
+int mixlu_batched_tune(mixlu_ctx_t ctx, int prec, int batch, const int *d_n,
+                       const double *const *d_A, const int *d_lda, const double *const *d_B,
+                       double *const *d_X, int nrhs, void *work, size_t lwork,
+                       const mixlu_opts *o, mixlu_report *d_reps, mixlu_batched_tiles *best,
+                       float *ms, int max_ms) {
+    if (!ctx) return -1;
+    if (!prec_valid(prec) || prec == MIXLU_FP8) return -2;
+    if (max_ms < 0 || (max_ms > 0 && !ms)) return -16;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIPCK(hipStreamIsCapturing(ctx->stream, &cap));
+    if (cap != hipStreamCaptureStatusNone) return MIXLU_ERR_CAPTURING;
+    const int slot = tile_slot(prec);
+    const BatchedTiles saved = ctx->btiles[slot];
+    const int saved_tuned = ctx->btuned[slot];
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return MIXLU_ERR_HIP;
+    }
+    int rc = MIXLU_OK;
+    float best_ms = 0.0f;
+    BatchedTiles best_t = saved;
+    int idx = 0;
+    for (int panel : {16, 8}) {
+        for (int chunk : {128, 64, 32}) {
+            for (int groups : {2, 1}) {
+                ctx->btiles[slot] = BatchedTiles{panel, chunk, groups};
+                float t_min = 0.0f;
+                for (int rep = 0; rep < 3 && rc == MIXLU_OK; ++rep) {
+                    if (hipEventRecord(e0, ctx->stream) != hipSuccess) rc = MIXLU_ERR_HIP;
+                    if (rc == MIXLU_OK)
+                        rc = mixlu_dxgesv_batched(ctx, prec, batch, d_n, d_A, d_lda, d_B, d_X,
+                                                  nrhs, work, lwork, o, d_reps);
+                    if (rc == MIXLU_OK && (hipEventRecord(e1, ctx->stream) != hipSuccess ||
+                                           hipEventSynchronize(e1) != hipSuccess))
+                        rc = MIXLU_ERR_HIP;
+                    float t = 0.0f;
+                    if (rc == MIXLU_OK && hipEventElapsedTime(&t, e0, e1) != hipSuccess)
+                        rc = MIXLU_ERR_HIP;
+                    if (rep == 1 || (rep == 2 && t < t_min)) t_min = t;  // run 0 is untimed
+                }
+                if (rc != MIXLU_OK) break;
+                if (idx < max_ms) ms[idx] = t_min;
+                if (idx == 0 || t_min < best_ms) {
+                    best_ms = t_min;
+                    best_t = ctx->btiles[slot];
+                }
+                ++idx;
+            }
+            if (rc != MIXLU_OK) break;
+        }
+        if (rc != MIXLU_OK) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != MIXLU_OK) {
+        ctx->btiles[slot] = saved;
+        ctx->btuned[slot] = saved_tuned;
+        return rc;
+    }
+    ctx->btiles[slot] = best_t;
+    ctx->btuned[slot] = 1;
+    if (best) {
+        best->panel = best_t.panel;
+        best->chunk = best_t.chunk;
+        best->groups = best_t.groups;
+        best->tuned = 1;
+    }
     return MIXLU_OK;
 }
 

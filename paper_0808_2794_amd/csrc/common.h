@@ -279,10 +279,18 @@ hipError_t launch_chol_to_lu(T *W, int ldw, int npad, const T *diag, hipStream_t
 
 // a10: batched solves (k_batched.hip)
 size_t batched_slot_bytes();
+// Tile choices of the batched launch (the autotuner's search space): panel
+// width of the per-system LU (8 or 16), trailing-update chunk (32, 64 or
+// 128 columns) and persistent workgroups per CU (1 or 2).
+struct BatchedTiles {
+    int panel, chunk, groups;
+};
+bool batched_tiles_valid(const BatchedTiles &t);
 hipError_t launch_batched(int prec, int batch, int nrhs, int equil, int itermax, double stall,
                           int fallback, const int *n, const double *const *A, const int *lda,
                           const double *const *B, double *const *X, mixlu_report *rep,
-                          int *order, int *counter, void *slots, int nslots, hipStream_t s);
+                          int *order, int *counter, void *slots, int nslots,
+                          const BatchedTiles &t, int num_cu, hipStream_t s);
 
 // a4-a8: solves and refinement (k_solve.hip)
 template <typename Tw>

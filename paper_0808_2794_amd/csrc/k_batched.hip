@@ -156,10 +156,11 @@ __device__ __noinline__ double sys_convert(const double *__restrict__ A, int lda
 // ------------------------------------------------------------------ getrf
 // In-place LU with partial pivoting of the n x n column-major W (ld = n) by
 // the whole workgroup; pivots in sh.piv; the first zero / non-finite pivot
-// column is recorded in sh.bad.  The trailing update runs in chunks of
-// `chunk` (<= kBC) columns.
-template <typename T, int LP>
+// column is recorded in sh.bad.  Panels are BB columns wide; the trailing
+// update runs in chunks of `chunk` (<= kBC) columns.
+template <typename T, int LP, int BB>
 __device__ __noinline__ void sys_getrf(T *__restrict__ W, int n, int chunk, BShared &sh) {
+    static_assert(BB <= kBB && 2 * BB <= 64, "panel width");
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int row = tid;
     T *prow = reinterpret_cast<T *>(sh.prow);
@@ -167,7 +168,6 @@ __device__ __noinline__ void sys_getrf(T *__restrict__ W, int n, int chunk, BSha
     T *sU = reinterpret_cast<T *>(sh.sU);
     T *L11 = reinterpret_cast<T *>(sh.L11);
     T *valw = reinterpret_cast<T *>(sh.valw);
-    constexpr int BB = kBB;
     constexpr int LP11 = kBB + 4;  // 16-byte aligned rows
     for (int k = 0; k < n; k += BB) {
         const int w = n - k < BB ? n - k : BB;
@@ -509,7 +509,7 @@ struct BatchArgs {
 
 // Solve one system with the factor in precision T (LP: trailing operand
 // rounding); falls back to FP64 inside the same slot.
-template <typename T, int LP>
+template <typename T, int LP, int BB>
 __device__ void sys_solve(const BatchArgs &g, int s, unsigned char *slot, BShared &sh) {
     const int tid = threadIdx.x;
     const int n = g.n[s];
@@ -535,7 +535,7 @@ __device__ void sys_solve(const BatchArgs &g, int s, unsigned char *slot, BShare
     __syncthreads();
     const double anorm = sys_convert<T>(A, lda, n, g.equil, W, sh);
     rep.anorm = anorm;
-    if (sh.overflow == 0) sys_getrf<T, LP>(W, n, g.chunk, sh);
+    if (sh.overflow == 0) sys_getrf<T, LP, BB>(W, n, g.chunk, sh);
     int reason = 0;
     if (sh.overflow) reason = -2;
     else if (sh.bad != INT_MAX) reason = sizeof(T) == 8 ? -1 : -3;
@@ -601,7 +601,7 @@ __device__ void sys_fallback(const BatchArgs &g, int s, unsigned char *slot, BSh
     }
     __syncthreads();
     sys_convert<double>(A, lda, n, 0, W64, sh);
-    sys_getrf<double, 0>(W64, n, g.chunk, sh);
+    sys_getrf<double, 0, kBB>(W64, n, g.chunk, sh);
     rep.prec = MIXLU_FP64;
     if (sh.bad != INT_MAX) {
         rep.info = sh.bad;
@@ -633,7 +633,7 @@ __device__ void sys_fallback(const BatchArgs &g, int s, unsigned char *slot, BSh
     if (tid == 0) g.rep[s] = rep;
 }
 
-template <typename T, int LP>
+template <typename T, int LP, int BB>
 __device__ __forceinline__ void batched_loop(const BatchArgs &g, BShared &sh) {
     unsigned char *slot = g.slots + (size_t)blockIdx.x * g.slot_bytes;
     for (;;) {
@@ -645,25 +645,26 @@ __device__ __forceinline__ void batched_loop(const BatchArgs &g, BShared &sh) {
         const int s = sh.sys;
         __syncthreads();
         if (s < 0) return;  // every workgroup leaves once the queue is empty
-        sys_solve<T, LP>(g, s, slot, sh);
+        sys_solve<T, LP, BB>(g, s, slot, sh);
         __syncthreads();
     }
 }
 
 // FP32-storage factors: two workgroups per CU, so at most 128 VGPRs (4
 // waves per SIMD), which these code paths meet without spilling.
-template <int LP>
+template <int LP, int BB>
 __global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k_batched(
     BatchArgs g) {
     __shared__ BShared sh;
-    batched_loop<float, LP>(g, sh);
+    batched_loop<float, LP, BB>(g, sh);
 }
 
 // FP64 factors (the FP64 comparator): the FP64 LU needs more registers; one
 // workgroup per CU.
+template <int BB>
 __global__ __launch_bounds__(kBT) void k_batched_fp64(BatchArgs g) {
     __shared__ BShared sh;
-    batched_loop<double, 0>(g, sh);
+    batched_loop<double, 0, BB>(g, sh);
 }
 
 // Second pass over the same queue (its own counter): the systems whose
@@ -727,25 +728,45 @@ __global__ __launch_bounds__(1024) void k_batch_order(int batch, const int *__re
 
 size_t batched_slot_bytes() { return align_up((size_t)kBatchedNmax * kBatchedNmax * 8, 256); }
 
+bool batched_tiles_valid(const BatchedTiles &t) {
+    return (t.panel == 8 || t.panel == 16) && (t.chunk == 32 || t.chunk == 64 || t.chunk == 128) &&
+           (t.groups == 1 || t.groups == 2);
+}
+
+template <int LP>
+hipError_t launch_lowp(int panel, int grid, const BatchArgs &g, hipStream_t s) {
+    if (panel == 8) k_batched<LP, 8><<<grid, kBT, 0, s>>>(g);
+    else k_batched<LP, 16><<<grid, kBT, 0, s>>>(g);
+    return hipGetLastError();
+}
+
 hipError_t launch_batched(int prec, int batch, int nrhs, int equil, int itermax, double stall,
                           int fallback, const int *n, const double *const *A, const int *lda,
                           const double *const *B, double *const *X, mixlu_report *rep,
-                          int *order, int *counter, void *slots, int nslots, hipStream_t s) {
+                          int *order, int *counter, void *slots, int nslots,
+                          const BatchedTiles &t, int num_cu, hipStream_t s) {
     if (batch <= 0) return hipSuccess;
+    if (!batched_tiles_valid(t)) return hipErrorInvalidValue;
     k_batch_order<<<dim3(1), dim3(1024), 0, s>>>(batch, n, order, counter);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     BatchArgs g{batch, nrhs, equil, itermax, stall, n, A, lda, B, X, rep, order, counter,
-                static_cast<unsigned char *>(slots), batched_slot_bytes(), fallback, kBC};
-    const int grid = batch < nslots ? batch : nslots;
+                static_cast<unsigned char *>(slots), batched_slot_bytes(), fallback, t.chunk};
+    // persistent workgroups: `groups` per CU, at most one per slot and system
+    int grid = t.groups * (num_cu > 0 ? num_cu : 256);
+    if (grid > nslots) grid = nslots;
+    if (grid > batch) grid = batch;
     switch (prec) {
-        case MIXLU_FP32: k_batched<0><<<grid, kBT, 0, s>>>(g); break;
-        case MIXLU_FP16: k_batched<MIXLU_FP16><<<grid, kBT, 0, s>>>(g); break;
-        case MIXLU_BF16: k_batched<MIXLU_BF16><<<grid, kBT, 0, s>>>(g); break;
-        case MIXLU_FP64: k_batched_fp64<<<grid, kBT, 0, s>>>(g); break;
+        case MIXLU_FP32: e = launch_lowp<0>(t.panel, grid, g, s); break;
+        case MIXLU_FP16: e = launch_lowp<MIXLU_FP16>(t.panel, grid, g, s); break;
+        case MIXLU_BF16: e = launch_lowp<MIXLU_BF16>(t.panel, grid, g, s); break;
+        case MIXLU_FP64:
+            if (t.panel == 8) k_batched_fp64<8><<<grid, kBT, 0, s>>>(g);
+            else k_batched_fp64<16><<<grid, kBT, 0, s>>>(g);
+            e = hipGetLastError();
+            break;
         default: return hipErrorInvalidValue;
     }
-    e = hipGetLastError();
     if (e != hipSuccess || prec == MIXLU_FP64 || !fallback) return e;
     k_batched_fallback<<<grid, kBT, 0, s>>>(g);
     return hipGetLastError();

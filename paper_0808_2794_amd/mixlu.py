@@ -55,6 +55,19 @@ class mixlu_factor(ctypes.Structure):
                 ("lwork", ctypes.c_size_t), ("off", ctypes.c_size_t * 16)]
 
 
+class mixlu_batched_tiles(ctypes.Structure):
+    _fields_ = [("panel", ctypes.c_int), ("chunk", ctypes.c_int), ("groups", ctypes.c_int),
+                ("tuned", ctypes.c_int)]
+
+    def as_dict(self) -> dict:
+        return {"panel": self.panel, "chunk": self.chunk, "groups": self.groups,
+                "tuned": bool(self.tuned)}
+
+
+# candidate order of mixlu_batched_tune's timings
+TILE_CANDIDATES = [(p, c, g) for p in (16, 8) for c in (128, 64, 32) for g in (2, 1)]
+
+
 class mixlu_kstat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char_p), ("launches", ctypes.c_longlong),
                 ("ms", ctypes.c_double), ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
@@ -65,7 +78,8 @@ EXPORTS = ("mixlu_status_string", "mixlu_default_opts", "mixlu_create", "mixlu_d
            "mixlu_getrs", "mixlu_refine", "mixlu_dxgesv", "mixlu_dxposv", "mixlu_dgesv",
            "mixlu_dposv", "mixlu_outer_update", "mixlu_batched_workspace_size",
            "mixlu_dxgesv_batched", "mixlu_profile_enable", "mixlu_profile_read",
-           "mixlu_sgesv", "mixlu_report_read")
+           "mixlu_sgesv", "mixlu_report_read", "mixlu_batched_tune", "mixlu_batched_get_tiles",
+           "mixlu_batched_set_tiles")
 
 _lib = None
 
@@ -101,6 +115,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "mixlu_profile_read": ([P, P, I, P], I),
         "mixlu_sgesv": ([P, I, I, P, I, P, I, P, I, P, S, P], I),
         "mixlu_report_read": ([P, P, I, P], I),
+        "mixlu_batched_tune": ([P, I, I, P, P, P, P, P, I, P, S, P, P, P, P, I], I),
+        "mixlu_batched_get_tiles": ([P, I, P], I),
+        "mixlu_batched_set_tiles": ([P, I, P], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -303,6 +320,33 @@ def mixlu_dxgesv_batched(ctx, prec: int, d_n, d_A, d_lda, d_B, d_X, nrhs: int, w
           "mixlu_dxgesv_batched")
 
 
+def mixlu_batched_tune(ctx, prec: int, d_n, d_A, d_lda, d_B, d_X, nrhs: int, work, d_reps,
+                       opts=None):
+    """Time every candidate tile set on this batch; the context keeps the
+    fastest.  Returns (chosen tiles as a dict, {candidate: ms})."""
+    batch = d_n.numel()
+    best = mixlu_batched_tiles()
+    ms = (ctypes.c_float * len(TILE_CANDIDATES))()
+    check(load().mixlu_batched_tune(ctx, prec, batch, _p(d_n), _p(d_A), _p(d_lda), _p(d_B),
+                                    _p(d_X), nrhs, _p(work), work.numel() * work.element_size(),
+                                    None if opts is None else ctypes.byref(opts), _p(d_reps),
+                                    ctypes.byref(best), ms, len(TILE_CANDIDATES)),
+          "mixlu_batched_tune")
+    return best.as_dict(), {c: float(ms[i]) for i, c in enumerate(TILE_CANDIDATES)}
+
+
+def mixlu_batched_get_tiles(ctx, prec: int) -> dict:
+    t = mixlu_batched_tiles()
+    check(load().mixlu_batched_get_tiles(ctx, prec, ctypes.byref(t)), "mixlu_batched_get_tiles")
+    return t.as_dict()
+
+
+def mixlu_batched_set_tiles(ctx, prec: int, panel: int, chunk: int, groups: int,
+                            tuned: bool = False) -> None:
+    t = mixlu_batched_tiles(panel, chunk, groups, int(tuned))
+    check(load().mixlu_batched_set_tiles(ctx, prec, ctypes.byref(t)), "mixlu_batched_set_tiles")
+
+
 def reports_from_bytes(buf) -> list:
     """Decode a host copy (bytes) of a device array of mixlu_report."""
     sz = ctypes.sizeof(mixlu_report)
@@ -427,6 +471,12 @@ class Solver:
         """Enqueue the batched solve on the context's stream (no sync)."""
         mixlu_dxgesv_batched(self.ctx, buf["prec"], buf["n"], buf["pA"], None, buf["pB"],
                              buf["pX"], buf["nrhs"], buf["work"], buf["reps"], buf["opts"])
+
+    def tune_batched(self, buf):
+        """Autotune the tile set for this batch's precision on this batch (the
+        context keeps it for later launches); returns (tiles, timings)."""
+        return mixlu_batched_tune(self.ctx, buf["prec"], buf["n"], buf["pA"], None, buf["pB"],
+                                  buf["pX"], buf["nrhs"], buf["work"], buf["reps"], buf["opts"])
 
     def dxgesv_batched(self, As, Bs, prec="fp32", opts=None):
         """Solve every A_i x_i = b_i in one persistent launch; returns the list

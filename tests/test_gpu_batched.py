@@ -188,3 +188,91 @@ def test_batched_full_workload_sampled(solver):
     idx = np.random.default_rng(0).choice(4096, 64, replace=False)
     _check_all([(As[i], bs[i], ks[i]) for i in idx], [Xs[i] for i in idx],
                [reps[i] for i in idx])
+
+
+def _oracle_refs(systems):
+    return [O.gesv_ir(A, b).x for A, b, _ in systems]
+
+
+def _check_with_refs(systems, refs, Xs, reps):
+    for i, ((A, b, kappa), ref, X, rep) in enumerate(zip(systems, refs, Xs, reps)):
+        m = O.metrics(A, X.cpu().numpy(), b, x_ref=ref)
+        assert m["passes"], (i, A.shape[0], rep)
+        assert float(np.max(m["fwd_ref"])) <= 1e-12 * kappa, (i, A.shape[0], rep)
+        assert rep["converged"], (i, rep)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batched_every_tile_set(solver, prec):
+    """Every candidate of the autotuner's search space (panel 16/8, chunk
+    128/64/32, 2/1 workgroups per CU) solves the ragged-size batch to the
+    oracle's bar."""
+    import torch
+
+    from paper_0808_2794_amd import mixlu
+
+    systems = _systems([1, 7, 8, 9, 16, 17, 31, 33, 64, 65, 100, 129, 255, 300, 511, 512], 611)
+    refs = _oracle_refs(systems)
+    p = mixlu.PREC[prec]
+    buf = solver.batched_buffers([_dev(A) for A, _, _ in systems],
+                                 [_dev(b) for _, b, _ in systems], prec)
+    saved = mixlu.mixlu_batched_get_tiles(solver.ctx, p)
+    try:
+        for panel, chunk, groups in mixlu.TILE_CANDIDATES:
+            _say(f"batched tiles {prec} panel={panel} chunk={chunk} groups={groups}")
+            mixlu.mixlu_batched_set_tiles(solver.ctx, p, panel, chunk, groups)
+            for X in buf["X"]:
+                X.zero_()
+            solver.run_batched(buf)
+            torch.cuda.synchronize()
+            reps = mixlu.reports_from_bytes(bytes(buf["reps"].cpu().numpy()))
+            _check_with_refs(systems, refs, buf["X"], reps)
+    finally:
+        mixlu.mixlu_batched_set_tiles(solver.ctx, p, saved["panel"], saved["chunk"],
+                                      saved["groups"], saved["tuned"])
+
+
+def test_batched_autotune(solver):
+    """The autotuner times all twelve candidates on the caller's batch, keeps
+    the fastest in the context (tuned flag set), and the tuned launch - also
+    when captured in a graph - solves the batch to the oracle's bar.  An
+    invalid tile set is refused."""
+    import torch
+
+    from paper_0808_2794_amd import mixlu
+
+    g = np.random.default_rng(12)
+    sizes = [int(v) for v in g.integers(16, 513, 96)]
+    systems = _systems(sizes, 612)
+    refs = _oracle_refs(systems)
+    buf = solver.batched_buffers([_dev(A) for A, _, _ in systems],
+                                 [_dev(b) for _, b, _ in systems], "fp32")
+    _say("batched autotune fp32")
+    best, ms = solver.tune_batched(buf)
+    assert best["tuned"] and (best["panel"], best["chunk"], best["groups"]) in ms
+    assert len(ms) == 12 and all(v > 0 for v in ms.values()), ms
+    assert ms[(best["panel"], best["chunk"], best["groups"])] == min(ms.values())
+    assert mixlu.mixlu_batched_get_tiles(solver.ctx, mixlu.FP32) == best
+    # the tune's own last run left complete results
+    torch.cuda.synchronize()
+    _check_with_refs(systems, refs, buf["X"],
+                     mixlu.reports_from_bytes(bytes(buf["reps"].cpu().numpy())))
+    stream = torch.cuda.Stream()
+    mixlu.mixlu_set_stream(solver.ctx, stream)
+    try:
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=stream):
+            solver.run_batched(buf)
+        for X in buf["X"]:
+            X.zero_()
+        torch.cuda.synchronize()
+        _say("batched tuned graph replay")
+        graph.replay()
+        torch.cuda.synchronize()
+        _check_with_refs(systems, refs, buf["X"],
+                         mixlu.reports_from_bytes(bytes(buf["reps"].cpu().numpy())))
+    finally:
+        mixlu.mixlu_set_stream(solver.ctx, torch.cuda.current_stream())
+    with pytest.raises(mixlu.MixluError):
+        mixlu.mixlu_batched_set_tiles(solver.ctx, mixlu.FP32, 12, 128, 2)
+    mixlu.mixlu_batched_set_tiles(solver.ctx, mixlu.FP32, 16, 128, 2)
