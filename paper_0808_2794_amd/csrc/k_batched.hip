@@ -47,6 +47,7 @@ struct BShared {
     double red[kBW][2];
     int pivw[kBW];
     int piv[kBatchedNmax];
+    int perm[kBatchedNmax];   // row of A (before pivoting) now at each position
     int src[kBatchedNmax];
     int mv_dst[2 * kBB], mv_src[2 * kBB];
     int nmoves;
@@ -169,6 +170,7 @@ __device__ __noinline__ void sys_getrf(T *__restrict__ W, int n, int chunk, BSha
     T *L11 = reinterpret_cast<T *>(sh.L11);
     T *valw = reinterpret_cast<T *>(sh.valw);
     constexpr int LP11 = kBB + 4;  // 16-byte aligned rows
+    for (int r = tid; r < n; r += kBT) sh.perm[r] = r;
     for (int k = 0; k < n; k += BB) {
         const int w = n - k < BB ? n - k : BB;
         T a[BB];
@@ -250,49 +252,81 @@ __device__ __noinline__ void sys_getrf(T *__restrict__ W, int n, int chunk, BSha
             }
         }
         __syncthreads();
+        int pnew = -1;
         if (row < n && sh.src[row] != row) {
             const int m = atomicAdd(&sh.nmoves, 1);
             sh.mv_dst[m] = row;
             sh.mv_src[m] = sh.src[row];
+            pnew = sh.perm[sh.src[row]];
         }
         __syncthreads();
+        if (pnew >= 0) sh.perm[row] = pnew;
         const int nm = sh.nmoves;  // <= 2 BB <= 64: one lane per move
         // rows move in the columns left and right of the panel: one wave per
         // column, lane m carries move m (all loads of a column before its
         // stores, so cycles of moves are safe)
         if (lane < nm) {
             const int dst = sh.mv_dst[lane], srow = sh.mv_src[lane];
-            for (int col = wave; col < n; col += kBW) {
-                if (col >= k && col < k + w) continue;
-                T *wc = W + (size_t)col * n;
-                const T v = wc[srow];
-                wc[dst] = v;
+            constexpr int U = 2;  // columns in flight per wave
+            for (int col0 = wave; col0 < n; col0 += U * kBW) {
+                T v[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int col = col0 + u * kBW;
+                    const bool on = col < n && (col < k || col >= k + w);
+                    v[u] = on ? W[(size_t)col * n + srow] : (T)0;
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int col = col0 + u * kBW;
+                    if (col < n && (col < k || col >= k + w)) W[(size_t)col * n + dst] = v[u];
+                }
             }
         }
         __syncthreads();
-        // U12 = L11^{-1} A12 and A22 -= L21 U12, by chunks of columns;
-        // a[] now only serves as the L21 operand
+        // U12 = L11^{-1} A12 for every column right of the panel, one thread
+        // per column (n <= kBT), by forward substitution in registers with
+        // L11 read from LDS by broadcast
+        {
+            const int col = k + w + tid;
+            if (col < n) {
+                T *wc = W + (size_t)col * n + k;
+                T x[BB];
 #pragma unroll
-        for (int c = 0; c < BB; ++c) a[c] = lowp_round<LP>(a[c]);
+                for (int r = 0; r < BB; ++r) x[r] = r < w ? wc[r] : (T)0;
+#pragma unroll
+                for (int r = 1; r < BB; ++r) {
+                    if (r < w) {
+#pragma unroll
+                        for (int q = 0; q < r; ++q) x[r] -= L11[r * LP11 + q] * x[q];
+                    }
+                    // keep the L11 loads of later rows from being hoisted
+                    // here (they would hold ~BB^2/2 registers)
+                    __asm__ volatile("" ::: "memory");
+                }
+#pragma unroll
+                for (int r = 0; r < BB; ++r) {
+                    if (r < w) wc[r] = x[r];
+                    if constexpr (LP == MIXLU_FP16)
+                        if (fabs(x[r]) > (T)65504) atomicAdd(&sh.overflow, 1);
+                }
+            }
+        }
+        __syncthreads();
+        // A22 -= L21 U12 by chunks of columns: the rounded L21 row of this
+        // thread in registers (reloaded from the stored panel), the rounded
+        // U12 chunk staged in sU
+#pragma unroll
+        for (int c = 0; c < BB; ++c)
+            a[c] = (row >= k + w && row < n && c < w) ? lowp_round<LP>(W[(size_t)(k + c) * n + row])
+                                                      : (T)0;
         for (int c0 = k + w; c0 < n; c0 += chunk) {
             const int nc = n - c0 < chunk ? n - c0 : chunk;
             if (tid < nc) {
-                // column c0 + tid of U12 by forward substitution; the column
-                // lives in this thread's LDS row of sU while it is solved
-                T *wc = W + (size_t)(c0 + tid) * n + k;
+                const T *wc = W + (size_t)(c0 + tid) * n + k;
                 T *xs = sU + tid * kSUP;
-                for (int r = 0; r < w; ++r) {
-                    T s = wc[r];
-                    for (int q = 0; q < r; ++q) s -= L11[r * LP11 + q] * xs[q];
-                    xs[r] = s;
-                    wc[r] = s;
-                }
-                for (int r = 0; r < BB; ++r) {
-                    const T x = r < w ? xs[r] : (T)0;
-                    if constexpr (LP == MIXLU_FP16)
-                        if (fabs(x) > (T)65504) atomicAdd(&sh.overflow, 1);
-                    xs[r] = lowp_round<LP>(x);
-                }
+#pragma unroll
+                for (int r = 0; r < BB; ++r) xs[r] = r < w ? lowp_round<LP>(wc[r]) : (T)0;
             }
             __syncthreads();
             if (row >= k + w && row < n) {
@@ -316,17 +350,9 @@ template <typename T>
 __device__ __noinline__ void sys_getrs(const T *__restrict__ W, int n, BShared &sh) {
     const int tid = threadIdx.x, lane = tid & 63;
     T *y = reinterpret_cast<T *>(sh.y);
-    for (int i = tid; i < n; i += kBT) y[i] = (T)(sh.R[i] * sh.r[i]);
-    __syncthreads();
-    if (tid == 0) {
-        for (int j = 0; j < n; ++j) {
-            const int p = sh.piv[j];
-            if (p != j) {
-                const T t = y[j];
-                y[j] = y[p];
-                y[p] = t;
-            }
-        }
+    for (int i = tid; i < n; i += kBT) {
+        const int p = sh.perm[i];
+        y[i] = (T)(sh.R[p] * sh.r[p]);
     }
     __syncthreads();
     // diagonal blocks are staged through LDS (the sU area is free here)
@@ -405,15 +431,29 @@ __device__ __noinline__ void sys_residual(const double *__restrict__ A, int lda,
                              double &xn) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     double rmax = 0.0, xmax = 0.0;
-    for (int i = wave; i < n; i += kBW) {
-        double s = 0.0;
-        for (int j = lane; j < n; j += 64) s += A[(size_t)i * lda + j] * sh.x[j];
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-        if (lane == 0) {
-            const double r = b[(size_t)i * ldb] - s;
-            sh.r[i] = r;
-            const double ar = fabs(r);
-            rmax = (ar > rmax || ar != ar) ? ar : rmax;
+    // each wave takes RW rows at a time, lanes along the rows, so RW
+    // independent row sums are in flight
+    constexpr int RW = 4;
+    for (int i0 = wave * RW; i0 < n; i0 += kBW * RW) {
+        double acc[RW];
+#pragma unroll
+        for (int u = 0; u < RW; ++u) acc[u] = 0.0;
+        for (int j = lane; j < n; j += 64) {
+            const double xj = sh.x[j];
+#pragma unroll
+            for (int u = 0; u < RW; ++u)
+                if (i0 + u < n) acc[u] += A[(size_t)(i0 + u) * lda + j] * xj;
+        }
+#pragma unroll
+        for (int u = 0; u < RW; ++u) {
+            double v = acc[u];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+            if (lane == 0 && i0 + u < n) {
+                const double r = b[(size_t)(i0 + u) * ldb] - v;
+                sh.r[i0 + u] = r;
+                const double ar = fabs(r);
+                rmax = (ar > rmax || ar != ar) ? ar : rmax;
+            }
         }
     }
     for (int i = tid; i < n; i += kBT) {
@@ -601,7 +641,7 @@ __device__ void sys_fallback(const BatchArgs &g, int s, unsigned char *slot, BSh
     }
     __syncthreads();
     sys_convert<double>(A, lda, n, 0, W64, sh);
-    sys_getrf<double, 0, kBB>(W64, n, g.chunk, sh);
+    sys_getrf<double, 0, kBB / 2>(W64, n, g.chunk, sh);
     rep.prec = MIXLU_FP64;
     if (sh.bad != INT_MAX) {
         rep.info = sh.bad;
@@ -659,10 +699,10 @@ __global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k
     batched_loop<float, LP, BB>(g, sh);
 }
 
-// FP64 factors (the FP64 comparator): the FP64 LU needs more registers; one
-// workgroup per CU.
+// FP64 factors (the FP64 comparator), under the same register budget.
 template <int BB>
-__global__ __launch_bounds__(kBT) void k_batched_fp64(BatchArgs g) {
+__global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k_batched_fp64(
+    BatchArgs g) {
     __shared__ BShared sh;
     batched_loop<double, 0, BB>(g, sh);
 }
@@ -671,7 +711,8 @@ __global__ __launch_bounds__(kBT) void k_batched_fp64(BatchArgs g) {
 // low-precision solve failed get the FP64 path; the others are skipped.  A
 // launch of its own, so the registers of the FP64 code do not limit the
 // occupancy of the low-precision pass.
-__global__ __launch_bounds__(kBT) void k_batched_fallback(BatchArgs g) {
+__global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k_batched_fallback(
+    BatchArgs g) {
     __shared__ BShared sh;
     unsigned char *slot = g.slots + (size_t)blockIdx.x * g.slot_bytes;
     for (;;) {
