@@ -14,6 +14,9 @@ calls the plain C routines of ``oracle.c``:
                    (SPOTRF/SPOTRS with a DSYMM residual, Section 3.1.1).
 * ``residual_ld`` -- b - A x accumulated in extended precision, for checks.
 * ``metrics``   -- normwise/componentwise backward error and forward error.
+* ``condest1``  -- estimate of kappa_1(A) (Hager's method with Higham's
+                   refinement) from the FP64 factors, for the Section 4 rule
+                   that refinement needs kappa eps_s below about one.
 
 The stopping rule is ||r||_inf <= sqrt(n) 2^-53 ||A||_inf ||x||_inf per
 right-hand side (Section 3), checked on the residual of the current iterate;
@@ -265,3 +268,48 @@ def metrics(A, x, b, x_ref=None, x_true=None) -> dict:
             d = np.abs(X2 - R2).max(axis=0)
             out[key] = d / np.maximum(np.abs(R2).max(axis=0), np.finfo(float).tiny)
     return out
+
+
+def norm_1(A) -> float:
+    """||A||_1: the largest column sum of |a_ij|."""
+    return float(np.abs(np.asarray(A, dtype=np.float64)).sum(axis=0).max()) if np.size(A) else 0.0
+
+
+def condest1(A, itmax: int = 5) -> float:
+    """Estimate of kappa_1(A) = ||A||_1 ||A^{-1}||_1 by Hager's method with
+    Higham's refinement (the scheme of LAPACK's xGECON), every solve by the
+    FP64 factors of ``getrf``.  In the method's order: x = (1/n, ..., 1/n);
+    y = A^{-1} x; xi = sign(y) with sign(0) = +1; z = A^{-T} xi; stop when
+    ||z||_inf <= z^T x or the new vertex repeats the last one, else x = e_j
+    at the first index j of the largest |z_j|; at most ``itmax`` sweeps,
+    keeping the largest ||y||_1.  Then Higham's alternating vector
+    v_i = (-1)^i (1 + i/(n-1)) gives 2 ||A^{-1} v||_1 / (3n), and the
+    estimate of ||A^{-1}||_1 is the larger of the two."""
+    A = np.asarray(A, dtype=np.float64)
+    n = A.shape[0]
+    if n == 0:
+        return 0.0
+    a1 = norm_1(A)
+    LU, ipiv, info = getrf(A)
+    if info:
+        return float("inf")
+    x = np.full(n, 1.0 / n)
+    est = 0.0
+    jprev = -1
+    for _ in range(itmax):
+        y = getrs(LU, ipiv, x)
+        est = max(est, float(np.abs(y).sum()))
+        xi = np.where(y >= 0.0, 1.0, -1.0)
+        z = getrs(LU, ipiv, xi, trans=True)
+        zinf = float(np.abs(z).max())
+        j = int(np.argmax(np.abs(z)))  # first index among equal maxima
+        if zinf <= float(z @ x) or j == jprev:
+            break
+        jprev = j
+        x = np.zeros(n)
+        x[j] = 1.0
+    i = np.arange(n)
+    v = np.where(i % 2 == 1, -1.0, 1.0) * (1.0 + (i / (n - 1) if n > 1 else 0.0))
+    alt = 2.0 * float(np.abs(getrs(LU, ipiv, v)).sum()) / (3.0 * n)
+    return a1 * max(est, alt)
+

@@ -351,3 +351,51 @@ def test_golden_exact_systems(case):
     r = O.gesv_ir(np.array(A, float), np.array(b, float))
     kappa = np.linalg.cond(np.array(A, float), np.inf)
     assert np.abs(r.x - xf).max() <= 4 * kappa * U_D * np.abs(xf).max()
+
+
+# ---------------------------------------------------------------- kappa_1
+def test_condest_diagonal_is_exact():
+    """For diagonal A the first sweep moves to the smallest |d_j| and the
+    estimate is kappa_1 = max|d| / min|d| exactly."""
+    g = np.random.default_rng(21)
+    d = g.uniform(0.5, 2.0, 30) * np.where(g.random(30) < 0.5, -1.0, 1.0)
+    d[11] = 3e-5
+    A = np.diag(d)
+    assert O.condest1(A) == pytest.approx(np.abs(d).max() / np.abs(d).min(), rel=1e-14)
+
+
+def test_condest_bidiagonal_closed_form():
+    """A = I - 2 N (N the shift above the diagonal): (A^{-1})_ij = 2^(j-i)
+    for j >= i, so ||A^{-1}||_1 = 2^n - 1 (last column) and ||A||_1 = 3;
+    the method reaches that column in one sweep."""
+    for n in (2, 5, 20, 40):
+        A = np.eye(n) - 2.0 * np.eye(n, k=1)
+        assert O.condest1(A) == pytest.approx(3.0 * (2.0 ** n - 1.0), rel=1e-13)
+
+
+def test_condest_special_cases():
+    assert O.condest1(np.array([[-4.0]])) == 1.0
+    assert O.condest1(np.eye(7)) == 1.0
+    P = np.eye(9)[[3, 0, 8, 1, 2, 7, 6, 5, 4]]
+    assert O.condest1(P) == pytest.approx(1.0, rel=1e-15)
+    assert O.condest1(np.zeros((0, 0))) == 0.0
+
+
+def test_condest_bounds_on_random_matrices():
+    """A lower bound of the true kappa_1 (||A^{-1}||_1 computed column by
+    column from the inverse), and never below a third of it on these seeded
+    matrices: iid uniform, a badly scaled column, prescribed singular values."""
+    for seed in range(45):
+        g = np.random.default_rng(300 + seed)
+        n = int(g.choice([3, 8, 20, 60]))
+        if seed % 3 == 0:
+            A = g.uniform(-1, 1, (n, n))
+        elif seed % 3 == 1:
+            A = g.standard_normal((n, n))
+            A[:, 0] *= 1e-4
+        else:
+            A, _, _ = gen.prescribed_cond_system(n, 1e6, g)
+        true = np.abs(A).sum(axis=0).max() * np.abs(np.linalg.inv(A)).sum(axis=0).max()
+        est = O.condest1(A)
+        assert est <= true * (1 + 1e-9), (seed, est, true)
+        assert est >= true / 3.0, (seed, est, true)
