@@ -95,7 +95,12 @@ typedef struct {
                          (k >= 2) or ||r_k|| >= ||r_{k-1}|| once (k >= 3);
                          default 0.9                                         */
     int refine;       /* mixlu_refine_kind (default MIXLU_REFINE_CLASSIC)    */
-    int reserved[5];
+    int condest;      /* 1: after a low-precision factorization, estimate
+                         kappa_1(A) with it (mixlu_condest); when
+                         kappa_1 eps_s >= 1 skip the refinement and take
+                         the FP64 path at once (report.iter = -5).  0
+                         (default): no estimate.  mixlu_dxgesv/dxposv.     */
+    int reserved[4];
 } mixlu_opts;
 
 /* Refinement after the low-precision factorization.  CLASSIC is the
@@ -126,6 +131,8 @@ typedef struct {
                       -3 zero or non-finite pivot in the low-precision
                          factor (Cholesky: non-positive pivot),
                       -4 refinement stalled,
+                      -5 the kappa_1 estimate ruled the low precision out
+                         (opts.condest),
                       -(itermax+1) no convergence within itermax.        */
     int info;      /* 0, or k+1 when the FP64 factorization met an exactly
                       zero pivot in column k (A singular; X undefined)     */
@@ -137,7 +144,9 @@ typedef struct {
     double berr;   /* max over columns of ||r|| / (||A|| ||x||)           */
     int converged; /* 1 when every column meets the stopping test
                       ||r||_inf <= sqrt(n) 2^-53 ||A||_inf ||x||_inf       */
-    int reserved[3];
+    float cond_est; /* kappa_1 estimate when opts.condest asked for it,
+                       else 0                                            */
+    int reserved[2];
 } mixlu_report;
 
 /* ----------------------------------------------------------- context */
@@ -228,6 +237,20 @@ int mixlu_getrs(mixlu_ctx_t ctx, const mixlu_factor *F, int trans, int nrhs,
 int mixlu_refine(mixlu_ctx_t ctx, mixlu_factor *F, int trans, int nrhs,
                  const double *A, int lda, const double *B, int ldb, double *X,
                  int ldx, const mixlu_opts *o, mixlu_report *rep);
+
+/* Estimate of the 1-norm condition number kappa_1(A) = ||A||_1 ||A^{-1}||_1
+   from the stored factors, for deciding whether refinement with them can
+   converge (Section 4: it needs kappa eps_s below about one).  ||A^{-1}||_1
+   is estimated by Hager's method with Higham's refinement, the scheme of
+   LAPACK's xGECON: from x = (1/n, ..., 1/n), y = A^{-1} x,
+   z = A^{-T} sign(y), stop when ||z||_inf <= z^T x, else restart from x =
+   e_j with j the first index of the largest |z_j| (at most 5 sweeps); the
+   result is the larger of ||y||_1 and 2 ||A^{-1} v||_1 / (3n) for
+   v_i = (-1)^i (1 + i/(n-1)).  Solves use the factors' precision, so the
+   value is a lower bound of kappa_1 up to the factor's error; it is exact
+   for diagonal A.  Uses the workspace's Krylov vectors (not valid during
+   an FGMRES refinement).  *kappa1 (host).  Synchronizes. */
+int mixlu_condest(mixlu_ctx_t ctx, const mixlu_factor *F, double *kappa1);
 
 /* One-shot mixed-precision solve A X = B (DSGESV-style): factor in prec,
    x_0, refinement, FP64 fallback.  A, B (const) and X are device memory. */

@@ -459,13 +459,15 @@ int factor_chol(hipStream_t s, void *work, const Layout &L, size_t woff, int tra
     return MIXLU_OK;
 }
 
-void init_status(hipStream_t s, int *status) {
+hipError_t init_status(hipStream_t s, int *status) {
     // ST_BREAKDOWN and ST_CHOL start at INT_MAX (no failure), the rest at 0
-    static const int zero = 0;
-    (void)zero;
-    launch_fill_u32(reinterpret_cast<unsigned *>(status), 0u, ST_COUNT, s);
-    launch_fill_u32(reinterpret_cast<unsigned *>(status + ST_BREAKDOWN), (unsigned)INT_MAX, 1, s);
-    launch_fill_u32(reinterpret_cast<unsigned *>(status + ST_CHOL), (unsigned)INT_MAX, 1, s);
+    hipError_t e = launch_fill_u32(reinterpret_cast<unsigned *>(status), 0u, ST_COUNT, s);
+    if (e == hipSuccess)
+        e = launch_fill_u32(reinterpret_cast<unsigned *>(status + ST_BREAKDOWN), (unsigned)INT_MAX,
+                            1, s);
+    if (e == hipSuccess)
+        e = launch_fill_u32(reinterpret_cast<unsigned *>(status + ST_CHOL), (unsigned)INT_MAX, 1, s);
+    return e;
 }
 
 // Failure column + 1 of the factorization (INT_MAX: none).
@@ -499,7 +501,7 @@ int convert_and_factor(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t wof
     double *R = at<double>(work, L.R), *C = at<double>(work, L.C);
     double *norms = at<double>(work, L.norms);
     int *status = at<int>(work, L.status);
-    init_status(s, status);
+    HIPCK(init_status(s, status));
     HIPCK(launch_row_stats(A, lda, n, tmp, tmp + np, s));
     if (L.kind == 1) {
         // ||A||_inf from the row sums; symmetric scaling keeps W symmetric
@@ -907,6 +909,78 @@ int factor_entry(mixlu_ctx_s *ctx, int op, int prec, int n, const double *A, int
     return factor_into(ctx, L, prec, A, lda, work, lwork, op_, F, info);
 }
 
+// Unit roundoff of the low-precision factor (C1 of the readings: eps_s).
+double eps_of(int prec) {
+    switch (prec) {
+        case MIXLU_FP32: return 0x1p-24;
+        case MIXLU_FP16: return 0x1p-11;
+        case MIXLU_BF16: return 0x1p-8;
+        case MIXLU_FP8: return 0x1p-4;
+        default: return 0x1p-53;
+    }
+}
+
+// kappa_1 estimate with the factors in F (see mixlu_condest).
+int condest_impl(mixlu_ctx_s *ctx, const mixlu_factor *F, double *kappa1) {
+    const Layout L = layout_of(F);
+    const int n = L.n;
+    void *work = F->work;
+    hipStream_t s = ctx->stream;
+    int st[ST_COUNT];
+    double nrm[2];
+    RETCK(read_status(ctx, L, work, st, nrm));
+    // ||A||_1 (= ||A||_inf for the symmetric A of a Cholesky factor, whose
+    // column sums are not formed)
+    const double a1 = L.kind == 1 ? nrm[0] : nrm[1];
+    if (n == 0 || !(a1 > 0.0)) {
+        *kappa1 = 0.0;
+        return MIXLU_OK;
+    }
+    const int cm = F->layout == MIXLU_COL_MAJOR;
+    double *K = at<double>(work, L.krylov);
+    double *x = K, *y = K + L.npad, *z = K + 2 * (size_t)L.npad, *out = K + 3 * (size_t)L.npad;
+    RETCK(ensure_hbuf(ctx, 4096));
+    auto solve = [&](const double *b, double *xo, int trans) -> int {
+        const int tr = eff_trans(L, trans, cm);
+        if (F->prec == MIXLU_FP64)
+            return lu_solve<double>(s, work, L, L.W, 1, b, 1, 0, xo, 1, 0, 1, tr);
+        return lu_solve<float>(s, work, L, L.W, 1, b, 1, 0, xo, 1, 0, 1, tr);
+    };
+    auto fetch = [&]() -> int {
+        HIPCK(hipMemcpyAsync(ctx->hbuf, out, 4 * 8, hipMemcpyDeviceToHost, s));
+        HIPCK(hipStreamSynchronize(s));
+        return MIXLU_OK;
+    };
+    HIPCK(launch_cond_start(x, n, 0, s));
+    double est = 0.0;
+    int jprev = -1;
+    for (int sweep = 0; sweep < 5; ++sweep) {
+        RETCK(solve(x, y, 0));                           // y = A^{-1} x
+        HIPCK(launch_cond_sign(y, n, z, out, s));        // z <- sign(y), ||y||_1
+        RETCK(solve(z, z, 1));                           // z = A^{-T} sign(y)
+        HIPCK(launch_cond_test(z, x, n, out, s));        // tests, x <- e_j
+        RETCK(fetch());
+        const double ynorm = ctx->hbuf[0], zinf = ctx->hbuf[1], ztx = ctx->hbuf[2];
+        const int j = (int)ctx->hbuf[3];
+        if (!(ynorm == ynorm) || !(zinf == zinf)) {
+            est = ynorm;
+            break;
+        }
+        est = ynorm > est ? ynorm : est;
+        if (zinf <= ztx || j == jprev) break;  // no better vertex
+        jprev = j;
+    }
+    // Higham's alternating vector guards against the cases the sweeps miss
+    HIPCK(launch_cond_start(x, n, 1, s));
+    RETCK(solve(x, y, 0));
+    HIPCK(launch_cond_sign(y, n, z, out, s));
+    RETCK(fetch());
+    const double alt = 2.0 * ctx->hbuf[0] / (3.0 * n);
+    if (alt > est || !(alt == alt)) est = alt;
+    *kappa1 = a1 * est;
+    return MIXLU_OK;
+}
+
 // One-shot solve (op GESV or POSV): factor, x_0, refinement, fallback.
 int dx_entry(mixlu_ctx_s *ctx, int op, int prec, int n, int nrhs, const double *A, int lda,
              const double *B, int ldb, double *X, int ldx, void *work, size_t lwork,
@@ -937,6 +1011,11 @@ int dx_entry(mixlu_ctx_s *ctx, int op, int prec, int n, int nrhs, const double *
         rep->iter = -1;
         return MIXLU_OK;
     }
+    double kest = 0.0;
+    if (F.lowp_status == 0 && op_.condest && prec != MIXLU_FP64) {
+        RETCK(condest_impl(ctx, &F, &kest));
+        if (!(kest * eps_of(prec) < 1.0)) F.lowp_status = -5;
+    }
     if (F.lowp_status == 0) {
         const int tr = eff_trans(L, 0, cm);
         if (prec == MIXLU_FP64)
@@ -944,7 +1023,9 @@ int dx_entry(mixlu_ctx_s *ctx, int op, int prec, int n, int nrhs, const double *
         else
             RETCK(lu_solve<float>(ctx->stream, work, L, L.W, nrhs, B, ldb, cm, X, ldx, cm, 1, tr));
     }
-    return mixlu_refine(ctx, &F, 0, nrhs, A, lda, B, ldb, X, ldx, &op_, rep);
+    RETCK(mixlu_refine(ctx, &F, 0, nrhs, A, lda, B, ldb, X, ldx, &op_, rep));
+    rep->cond_est = (float)kest;
+    return MIXLU_OK;
 }
 
 // FP64 factorization and solve without refinement (op DGESV or DPOSV).
@@ -1223,6 +1304,14 @@ int mixlu_dgesv(mixlu_ctx_t ctx, int n, int nrhs, const double *A, int lda, cons
     if (!ctx) return -1;
     ProfCall pc_(ctx);
     return d_entry(ctx, MIXLU_OP_DGESV, n, nrhs, A, lda, B, ldb, X, ldx, work, lwork, info);
+}
+
+int mixlu_condest(mixlu_ctx_t ctx, const mixlu_factor *F, double *kappa1) {
+    if (!ctx) return -1;
+    if (!F || !F->work) return -2;
+    if (!kappa1) return -3;
+    ProfCall pc_(ctx);
+    return condest_impl(ctx, F, kappa1);
 }
 
 int mixlu_sgesv(mixlu_ctx_t ctx, int n, int nrhs, const double *A, int lda, const double *B,

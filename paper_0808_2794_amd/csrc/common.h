@@ -292,6 +292,11 @@ hipError_t launch_batched(int prec, int batch, int nrhs, int equil, int itermax,
                           int *order, int *counter, void *slots, int nslots,
                           const BatchedTiles &t, int num_cu, hipStream_t s);
 
+// kappa_1 estimate (k_condest.hip)
+hipError_t launch_cond_start(double *x, int n, int alt, hipStream_t s);
+hipError_t launch_cond_sign(const double *y, int n, double *xi, double *out, hipStream_t s);
+hipError_t launch_cond_test(const double *z, double *x, int n, double *out, hipStream_t s);
+
 // a4-a8: solves and refinement (k_solve.hip)
 template <typename Tw>
 hipError_t launch_rhs_gather(int n, int npad, int nrhs, const double *B, int ldb, int b_col_major,

@@ -31,7 +31,7 @@ class mixlu_opts(ctypes.Structure):
     _fields_ = [("itermax", ctypes.c_int), ("equilibrate", ctypes.c_int),
                 ("fallback", ctypes.c_int), ("nb", ctypes.c_int), ("layout", ctypes.c_int),
                 ("stall", ctypes.c_double), ("refine", ctypes.c_int),
-                ("reserved", ctypes.c_int * 5)]
+                ("condest", ctypes.c_int), ("reserved", ctypes.c_int * 4)]
 
 
 class mixlu_report(ctypes.Structure):
@@ -39,12 +39,13 @@ class mixlu_report(ctypes.Structure):
                 ("fallback_iter", ctypes.c_int), ("anorm", ctypes.c_double),
                 ("rnorm", ctypes.c_double), ("xnorm", ctypes.c_double),
                 ("berr", ctypes.c_double), ("converged", ctypes.c_int),
-                ("reserved", ctypes.c_int * 3)]
+                ("cond_est", ctypes.c_float), ("reserved", ctypes.c_int * 2)]
 
     def as_dict(self) -> dict:
         return {"iter": self.iter, "info": self.info, "prec": PREC_NAME.get(self.prec, self.prec),
                 "fallback_iter": self.fallback_iter, "anorm": self.anorm, "rnorm": self.rnorm,
-                "xnorm": self.xnorm, "berr": self.berr, "converged": bool(self.converged)}
+                "xnorm": self.xnorm, "berr": self.berr, "converged": bool(self.converged),
+                "cond_est": float(self.cond_est)}
 
 
 class mixlu_factor(ctypes.Structure):
@@ -79,7 +80,7 @@ EXPORTS = ("mixlu_status_string", "mixlu_default_opts", "mixlu_create", "mixlu_d
            "mixlu_dposv", "mixlu_outer_update", "mixlu_batched_workspace_size",
            "mixlu_dxgesv_batched", "mixlu_profile_enable", "mixlu_profile_read",
            "mixlu_sgesv", "mixlu_report_read", "mixlu_batched_tune", "mixlu_batched_get_tiles",
-           "mixlu_batched_set_tiles")
+           "mixlu_batched_set_tiles", "mixlu_condest")
 
 _lib = None
 
@@ -118,6 +119,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "mixlu_batched_tune": ([P, I, I, P, P, P, P, P, I, P, S, P, P, P, P, I], I),
         "mixlu_batched_get_tiles": ([P, I, P], I),
         "mixlu_batched_set_tiles": ([P, I, P], I),
+        "mixlu_condest": ([P, P, P], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -281,6 +283,13 @@ def mixlu_getrs(ctx, F: mixlu_factor, B, X, trans: int = 0) -> None:
     cm = F.layout == COL_MAJOR
     check(load().mixlu_getrs(ctx, ctypes.byref(F), trans, nrhs, _p(B), _ld(B, cm), _p(X),
                              _ld(X, cm)), "mixlu_getrs")
+
+
+def mixlu_condest(ctx, F: mixlu_factor) -> float:
+    """kappa_1(A) estimated with the factors in F (Hager / Higham)."""
+    k = ctypes.c_double()
+    check(load().mixlu_condest(ctx, ctypes.byref(F), ctypes.byref(k)), "mixlu_condest")
+    return k.value
 
 
 def mixlu_refine(ctx, F: mixlu_factor, A, B, X, opts=None, trans: int = 0) -> mixlu_report:
