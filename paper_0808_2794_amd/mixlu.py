@@ -388,6 +388,11 @@ class Solver:
     """A context plus a reusable workspace on the current device/stream."""
 
     def __init__(self, stream=None):
+        import torch
+
+        # torch allocates the buffers; its HIP runtime, initialized first,
+        # is the one the library's calls then use
+        torch.cuda.init()
         self.ctx = mixlu_create(stream)
         self._work = None
 
