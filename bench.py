@@ -62,7 +62,26 @@ def parse():
     ap.add_argument("--compare-steps", type=int, default=2, help="timed FP64 comparator runs")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target wall time of the CPU oracle sample (0: skip)")
+    ap.add_argument("--tiles", default=None,
+                    help="batched workload: panel,chunk,groups tile set instead of autotuning "
+                         "(e.g. 16,128,2)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only copy 512 MiB once on the device (the reference kernel for "
+                         "scaling the FETCH_SIZE / WRITE_SIZE counters) and exit")
     return ap.parse_args()
+
+
+def calibrate_copy():
+    """One device copy of 512 MiB: the counter runs divide a kernel's
+    FETCH_SIZE / WRITE_SIZE by what the counters read here per byte copied."""
+    import torch
+
+    x = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    sync()
+    y.copy_(x)
+    sync()
+    print(json.dumps({"copied_bytes": x.numel() * 4}), flush=True)
 
 
 def sync():
@@ -307,7 +326,12 @@ def run_batched(args, prec):
     buf = solver.batched_buffers(dA, dB, prec)
     sync()
     # tile sets chosen by the autotuner on this batch (outside the timed region)
-    tiles, tile_ms = solver.tune_batched(buf)
+    if args.tiles:
+        p_, c_, g_ = (int(v) for v in args.tiles.split(","))
+        mixlu.mixlu_batched_set_tiles(solver.ctx, mixlu.PREC[prec], p_, c_, g_)
+        tiles, tile_ms = mixlu.mixlu_batched_get_tiles(solver.ctx, mixlu.PREC[prec]), {}
+    else:
+        tiles, tile_ms = solver.tune_batched(buf)
     sync()
     for _ in range(args.warmup):
         solver.run_batched(buf)
@@ -431,12 +455,15 @@ def run_adjoint(args, prec):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU layout is described in the design notes)", file=sys.stderr)
+        print(f"bench.py: the solver runs on one GPU; --gpus {args.gpus} is not supported "
+              "(how it would shard is described in the design notes)", file=sys.stderr)
         sys.exit(2)
     import torch
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     prec = args.prec or DEFAULT_PREC[args.workload]
     fn = {"dense": run_dense, "spd": run_spd, "batched": run_batched,
           "adjoint": run_adjoint}[args.workload]
