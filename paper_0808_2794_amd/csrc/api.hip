@@ -278,6 +278,7 @@ int factor_lu(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t woff, int tr
     int *perm = at<int>(work, L.perm);
     int *status = at<int>(work, L.status);
     auto *xbuf = at<unsigned long long>(work, L.xbuf);
+    int *moves = at<int>(work, L.moves);  // row-move list of the wide (outer) pivot blocks
     if (nb % B || nb % 64 || nb > 512) return MIXLU_ERR_NOT_IMPLEMENTED;
     RETCK(ensure_side(ctx));
     hipStream_t s2 = ctx->side;
@@ -299,7 +300,8 @@ int factor_lu(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t woff, int tr
                 ProfScope ps(PC_PANEL, fl, 2.0 * m * B * sizeof(T), s);
                 HIPCK(launch_panel<T>(W, np, k, np - k, ipiv, xbuf, status, s));
             }
-            HIPCK(launch_row_swaps<T>(ipiv, k, B, np, perm, W, np, K0, kend, k, k + B, s));
+            HIPCK(launch_row_swaps<T>(ipiv, k, B, np, perm, W, np, K0, kend, k, k + B, moves,
+                                      s));
             if (k + B < kend) {
                 HIPCK(launch_trsm_diag<T>(Wp(k, k), np, Wp(k, k + B), np, kend - k - B, s));
                 HIPCK(launch_gemm<T>(np - k - B, kend - k - B, B, Wp(k + B, k), np, Wp(k, k + B),
@@ -312,7 +314,7 @@ int factor_lu(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t woff, int tr
             HIPCK(hipStreamWaitEvent(s, ctx->ev_join, 0));
             side_busy = false;
         }
-        HIPCK(launch_row_swaps<T>(ipiv, K0, nb, np, nullptr, W, np, 0, np, K0, kend, s));
+        HIPCK(launch_row_swaps<T>(ipiv, K0, nb, np, nullptr, W, np, 0, np, K0, kend, moves, s));
         if (kend >= np) break;
         const int nr = np - kend;
         for (int ib = 0; ib < nb; ib += B) {

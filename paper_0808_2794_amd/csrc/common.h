@@ -250,7 +250,10 @@ hipError_t launch_panel(T *W, int ldw, int k0, int m, int *ipiv, unsigned long l
 // [skip0, skip1) of W, and to perm when given, in one launch
 template <typename T>
 hipError_t launch_row_swaps(const int *ipiv, int k0, int cnt, int npad, int *perm, T *W, int ldw,
-                            int c0, int c1, int skip0, int skip1, hipStream_t s);
+                            int c0, int c1, int skip0, int skip1, int *moves, hipStream_t s);
+// blocks of more pivots than this (with a moves buffer of 2 + 4 cnt ints)
+// compose once in a separate launch
+constexpr int kSwapsFused = 64;
 template <typename T>
 hipError_t launch_trsm_diag(const T *Ldiag, int ldl, T *X, int ldx, int ncols, hipStream_t s);
 template <typename T>

@@ -6,6 +6,7 @@
 //                 per column: wavefront argmax (first index on ties), one
 //                 tagged cross-workgroup exchange, swap, scale, rank-1 update.
 //   k_row_swaps   applies a block of pivots to the columns outside the panel
+//   k_swaps_compose, k_rows_apply: the same for wide blocks, in two launches
 //   k_trsm_diag   X = L^{-1} X with a unit lower diagonal block in LDS
 //   k_gemm        C -= A B on MFMA (f32 16x16x4, f64 16x16x4)
 //   k_pack_*      rounds L21 / U12 to FP16 or BF16 for the trailing update
@@ -304,13 +305,19 @@ __global__ __launch_bounds__(256) void k_row_swaps(const int *__restrict__ ipiv,
     int *mv = cur + m;                                        // 2 * (2 * cnt)
     T *buf = reinterpret_cast<T *>(mv + 4 * cnt + 4);        // 2 * cnt * CW
     __shared__ int s_count;
+    __shared__ int s_pv[512];  // the block's pivots, relative to k0 (cnt <= 512)
     for (int i = threadIdx.x; i < m; i += 256) cur[i] = i;
+    for (int i = threadIdx.x; i < cnt; i += 256) {
+        int q = ipiv[k0 + i] - k0;
+        if (q < i || q >= m) q = i;  // never index outside [k0, npad)
+        s_pv[i] = q;
+    }
     if (threadIdx.x == 0) s_count = 0;
     __syncthreads();
     if (threadIdx.x == 0) {
+        // the composition is sequential; its operands are all in LDS
         for (int s = 0; s < cnt; ++s) {
-            int q = ipiv[k0 + s] - k0;
-            if (q < s || q >= m) q = s;  // never index outside [k0, npad)
+            const int q = s_pv[s];
             if (q != s) {
                 const int t = cur[s];
                 cur[s] = cur[q];
@@ -363,9 +370,90 @@ __global__ __launch_bounds__(256) void k_row_swaps(const int *__restrict__ ipiv,
     }
 }
 
+// Wide blocks of pivots (more than kSwapsFused): the composition is long and
+// sequential, so it runs once, in k_swaps_compose (one workgroup), which
+// writes moves = {count, pad, (dst, src)...} to global memory (after the
+// swaps, row dst holds what row src held before); k_rows_apply then moves
+// the rows of every column, CW columns per workgroup, through LDS.
+__global__ __launch_bounds__(1024) void k_swaps_compose(const int *__restrict__ ipiv, int k0,
+                                                        int cnt, int npad, int *__restrict__ perm,
+                                                        int *__restrict__ moves) {
+    extern __shared__ int cur[];
+    __shared__ int s_count;
+    __shared__ int s_pv[512];
+    __shared__ int s_dst[1024], s_src[1024];
+    const int m = npad - k0;
+    for (int i = threadIdx.x; i < m; i += blockDim.x) cur[i] = i;
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+        int q = ipiv[k0 + i] - k0;
+        if (q < i || q >= m) q = i;  // never index outside [k0, npad)
+        s_pv[i] = q;
+    }
+    if (threadIdx.x == 0) s_count = 0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int s = 0; s < cnt; ++s) {
+            const int q = s_pv[s];
+            if (q != s) {
+                const int t = cur[s];
+                cur[s] = cur[q];
+                cur[q] = t;
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+        const int src = cur[i];
+        if (src != i) {
+            const int q = atomicAdd(&s_count, 1);
+            s_dst[q] = k0 + i;
+            s_src[q] = k0 + src;
+        }
+    }
+    __syncthreads();
+    const int count = s_count;  // <= 2 cnt <= 1024 = blockDim.x
+    const int t = threadIdx.x;
+    int keep = 0;
+    if (t < count) {
+        moves[2 + 2 * t] = s_dst[t];
+        moves[3 + 2 * t] = s_src[t];
+        if (perm) keep = perm[s_src[t]];
+    }
+    __syncthreads();
+    if (perm && t < count) perm[s_dst[t]] = keep;
+    if (t == 0) moves[0] = count;
+}
+
+template <typename T, int CW>
+__global__ __launch_bounds__(256) void k_rows_apply(T *__restrict__ W, int ldw,
+                                                    const int *__restrict__ moves, int c0,
+                                                    int nleft, int gap, int ncols) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    T *buf = reinterpret_cast<T *>(smem);
+    const int count = moves[0];
+    const int lc0 = blockIdx.x * CW;
+    for (int e = threadIdx.x; e < count * CW; e += 256) {
+        const int q = e / CW, cc = e % CW;
+        const int lc = lc0 + cc;
+        if (lc < ncols) {
+            const int col = c0 + lc + (lc >= nleft ? gap : 0);
+            buf[e] = W[(size_t)moves[3 + 2 * q] * ldw + col];
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < count * CW; e += 256) {
+        const int q = e / CW, cc = e % CW;
+        const int lc = lc0 + cc;
+        if (lc < ncols) {
+            const int col = c0 + lc + (lc >= nleft ? gap : 0);
+            W[(size_t)moves[2 + 2 * q] * ldw + col] = buf[e];
+        }
+    }
+}
+
 template <typename T>
 hipError_t launch_row_swaps(const int *ipiv, int k0, int cnt, int npad, int *perm, T *W, int ldw,
-                            int c0, int c1, int skip0, int skip1, hipStream_t s) {
+                            int c0, int c1, int skip0, int skip1, int *moves, hipStream_t s) {
     constexpr int CW = sizeof(T) == 4 ? 16 : 8;
     constexpr size_t kMaxLds = 152 * 1024;  // of the 160 KiB, leaving room for static LDS
     if (cnt > 512) return hipErrorInvalidValue;
@@ -376,6 +464,29 @@ hipError_t launch_row_swaps(const int *ipiv, int k0, int cnt, int npad, int *per
     const int gap = skip1 - skip0;
     int ncols = (c1 - c0) - gap;
     const int m = npad - k0;
+    if (cnt > kSwapsFused && moves) {
+        // compose once, then apply in a second launch
+        const size_t lds_c = (size_t)m * sizeof(int);
+        const size_t lds_a = (size_t)2 * cnt * CW * sizeof(T);
+        if (lds_c > kMaxLds - 16 * 1024 || lds_a > kMaxLds) return hipErrorInvalidValue;
+        static bool attr2_done = false;
+        if (!attr2_done) {
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_swaps_compose),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)(kMaxLds - 16 * 1024));
+            if (e == hipSuccess)
+                e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rows_apply<T, CW>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds);
+            if (e != hipSuccess) return e;
+            attr2_done = true;
+        }
+        k_swaps_compose<<<dim3(1), dim3(1024), lds_c, s>>>(ipiv, k0, cnt, npad, perm, moves);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess || ncols <= 0) return e;
+        k_rows_apply<T, CW><<<dim3((ncols + CW - 1) / CW), dim3(256), lds_a, s>>>(
+            W, ldw, moves, c0, nleft, gap, ncols);
+        return hipGetLastError();
+    }
     const size_t lds = align_up((size_t)(m + 4 * cnt + 4) * 4, 16) + (size_t)2 * cnt * CW * sizeof(T);
     if (lds > kMaxLds) return hipErrorInvalidValue;
     static bool attr_done = false;
@@ -393,9 +504,9 @@ hipError_t launch_row_swaps(const int *ipiv, int k0, int cnt, int npad, int *per
     return hipGetLastError();
 }
 template hipError_t launch_row_swaps<float>(const int *, int, int, int, int *, float *, int, int,
-                                            int, int, int, hipStream_t);
+                                            int, int, int, int *, hipStream_t);
 template hipError_t launch_row_swaps<double>(const int *, int, int, int, int *, double *, int, int,
-                                             int, int, int, hipStream_t);
+                                             int, int, int, int *, hipStream_t);
 
 // ======================================================================
 // Triangular solve with a unit lower diagonal block (LDS-staged)
