@@ -49,3 +49,43 @@ def test_host_only_entry_points():
         mixlu.default_opts(bogus=1)
     # a NULL context is rejected as argument 1 without touching the device
     assert lib.mixlu_destroy(None) == -1
+
+
+def test_host_only_new_entry_points():
+    """NULL contexts are refused as argument 1 before any device work; the
+    new option and report fields sit where the header puts them; the
+    capturing status has a string."""
+    import ctypes
+
+    from paper_0808_2794_amd import mixlu
+
+    lib = mixlu.load()
+    assert b"CAPTURING" in lib.mixlu_status_string(6)
+    t = mixlu.mixlu_batched_tiles(16, 128, 2, 0)
+    assert lib.mixlu_batched_set_tiles(None, mixlu.FP32, ctypes.byref(t)) == -1
+    assert lib.mixlu_batched_get_tiles(None, mixlu.FP32, ctypes.byref(t)) == -1
+    k = ctypes.c_double()
+    assert lib.mixlu_condest(None, None, ctypes.byref(k)) == -1
+    assert lib.mixlu_report_read(None, None, 0, None) == -1
+    info = ctypes.c_int()
+    assert lib.mixlu_sgesv(None, 1, 1, None, 1, None, 1, None, 1, None, 0, ctypes.byref(info)) == -1
+    # layout: the condest option follows refine; the estimate follows converged
+    assert mixlu.mixlu_opts.condest.offset == mixlu.mixlu_opts.refine.offset + 4
+    assert mixlu.mixlu_report.cond_est.offset == mixlu.mixlu_report.converged.offset + 4
+    assert ctypes.sizeof(mixlu.mixlu_report) == 64
+    o = mixlu.default_opts()
+    assert o.condest == 0 and o.refine == mixlu.REFINE_CLASSIC
+
+
+def test_sweep_datta_bound():
+    """The bound the experiment prints: ceil(ln eps_d / (ln eps_s + ln kappa)),
+    finite only while kappa eps_s < 1 (worked by hand for FP32: kappa = 10
+    gives ceil(36.74 / 14.33) = 3, kappa = 1e7 gives ceil(36.74 / 0.52) = 71)."""
+    from paper_0808_2794_amd import sweep
+
+    assert sweep.datta("fp32", 1e1) == 3
+    assert sweep.datta("fp32", 1e7) == 71
+    assert sweep.datta("fp32", 1e8) is None
+    assert sweep.datta("fp16", 1e1) == 7
+    assert sweep.datta("bf16", 1e2) == 40
+    assert sweep.datta("fp16", 2.0 ** 11) is None

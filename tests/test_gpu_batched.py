@@ -276,3 +276,29 @@ def test_batched_autotune(solver):
     with pytest.raises(mixlu.MixluError):
         mixlu.mixlu_batched_set_tiles(solver.ctx, mixlu.FP32, 12, 128, 2)
     mixlu.mixlu_batched_set_tiles(solver.ctx, mixlu.FP32, 16, 128, 2)
+
+
+def test_batched_tune_refused_during_capture(solver):
+    """The autotuner synchronizes, so under graph capture it refuses with
+    MIXLU_ERR_CAPTURING before enqueuing anything; the tiles stay as they
+    were."""
+    import torch
+
+    from paper_0808_2794_amd import mixlu
+
+    systems = _systems([40, 90], 91)
+    buf = solver.batched_buffers([_dev(A) for A, _, _ in systems],
+                                 [_dev(b) for _, b, _ in systems], "fp32")
+    before = mixlu.mixlu_batched_get_tiles(solver.ctx, mixlu.FP32)
+    stream = torch.cuda.Stream()
+    mixlu.mixlu_set_stream(solver.ctx, stream)
+    try:
+        g = torch.cuda.CUDAGraph()
+        _say("batched tune under capture")
+        with pytest.raises(mixlu.MixluError, match="code 6"):
+            with torch.cuda.graph(g, stream=stream):
+                solver.tune_batched(buf)
+    finally:
+        mixlu.mixlu_set_stream(solver.ctx, torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    assert mixlu.mixlu_batched_get_tiles(solver.ctx, mixlu.FP32) == before

@@ -116,3 +116,17 @@ def test_condest_option_routes_to_fp64(solver):
         x = r.x.cpu().numpy()
         m = O.metrics(A, x, b, x_ref=O.gesv_ir(A, b).x)
         assert m["passes"] and float(np.max(m["fwd_ref"])) <= 1e-12 * kappa
+
+
+def test_condest_empty_system(solver):
+    """n = 0: the estimate is 0 (nothing to invert)."""
+    import torch
+
+    from paper_0808_2794_amd import mixlu
+
+    o = mixlu.default_opts()
+    work = solver.workspace(mixlu.OP_GESV, mixlu.FP32, 0, 1, o)
+    A = torch.zeros((0, 0), dtype=torch.float64, device="cuda")
+    F, info = mixlu.mixlu_getrf(solver.ctx, mixlu.FP32, A, work, o)
+    assert info == 0
+    assert mixlu.mixlu_condest(solver.ctx, F) == 0.0

@@ -305,3 +305,13 @@ def test_fp8_operands_factor_and_converge(solver, n):
     ref = O.gesv_ir(A, b)
     _check(A, b, r.x.cpu().numpy(), 2.0, ref.x)
     assert r.report["converged"], r.report
+
+
+def test_sgesv_empty(solver):
+    """n = 0 or no right-hand side: info 0, nothing to do."""
+    import torch
+
+    _say("sgesv empty")
+    A = torch.zeros((0, 0), dtype=torch.float64, device="cuda")
+    B = torch.zeros((0, 1), dtype=torch.float64, device="cuda")
+    assert solver.sgesv(A, B).report["info"] == 0
