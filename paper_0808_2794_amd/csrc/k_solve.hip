@@ -319,6 +319,27 @@ __global__ __launch_bounds__(256) void k_trsm_step(const T *__restrict__ W, int 
     __shared__ T sy[BS][4];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int col = blockIdx.y * 4 + wave;
+    // this workgroup's tile (workgroups x >= 1): its loads do not depend on
+    // the diagonal solve, so they are issued first and their latency hides
+    // behind it (the tile of M in registers for FP32 storage)
+    const int t = blockIdx.x - 1;
+    const int r0 = FWD ? j0 + BS + t * BS : t * BS;
+    const int row = r0 + lane;
+    const int rows_end = FWD ? npad : j0;
+    const bool upd = blockIdx.x > 0 && row < rows_end && col < nrhs;
+    constexpr bool PRE = sizeof(T) == 4;
+    T wpre[PRE ? BS : 1];
+    T ypre = (T)0;
+    // the diagonal block's right-hand sides, also loaded ahead of the barrier
+    const T ydiag = col < nrhs ? Y[(size_t)(j0 + lane) * ldy + col] : (T)0;
+    if (upd) {
+        ypre = Y[(size_t)row * ldy + col];
+        if constexpr (PRE) {
+#pragma unroll
+            for (int k = 0; k < BS; ++k)
+                wpre[k] = TR ? W[(size_t)(j0 + k) * ldw + row] : W[(size_t)row * ldw + j0 + k];
+        }
+    }
     for (int e = tid; e < BS * BS; e += 256) {
         const int r = e / BS, c = e % BS;
         const T v = W[(size_t)(j0 + r) * ldw + j0 + c];
@@ -330,12 +351,14 @@ __global__ __launch_bounds__(256) void k_trsm_step(const T *__restrict__ W, int 
         T mrow[BS];
 #pragma unroll
         for (int k = 0; k < BS; ++k) mrow[k] = sd[lane][k];
-        T y = Y[(size_t)(j0 + lane) * ldy + col];
+        T y = ydiag;
+        // reciprocal of this lane's diagonal entry, formed off the chain
+        const T dinv = UNIT ? (T)1 : (T)1 / sd[lane][lane];
         if constexpr (FWD) {
 #pragma unroll
             for (int k = 0; k < BS; ++k) {
                 if constexpr (!UNIT) {
-                    const T yk = readlane_t(y, k) / readlane_t(mrow[k], k);
+                    const T yk = readlane_t(y, k) * readlane_t(dinv, k);
                     if (lane == k) y = yk;
                     else if (lane > k) y -= mrow[k] * yk;
                 } else {
@@ -347,7 +370,7 @@ __global__ __launch_bounds__(256) void k_trsm_step(const T *__restrict__ W, int 
 #pragma unroll
             for (int k = BS - 1; k >= 0; --k) {
                 if constexpr (!UNIT) {
-                    const T yk = readlane_t(y, k) / readlane_t(mrow[k], k);
+                    const T yk = readlane_t(y, k) * readlane_t(dinv, k);
                     if (lane == k) y = yk;
                     else if (lane < k) y -= mrow[k] * yk;
                 } else {
@@ -362,18 +385,16 @@ __global__ __launch_bounds__(256) void k_trsm_step(const T *__restrict__ W, int 
     if (blockIdx.x == 0) return;
     __syncthreads();
     // tile update: thread (row, wave) = (row, column)
-    const int t = blockIdx.x - 1;
-    const int r0 = FWD ? j0 + BS + t * BS : t * BS;
-    const int row = r0 + lane;
-    const int rows_end = FWD ? npad : j0;
-    if (row >= rows_end || col >= nrhs) return;
+    if (!upd) return;
     T acc = (T)0;
 #pragma unroll
     for (int k = 0; k < BS; ++k) {
-        const T m = TR ? W[(size_t)(j0 + k) * ldw + row] : W[(size_t)row * ldw + j0 + k];
+        T m;
+        if constexpr (PRE) m = wpre[k];
+        else m = TR ? W[(size_t)(j0 + k) * ldw + row] : W[(size_t)row * ldw + j0 + k];
         acc += m * sy[k][wave];
     }
-    Y[(size_t)row * ldy + col] -= acc;
+    Y[(size_t)row * ldy + col] = ypre - acc;
 }
 
 template <typename Tw>
