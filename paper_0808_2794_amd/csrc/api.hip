@@ -590,6 +590,20 @@ int refine_loop(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t woff, cons
     const double thr = std::sqrt((double)n) * kEpsD * anorm;
     std::vector<double> prev(nrhs, 0.0), ratio_prev(nrhs, 0.0);
     res = LoopResult{0, 0, 0.0, 0.0, 0.0};
+    // several right-hand sides: the residual GEMM splits K; its partial
+    // products go to the FP64 fallback region while that is unused (this is
+    // not the fallback's own refinement), else to the Krylov vectors
+    double *split_buf = nullptr;
+    int nsplit = 1;
+    if (nrhs > 1) {
+        const bool w64_free = L.W64 && woff != L.W64;
+        split_buf = at<double>(work, w64_free ? L.W64 : L.krylov);
+        const size_t cap = w64_free ? (size_t)L.npad * L.npad : (size_t)(2 * kKrylov + 2) * L.npad;
+        const size_t per = (size_t)n * nrhs;
+        const size_t smax = 1 + cap / per;
+        const int want = n / 512 < 16 ? (n / 512 > 1 ? n / 512 : 1) : 16;
+        nsplit = (size_t)want < smax ? want : (int)smax;
+    }
     for (int k = 0;; ++k) {
         HIPCK(launch_fill_f64(rnorm, 0.0, nrhs, s));
         HIPCK(launch_fill_f64(xnorm, 0.0, nrhs, s));
@@ -598,7 +612,7 @@ int refine_loop(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t woff, cons
                          8.0 * n * n + 8.0 * n * nrhs * 3.0, s);
             if (nrhs > 1)
                 HIPCK(launch_residual_mm(n, nrhs, A, lda, trans, X, ldx, B, ldb, cm, Rv, nrhs,
-                                         rnorm, xnorm, s));
+                                         rnorm, xnorm, split_buf, nsplit, s));
             else if (trans)
                 HIPCK(launch_residual_t(n, nrhs, A, lda, X, ldx, B, ldb, cm, Rv, nrhs, rnorm,
                                         xnorm, at<double>(work, L.tmp), s));

@@ -256,6 +256,12 @@ hipError_t launch_row_swaps(const int *ipiv, int k0, int cnt, int npad, int *per
 constexpr int kSwapsFused = 64;
 template <typename T>
 hipError_t launch_trsm_diag(const T *Ldiag, int ldl, T *X, int ldx, int ncols, hipStream_t s);
+// C -= op(A) op(B) with K split over nsplit workgroup slices: partial
+// products in P ((nsplit - 1) M ldc elements), then summed into C
+template <typename T>
+hipError_t launch_gemm_splitk(int M, int N, int K, const T *A, int lda, const T *B, int ldb,
+                              T *C, int ldc, int transb, int transa, T *P, int nsplit,
+                              hipStream_t s);
 template <typename T>
 hipError_t launch_gemm(int M, int N, int K, const T *A, int lda, const T *B, int ldb, T *C,
                        int ldc, hipStream_t s, int transb = 0, int lower = 0, int transa = 0,
@@ -325,7 +331,8 @@ hipError_t launch_trsm_blocked(int upper, int trans, const Tw *W, int ldw, int n
 // column norms of R and X (rnorm, xnorm zeroed by the caller)
 hipError_t launch_residual_mm(int n, int nrhs, const double *A, int lda, int transa,
                               const double *X, int ldx, const double *B, int ldb, int cm,
-                              double *Rv, int ldr, double *rnorm, double *xnorm, hipStream_t s);
+                              double *Rv, int ldr, double *rnorm, double *xnorm, double *P,
+                              int nsplit, hipStream_t s);
 // FP64 vector kernels of the flexible GMRES refinement (V[j * ldv + i])
 hipError_t launch_dots(int n, int k, const double *V, size_t ldv, const double *w, double *h,
                        hipStream_t s);

@@ -627,11 +627,23 @@ inline dim3 gemm_grid(int spare_xcd0, int tiles_x, int tiles_y) {
 // as the off-diagonal blocks of the transposed triangular solves).
 // lower != 0: only tiles that touch the lower triangle (col <= row) of C
 // are computed.
+// Split K (gridDim.z = S > 1): workgroup z takes the z-th slice of K (a
+// multiple of BK); slice 0 updates C in place, slice z > 0 stores its
+// -A_z B_z into P + (z - 1) pstride (leading dimension ldc), for a
+// following reduction.
 template <typename T, bool TB, bool TA = false>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const T *__restrict__ A, int lda,
                                               const T *__restrict__ Bm, int ldb, T *__restrict__ C,
-                                              int ldc, int lower, int spare_xcd0) {
+                                              int ldc, int lower, int spare_xcd0,
+                                              T *__restrict__ P = nullptr, size_t pstride = 0) {
     constexpr int BM = 64, BN = 64, BK = 16;
+    const int nsplit = gridDim.z, z = blockIdx.z;
+    int kb = 0, ke = K;
+    if (nsplit > 1) {
+        const int kc = (K + nsplit * BK - 1) / (nsplit * BK) * BK;
+        kb = z * kc;
+        ke = kb + kc < K ? kb + kc : K;
+    }
     __shared__ T sA[BK][BM + 4];
     __shared__ T sB[BK][BN + 4];
     using acc_t = typename Mfma<T>::acc_t;
@@ -646,14 +658,14 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const T *__re
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
-    for (int k0 = 0; k0 < K; k0 += BK) {
+    for (int k0 = kb; k0 < ke; k0 += BK) {
         if constexpr (TA) {
             const int kk = tid >> 4, r = (tid & 15) * 4;
             const int gk = k0 + kk;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int gr = m0 + r + q;
-                sA[kk][r + q] = (gk < K && gr < M) ? A[(size_t)gk * lda + gr] : (T)0;
+                sA[kk][r + q] = (gk < ke && gr < M) ? A[(size_t)gk * lda + gr] : (T)0;
             }
         } else {
             const int r = tid >> 2, kk = (tid & 3) * 4;
@@ -661,7 +673,7 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const T *__re
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int gk = k0 + kk + q;
-                sA[kk + q][r] = (gr < M && gk < K) ? A[(size_t)gr * lda + gk] : (T)0;
+                sA[kk + q][r] = (gr < M && gk < ke) ? A[(size_t)gr * lda + gk] : (T)0;
             }
         }
         if constexpr (TB) {
@@ -670,7 +682,7 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const T *__re
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int gk = k0 + kk + q;
-                sB[kk + q][c] = (gc < N && gk < K) ? Bm[(size_t)gc * ldb + gk] : (T)0;
+                sB[kk + q][c] = (gc < N && gk < ke) ? Bm[(size_t)gc * ldb + gk] : (T)0;
             }
         } else {
             const int kk = tid >> 4, c = (tid & 15) * 4;
@@ -678,7 +690,7 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const T *__re
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int gc = n0 + c + q;
-                sB[kk][c + q] = (gk < K && gc < N) ? Bm[(size_t)gk * ldb + gc] : (T)0;
+                sB[kk][c + q] = (gk < ke && gc < N) ? Bm[(size_t)gk * ldb + gc] : (T)0;
             }
         }
         __syncthreads();
@@ -704,7 +716,10 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const T *__re
             for (int v = 0; v < 4; ++v) {
                 const int row = m0 + wm * 32 + i * 16 + Mfma<T>::row(lane, v);
                 const int col = n0 + wn * 32 + j * 16 + (lane & 15);
-                if (row < M && col < N) C[(size_t)row * ldc + col] -= acc[i][j][v];
+                if (row < M && col < N) {
+                    if (z == 0) C[(size_t)row * ldc + col] -= acc[i][j][v];
+                    else P[(size_t)(z - 1) * pstride + (size_t)row * ldc + col] = -acc[i][j][v];
+                }
             }
 }
 
@@ -856,6 +871,54 @@ template hipError_t launch_gemm<float>(int, int, int, const float *, int, const 
                                        float *, int, hipStream_t, int, int, int, int);
 template hipError_t launch_gemm<double>(int, int, int, const double *, int, const double *, int,
                                         double *, int, hipStream_t, int, int, int, int);
+
+// C[i][j] += sum_{z < nparts} P[z][i][j] (M x N, leading dimension ldc)
+template <typename T>
+__global__ __launch_bounds__(256) void k_splitk_reduce(int M, int N, T *__restrict__ C, int ldc,
+                                                       const T *__restrict__ P, size_t pstride,
+                                                       int nparts) {
+    const size_t total = (size_t)M * N;
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < total;
+         e += (size_t)gridDim.x * 256) {
+        const int i = (int)(e / N), j = (int)(e % N);
+        const size_t off = (size_t)i * ldc + j;
+        T acc = C[off];
+        for (int z = 0; z < nparts; ++z) acc += P[(size_t)z * pstride + off];
+        C[off] = acc;
+    }
+}
+
+template <typename T>
+hipError_t launch_gemm_splitk(int M, int N, int K, const T *A, int lda, const T *B, int ldb,
+                              T *C, int ldc, int transb, int transa, T *P, int nsplit,
+                              hipStream_t s) {
+    if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
+    if (nsplit <= 1 || !P)
+        return launch_gemm<T>(M, N, K, A, lda, B, ldb, C, ldc, s, transb, 0, transa, 0);
+    const size_t pstride = (size_t)M * ldc;
+    const dim3 grid((N + 63) / 64, (M + 63) / 64, nsplit);
+    if (transa && transb)
+        k_gemm<T, true, true><<<grid, dim3(256), 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc, 0, 0, P,
+                                                         pstride);
+    else if (transa)
+        k_gemm<T, false, true><<<grid, dim3(256), 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc, 0, 0, P,
+                                                          pstride);
+    else if (transb)
+        k_gemm<T, true><<<grid, dim3(256), 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc, 0, 0, P,
+                                                   pstride);
+    else
+        k_gemm<T, false><<<grid, dim3(256), 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc, 0, 0, P,
+                                                    pstride);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t total = (size_t)M * N;
+    const unsigned rgrid = (unsigned)((total + 255) / 256 < 4096 ? (total + 255) / 256 : 4096);
+    k_splitk_reduce<T><<<rgrid, dim3(256), 0, s>>>(M, N, C, ldc, P, pstride, nsplit - 1);
+    return hipGetLastError();
+}
+template hipError_t launch_gemm_splitk<double>(int, int, int, const double *, int, const double *,
+                                               int, double *, int, int, int, double *, int,
+                                               hipStream_t);
 
 // ======================================================================
 // Low-precision trailing update

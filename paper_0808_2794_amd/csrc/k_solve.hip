@@ -750,7 +750,8 @@ __global__ __launch_bounds__(256) void k_col_norms(int n, int nrhs, const double
 
 hipError_t launch_residual_mm(int n, int nrhs, const double *A, int lda, int transa,
                               const double *X, int ldx, const double *B, int ldb, int cm,
-                              double *Rv, int ldr, double *rnorm, double *xnorm, hipStream_t s) {
+                              double *Rv, int ldr, double *rnorm, double *xnorm, double *P,
+                              int nsplit, hipStream_t s) {
     if (n == 0 || nrhs == 0) return hipSuccess;
     const size_t cnt = (size_t)n * nrhs;
     k_copy_rhs<<<dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s>>>(n, nrhs, B, ldb, cm, Rv,
@@ -758,7 +759,9 @@ hipError_t launch_residual_mm(int n, int nrhs, const double *A, int lda, int tra
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // column-major X is the row-major nrhs x n matrix X^T: the "B transposed" form
-    e = launch_gemm<double>(n, nrhs, n, A, lda, X, ldx, Rv, ldr, s, cm, 0, transa);
+    // K split over nsplit slices (partials in P): a few right-hand sides give
+    // too few output tiles to keep the GPU busy over the long K = n
+    e = launch_gemm_splitk<double>(n, nrhs, n, A, lda, X, ldx, Rv, ldr, cm, transa, P, nsplit, s);
     if (e != hipSuccess) return e;
     k_col_norms<<<dim3((n + 255) / 256), dim3(256), 0, s>>>(n, nrhs, Rv, ldr, X, ldx, cm, rnorm,
                                                             xnorm);
