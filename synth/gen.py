@@ -21,6 +21,11 @@ solver is benchmarked on:
   and Gaussian loss weights W (loss = sum W * X).
 * ``integer_system``: small integer A and x_true so that b = A x_true is
   exact in FP64 and x_true is the exact solution.
+* ``sparse_convdiff3d``: the 7-point finite-difference operator of
+  -Laplace(u) + w . grad(u) on a k^3 grid (Dirichlet boundary, first-order
+  upwind convection with Peclet number w h / 2 per direction; w = 0 gives the
+  symmetric 3-D Poisson matrix) in CRS form, x_true iid U[-1, 1],
+  b = A x_true: synthetic stand-ins for the sparse matrices of Section 3.2.
 
 Haar-random orthogonal matrices are the Q factor of a QR factorization of a
 Gaussian matrix with the columns' signs fixed by sign(diag R) (Stewart 1980;
@@ -188,3 +193,53 @@ def integer_system(n: int, seed, lo: int = -9, hi: int = 9, xlo: int = -9, xhi: 
     x = g.integers(xlo, xhi + 1, (n, 1)).astype(np.float64)
     b = A @ x
     return A, b, x
+
+
+def sparse_convdiff3d(k: int, peclet: float = 0.0, seed=0):
+    """CRS (rowptr, colind, vals) of the 7-point operator on a k x k x k grid
+    (row index i + k j + k^2 l), scaled by h^2: diagonal 6 + sum of the upwind
+    terms, neighbours -1 (minus the upwind term in the upstream direction);
+    x_true iid U[-1, 1] from the seed and b = A x_true (FP64)."""
+    g = _rng(seed)
+    n = k ** 3
+    p = float(peclet)
+    rows, cols, vals = [], [], []
+    idx = np.arange(n).reshape(k, k, k)  # [l, j, i]
+    for (dl, dj, di) in ((0, 0, 0), (-1, 0, 0), (0, -1, 0), (0, 0, -1), (1, 0, 0), (0, 1, 0),
+                         (0, 0, 1)):
+        if (dl, dj, di) == (0, 0, 0):
+            src = idx.ravel()
+            rows.append(src)
+            cols.append(src)
+            vals.append(np.full(n, 6.0 + 3.0 * 2.0 * p))
+            continue
+        sl = [slice(None)] * 3
+        sd = [slice(None)] * 3
+        for ax, d in enumerate((dl, dj, di)):
+            if d == -1:
+                sl[ax], sd[ax] = slice(1, None), slice(0, -1)
+            elif d == 1:
+                sl[ax], sd[ax] = slice(0, -1), slice(1, None)
+        r = idx[tuple(sl)].ravel()
+        c = idx[tuple(sd)].ravel()
+        # upwind convection with positive velocity in every direction: the
+        # upstream neighbour (d = -1) takes -(1 + 2p), the downstream one -1
+        v = -(1.0 + 2.0 * p) if -1 in (dl, dj, di) else -1.0
+        rows.append(r)
+        cols.append(c)
+        vals.append(np.full(r.size, v))
+    r = np.concatenate(rows)
+    c = np.concatenate(cols)
+    v = np.concatenate(vals)
+    order = np.lexsort((c, r))
+    r, c, v = r[order], c[order], v[order]
+    rowptr = np.zeros(n + 1, dtype=np.int32)
+    np.add.at(rowptr, r + 1, 1)
+    rowptr = np.cumsum(rowptr).astype(np.int32)
+    colind = c.astype(np.int32)
+    x_true = g.uniform(-1.0, 1.0, n)
+    # b = A x_true, row by row in FP64
+    b = np.zeros(n)
+    np.add.at(b, r, v * x_true[c])
+    return rowptr, colind, v.astype(np.float64), b, x_true
+

@@ -399,3 +399,92 @@ def test_condest_bounds_on_random_matrices():
         est = O.condest1(A)
         assert est <= true * (1 + 1e-9), (seed, est, true)
         assert est >= true / 3.0, (seed, est, true)
+
+
+# --------------------------------------------- sparse inner-outer FGMRES
+def _dense_from_csr(rp, ci, v):
+    n = len(rp) - 1
+    A = np.zeros((n, n))
+    for i in range(n):
+        for p in range(rp[i], rp[i + 1]):
+            A[i, ci[p]] += v[p]
+    return A
+
+
+def test_sparse_generator_and_matvec():
+    """The 3-D Poisson matrix (Peclet 0) has the closed-form eigenvalues
+    6 - 2 (cos(a pi/(k+1)) + cos(b pi/(k+1)) + cos(c pi/(k+1))); its
+    upwind convection-diffusion variant has zero interior row sums; the CRS
+    product equals the dense product built entry by entry."""
+    from oracle import sparse_ir as S
+
+    k = 5
+    rp, ci, v, b, x = gen.sparse_convdiff3d(k, 0.0, 1)
+    A = _dense_from_csr(rp, ci, v)
+    t = np.cos(np.arange(1, k + 1) * np.pi / (k + 1))
+    lam = np.sort((6 - 2 * (t[:, None, None] + t[None, :, None] + t[None, None, :])).ravel())
+    assert np.allclose(np.linalg.eigvalsh(A), lam, atol=1e-12)
+    assert np.allclose(A @ x, b, atol=1e-14)
+    rp2, ci2, v2, b2, x2 = gen.sparse_convdiff3d(k, 0.7, 2)
+    A2 = _dense_from_csr(rp2, ci2, v2)
+    interior = [i + k * j + k * k * l for l in range(1, k - 1) for j in range(1, k - 1)
+                for i in range(1, k - 1)]
+    assert np.allclose(A2[interior].sum(axis=1), 0.0, atol=1e-13)
+    g = np.random.default_rng(4)
+    u = g.standard_normal(k ** 3)
+    assert np.allclose(S.csr_matvec(rp2, ci2, v2, u), A2 @ u, atol=1e-13)
+    assert S.norm_inf_csr(rp2, v2) == pytest.approx(np.abs(A2).sum(axis=1).max())
+
+
+def test_gmres_cycle_closed_forms():
+    """GMRES(1) from zero is the minimal-residual step z = (v.Av / Av.Av) v;
+    GMRES(n) in FP64 exhausts the Krylov space and solves the system."""
+    from oracle import sparse_ir as S
+
+    rp, ci, v, _, _ = gen.sparse_convdiff3d(3, 0.4, 5)
+    A = _dense_from_csr(rp, ci, v)
+    g = np.random.default_rng(6)
+    w = g.standard_normal(27)
+    mv = lambda u: A @ u
+    z, k = S.gmres_cycle(mv, w, 1, np.float64)
+    Aw = A @ w
+    assert k == 1 and np.allclose(z, (w @ Aw) / (Aw @ Aw) * w, rtol=1e-13)
+    z, k = S.gmres_cycle(mv, w, 27, np.float64)
+    assert np.linalg.norm(A @ z - w) <= 1e-12 * np.linalg.norm(w)
+    # single precision: the residual stalls near the FP32 unit roundoff, not below
+    z32, _ = S.gmres_cycle(lambda u: (A.astype(np.float32) @ u), w.astype(np.float32), 27,
+                           np.float32)
+    rel = np.linalg.norm(A @ z32.astype(np.float64) - w) / np.linalg.norm(w)
+    assert 1e-9 < rel < 1e-5
+
+
+def test_fgmres_gmres_sp_solves():
+    """Algorithm 2 on Poisson and convection-diffusion: the stopping rule
+    holds for the returned x, which matches the dense direct solution; FP64
+    inner solves (the GMRES_DP variant) also converge; on the identity FP64
+    inner cycles finish in at most two applications, while FP32 inner cycles
+    need a few outer steps to remove their rounding."""
+    from oracle import sparse_ir as S
+
+    for k, p in ((6, 0.0), (7, 1.5)):
+        rp, ci, v, b, x_true = gen.sparse_convdiff3d(k, p, 10 + k)
+        A = _dense_from_csr(rp, ci, v)
+        for dt in (np.float32, np.float64):
+            r = S.fgmres_gmres(rp, ci, v, b, m_out=8, m_in=10, inner_dtype=dt)
+            assert r.converged, (k, p, dt)
+            res = b - A @ r.x
+            assert np.abs(res).max() <= np.sqrt(len(b)) * 2.0 ** -53 * np.abs(A).sum(1).max() * \
+                np.abs(r.x).max()
+            xs = np.linalg.solve(A, b)
+            assert np.abs(r.x - xs).max() <= 1e-12 * np.linalg.cond(A) * np.abs(xs).max()
+    n = 10
+    rp = np.arange(n + 1, dtype=np.int32)
+    ci = np.arange(n, dtype=np.int32)
+    b = np.random.default_rng(1).uniform(-1, 1, n)
+    # FP64 inner solves invert the identity up to FP64 rounding: at most a
+    # second application removes it
+    r = S.fgmres_gmres(rp, ci, np.ones(n), b, m_out=5, m_in=5, inner_dtype=np.float64)
+    assert r.converged and r.inner_calls <= 2 and np.abs(r.x - b).max() <= 4e-16
+    # FP32 inner solves leave a rounding-size residual for the outer steps to remove
+    r = S.fgmres_gmres(rp, ci, np.ones(n), b, m_out=5, m_in=5)
+    assert r.converged and 1 < r.inner_calls <= 5 and np.abs(r.x - b).max() <= 4e-16
