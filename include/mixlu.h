@@ -146,7 +146,8 @@ typedef struct {
                       ||r||_inf <= sqrt(n) 2^-53 ||A||_inf ||x||_inf       */
     float cond_est; /* kappa_1 estimate when opts.condest asked for it,
                        else 0                                            */
-    int reserved[2];
+    int outer;      /* mixlu_sparse_fgmres: outer FGMRES cycles run      */
+    int reserved[1];
 } mixlu_report;
 
 /* ----------------------------------------------------------- context */
@@ -355,6 +356,33 @@ int mixlu_batched_tune(mixlu_ctx_t ctx, int prec, int batch, const int *d_n,
    not one of the candidates). */
 int mixlu_batched_get_tiles(mixlu_ctx_t ctx, int prec, mixlu_batched_tiles *t);
 int mixlu_batched_set_tiles(mixlu_ctx_t ctx, int prec, const mixlu_batched_tiles *t);
+
+/* ------------------------------------------------------------- sparse */
+/* Inner-outer FGMRES(m_out)-GMRES(m_in) for a sparse A (Section 3.2,
+   Algorithm 2).  A is n x n in CRS storage (device): rowptr[n + 1],
+   colind[nnz] (0-based), vals[nnz] (FP64).  The outer flexible GMRES runs in
+   FP64 from x = 0: r = b - A x, the stopping test of Section 3 on this true
+   residual (||r||_inf <= sqrt(n) 2^-53 ||A||_inf ||x||_inf), then up to
+   m_out flexible Arnoldi steps whose preconditioner is one cycle of
+   GMRES(m_in) from zero in the inner precision (MIXLU_FP32: GMRES_SP on an
+   FP32 copy of the values; MIXLU_FP64: GMRES_DP), the FP64 product A z_k,
+   Gram-Schmidt against the basis (classical, applied twice) and the new
+   basis vector; a cycle ends early once its least-squares residual meets
+   the threshold; then x += Z y.  Every reduction of both loops runs on the
+   device; the small least-squares problems are solved on the host.  b and
+   x (device, n).  o->itermax bounds the outer cycles and o->stall applies
+   the refinement's stall rule to their residuals (NULL: defaults).  rep
+   (host): iter = inner cycles run (preconditioner applications), or -4 /
+   -(itermax+1) on failure (no direct fallback exists for a sparse A; x then
+   holds the last iterate), outer = outer cycles, rnorm/xnorm/berr of the
+   final x, anorm = ||A||_inf, prec = inner_prec.  Synchronizes. */
+int mixlu_sparse_workspace_size(mixlu_ctx_t ctx, int inner_prec, int n, int nnz,
+                                int m_out, int m_in, size_t *bytes);
+int mixlu_sparse_fgmres(mixlu_ctx_t ctx, int inner_prec, int n, int nnz,
+                        const int *rowptr, const int *colind,
+                        const double *vals, const double *b, double *x,
+                        int m_out, int m_in, void *work, size_t lwork,
+                        const mixlu_opts *o, mixlu_report *rep);
 
 /* Copy count reports from device memory (d, as filled by
    mixlu_dxgesv_batched) to host memory h, in order on the context's stream;

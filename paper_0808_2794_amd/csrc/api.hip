@@ -7,6 +7,7 @@
 // Section 4; fall back to FP64 when refinement cannot converge).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cmath>
 #include <cstdio>
@@ -1096,6 +1097,262 @@ int s_entry(mixlu_ctx_s *ctx, int n, int nrhs, const double *A, int lda, const d
     HIPCK(hipStreamSynchronize(ctx->stream));
     return MIXLU_OK;
 }
+
+// ---------------------------------------------------------------- sparse
+// Workspace of the sparse inner-outer solver (offsets in bytes).
+struct SparseLayout {
+    size_t vals_s;  // nnz values in the inner precision
+    size_t Vo, Zo;  // outer FP64 basis (m_out + 1 vectors) and preconditioned vectors (m_out)
+    size_t r, w;    // FP64 residual and work vector
+    size_t Vi, wi;  // inner basis (m_in + 1) and work vector, inner precision
+    size_t h;       // device scalars: two Gram-Schmidt passes and a squared norm
+    size_t y;       // least-squares solution staged for the basis update (doubles)
+    size_t norms;   // ||r||_inf, ||x||_inf
+    size_t total;
+};
+
+size_t plan_sparse(SparseLayout &S, int inner_prec, int n, int nnz, int m_out, int m_in) {
+    const size_t ts = inner_prec == MIXLU_FP64 ? 8 : 4;
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+    const int mh = (m_out > m_in ? m_out : m_in) + 2;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at_ = off;
+        off = align_up(off + bytes, 256);
+        return at_;
+    };
+    S.vals_s = take((size_t)(nnz > 0 ? nnz : 1) * ts);
+    S.Vo = take((size_t)(m_out + 1) * nn * 8);
+    S.Zo = take((size_t)m_out * nn * 8);
+    S.r = take(nn * 8);
+    S.w = take(nn * 8);
+    S.Vi = take((size_t)(m_in + 1) * nn * ts);
+    S.wi = take(nn * ts);
+    S.h = take((size_t)3 * mh * 8);
+    S.y = take((size_t)mh * 8);
+    S.norms = take(4 * 8);
+    S.total = off;
+    return off;
+}
+
+// Host side of one flexible/standard GMRES step: apply the earlier Givens
+// rotations to column j of H (rows 0..j+1), make the new one, update g.
+void givens_column(std::vector<double> &H, int ld, int j, std::vector<double> &cs,
+                   std::vector<double> &sn, std::vector<double> &g) {
+    auto Hat = [&](int i) -> double & { return H[(size_t)i * ld + j]; };
+    for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * Hat(i) + sn[i] * Hat(i + 1);
+        Hat(i + 1) = -sn[i] * Hat(i) + cs[i] * Hat(i + 1);
+        Hat(i) = t;
+    }
+    const double a = Hat(j), b = Hat(j + 1);
+    double c = 1.0, s = 0.0;
+    if (b != 0.0) {
+        const double r = std::hypot(a, b);
+        c = a / r;
+        s = b / r;
+    }
+    cs[j] = c;
+    sn[j] = s;
+    Hat(j) = c * a + s * b;
+    Hat(j + 1) = 0.0;
+    g[j + 1] = -s * g[j];
+    g[j] = c * g[j];
+}
+
+// y solving the k x k upper triangle of the rotated H against g.
+void back_substitute(const std::vector<double> &H, int ld, int k, const std::vector<double> &g,
+                     std::vector<double> &y) {
+    for (int i = k - 1; i >= 0; --i) {
+        double s = g[i];
+        for (int q = i + 1; q < k; ++q) s -= H[(size_t)i * ld + q] * y[q];
+        y[i] = s / H[(size_t)i * ld + i];
+    }
+}
+
+// One Arnoldi step on device vectors: w is orthogonalized against the k
+// basis vectors V (Gram-Schmidt twice, classical), its squared norm formed;
+// the host receives H[0..k-1][j] (both passes summed) and ||w||_2.
+template <typename T>
+int arnoldi_orth(mixlu_ctx_s *ctx, int n, int k, const T *V, T *w, T *hdev, std::vector<double> &col,
+                 double &wnorm) {
+    hipStream_t s = ctx->stream;
+    const size_t nn = (size_t)n;
+    T *h1 = hdev, *h2 = hdev + k, *hn = hdev + 2 * k;
+    HIPCK(launch_vdots<T>(n, k, V, nn, w, h1, s));
+    HIPCK(launch_vcombine<T>(n, k, V, nn, h1, w, s));
+    HIPCK(launch_vdots<T>(n, k, V, nn, w, h2, s));
+    HIPCK(launch_vcombine<T>(n, k, V, nn, h2, w, s));
+    HIPCK(launch_vdots<T>(n, 1, w, nn, w, hn, s));
+    T *hb = reinterpret_cast<T *>(ctx->hbuf);
+    HIPCK(hipMemcpyAsync(hb, hdev, (size_t)(2 * k + 1) * sizeof(T), hipMemcpyDeviceToHost, s));
+    HIPCK(hipStreamSynchronize(s));
+    for (int i = 0; i < k; ++i) col[i] = (double)hb[i] + (double)hb[k + i];
+    wnorm = std::sqrt((double)hb[2 * k]);
+    return MIXLU_OK;
+}
+
+// One GMRES(m) cycle from z = 0 for A z = v in precision T (values vals_t),
+// v given in FP64 (v64); z (FP64) = V y.  Returns the steps taken in *steps.
+template <typename T>
+int inner_gmres(mixlu_ctx_s *ctx, const SparseLayout &S, void *work, int n, const int *rowptr,
+                const int *colind, const T *vals_t, const double *v64, double *z64, int m,
+                int *steps) {
+    hipStream_t s = ctx->stream;
+    const size_t nn = (size_t)n;
+    T *Vi = at<T>(work, S.Vi), *w = at<T>(work, S.wi);
+    T *hdev = at<T>(work, S.h);
+    double *ydev = at<double>(work, S.y);
+    const double eps_rel = sizeof(T) == 4 ? 0x1p-24 : 0x1p-53;
+    *steps = 0;
+    // V_0 = v / ||v||
+    HIPCK((launch_convert_vec<double, T>(nn, v64, w, s)));
+    std::vector<double> col(m + 1), H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1, 0.0),
+        y(m);
+    double beta = 0.0;
+    {
+        T *hn = hdev;
+        HIPCK(launch_vdots<T>(n, 1, w, nn, w, hn, s));
+        T *hb = reinterpret_cast<T *>(ctx->hbuf);
+        HIPCK(hipMemcpyAsync(hb, hn, sizeof(T), hipMemcpyDeviceToHost, s));
+        HIPCK(hipStreamSynchronize(s));
+        beta = std::sqrt((double)hb[0]);
+        if (!(beta > 0.0)) {
+            HIPCK(launch_fill_f64(z64, 0.0, nn, s));
+            return MIXLU_OK;
+        }
+        HIPCK(launch_vscale<T>(n, w, hn, Vi, s));
+    }
+    g[0] = beta;
+    int k = 0;
+    for (int j = 0; j < m; ++j) {
+        HIPCK(launch_csr_spmv<T>(n, rowptr, colind, vals_t, Vi + (size_t)j * nn, w, s));
+        double wn = 0.0;
+        RETCK(arnoldi_orth<T>(ctx, n, j + 1, Vi, w, hdev, col, wn));
+        for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = col[i];
+        H[(size_t)(j + 1) * m + j] = wn;
+        givens_column(H, m, j, cs, sn, g);
+        k = j + 1;
+        if (!(wn > 0.0) || std::fabs(g[j + 1]) <= eps_rel * beta) break;
+        if (j + 1 < m)
+            HIPCK(launch_vscale<T>(n, w, hdev + 2 * (j + 1), Vi + (size_t)(j + 1) * nn, s));
+    }
+    back_substitute(H, m, k, g, y);
+    double *hy = ctx->hbuf + 2048;  // staging well past the words read back above
+    for (int i = 0; i < k; ++i) hy[i] = y[i];
+    HIPCK(hipMemcpyAsync(ydev, hy, (size_t)k * 8, hipMemcpyHostToDevice, s));
+    HIPCK(launch_fill_f64(z64, 0.0, nn, s));
+    HIPCK((launch_vaxpy_basis<T, double>(n, k, Vi, nn, ydev, z64, s)));
+    HIPCK(hipStreamSynchronize(s));  // hy is reused by the next call
+    *steps = k;
+    return MIXLU_OK;
+}
+
+template <typename T>
+int sparse_solve(mixlu_ctx_s *ctx, const SparseLayout &S, void *work, int n, int nnz,
+                 const int *rowptr, const int *colind, const double *vals, const double *b,
+                 double *x, int m_out, int m_in, const mixlu_opts &o, mixlu_report *rep) {
+    hipStream_t s = ctx->stream;
+    const size_t nn = (size_t)n;
+    const T *vals_t;
+    if constexpr (sizeof(T) == 4) {
+        float *vs = at<float>(work, S.vals_s);
+        HIPCK((launch_convert_vec<double, float>((size_t)nnz, vals, vs, s)));
+        vals_t = vs;
+    } else {
+        vals_t = vals;
+    }
+    double *Vo = at<double>(work, S.Vo), *Zo = at<double>(work, S.Zo);
+    double *r = at<double>(work, S.r), *w = at<double>(work, S.w);
+    double *hdev = at<double>(work, S.h), *ydev = at<double>(work, S.y);
+    double *norms = at<double>(work, S.norms);
+    double anorm = 0.0;
+    HIPCK(launch_fill_f64(norms, 0.0, 2, s));
+    HIPCK(launch_csr_norm_inf(n, rowptr, vals, norms, s));
+    HIPCK(hipMemcpyAsync(ctx->hbuf, norms, 8, hipMemcpyDeviceToHost, s));
+    HIPCK(hipStreamSynchronize(s));
+    anorm = ctx->hbuf[0];
+    const double thr = std::sqrt((double)n) * kEpsD * anorm;
+    HIPCK(launch_fill_f64(x, 0.0, nn, s));
+    std::vector<double> col(m_out + 1), H((size_t)(m_out + 1) * m_out), cs(m_out), sn(m_out),
+        g(m_out + 1), y(m_out);
+    double bnorm_inf = 0.0;
+    int inner_calls = 0, outer = 0;
+    double prev = 0.0, ratio_prev = 0.0;
+    double rn = 0.0, xn = 0.0;
+    int reason = 0;
+    for (int it = 0;; ++it) {
+        HIPCK(launch_fill_f64(norms, 0.0, 2, s));
+        HIPCK(launch_csr_resid(n, rowptr, colind, vals, x, b, r, norms, s));
+        HIPCK(launch_vdots<double>(n, 1, r, nn, r, hdev, s));
+        HIPCK(hipMemcpyAsync(ctx->hbuf, norms, 16, hipMemcpyDeviceToHost, s));
+        HIPCK(hipMemcpyAsync(ctx->hbuf + 2, hdev, 8, hipMemcpyDeviceToHost, s));
+        HIPCK(hipStreamSynchronize(s));
+        rn = ctx->hbuf[0];
+        xn = ctx->hbuf[1];
+        const double beta = std::sqrt(ctx->hbuf[2]);
+        if (it == 0) bnorm_inf = rn;  // x = 0: r = b
+        const bool finite = std::isfinite(rn) && std::isfinite(xn) && std::isfinite(beta);
+        if (finite && rn <= thr * xn) break;
+        if (!finite) {
+            reason = -4;
+            break;
+        }
+        if (it >= 1 && prev > 0.0) {
+            const double rho = rn / prev;
+            if ((it >= 2 && rho >= o.stall && ratio_prev >= o.stall) || (it >= 3 && rho >= 1.0)) {
+                reason = -4;
+                break;
+            }
+            ratio_prev = rho;
+        }
+        prev = rn;
+        if (it == o.itermax) {
+            reason = -(o.itermax + 1);
+            break;
+        }
+        const double scale = std::max(xn, anorm > 0.0 ? bnorm_inf / anorm : 0.0);
+        const double thr2 = thr * scale;
+        std::fill(H.begin(), H.end(), 0.0);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        HIPCK(launch_vscale<double>(n, r, hdev, Vo, s));
+        int k = 0;
+        for (int j = 0; j < m_out; ++j) {
+            int st = 0;
+            RETCK(inner_gmres<T>(ctx, S, work, n, rowptr, colind, vals_t, Vo + (size_t)j * nn,
+                                 Zo + (size_t)j * nn, m_in, &st));
+            ++inner_calls;
+            HIPCK(launch_csr_spmv<double>(n, rowptr, colind, vals, Zo + (size_t)j * nn, w, s));
+            double wn = 0.0;
+            RETCK(arnoldi_orth<double>(ctx, n, j + 1, Vo, w, hdev, col, wn));
+            for (int i = 0; i <= j; ++i) H[(size_t)i * m_out + j] = col[i];
+            H[(size_t)(j + 1) * m_out + j] = wn;
+            givens_column(H, m_out, j, cs, sn, g);
+            k = j + 1;
+            if (!(wn > 0.0) || std::fabs(g[j + 1]) <= thr2) break;
+            if (j + 1 < m_out)
+                HIPCK(launch_vscale<double>(n, w, hdev + 2 * (j + 1), Vo + (size_t)(j + 1) * nn,
+                                            s));
+        }
+        back_substitute(H, m_out, k, g, y);
+        double *hy = ctx->hbuf + 2048;
+        for (int i = 0; i < k; ++i) hy[i] = y[i];
+        HIPCK(hipMemcpyAsync(ydev, hy, (size_t)k * 8, hipMemcpyHostToDevice, s));
+        HIPCK((launch_vaxpy_basis<double, double>(n, k, Zo, nn, ydev, x, s)));
+        HIPCK(hipStreamSynchronize(s));
+        ++outer;
+    }
+    rep->iter = reason ? reason : inner_calls;
+    rep->converged = reason ? 0 : 1;
+    rep->outer = outer;
+    rep->anorm = anorm;
+    rep->rnorm = rn;
+    rep->xnorm = xn;
+    rep->berr = (xn > 0.0 && anorm > 0.0) ? rn / (anorm * xn) : 0.0;
+    return MIXLU_OK;
+}
+
 }  // namespace
 
 // ======================================================================
@@ -1335,6 +1592,55 @@ int mixlu_sgesv(mixlu_ctx_t ctx, int n, int nrhs, const double *A, int lda, cons
     if (!ctx) return -1;
     ProfCall pc_(ctx);
     return s_entry(ctx, n, nrhs, A, lda, B, ldb, X, ldx, work, lwork, info);
+}
+
+int mixlu_sparse_workspace_size(mixlu_ctx_t ctx, int inner_prec, int n, int nnz, int m_out,
+                                int m_in, size_t *bytes) {
+    if (!ctx) return -1;
+    if (inner_prec != MIXLU_FP32 && inner_prec != MIXLU_FP64) return -2;
+    if (n < 0) return -3;
+    if (nnz < 0) return -4;
+    if (m_out < 1 || m_out > kSparseMaxRestart) return -5;
+    if (m_in < 1 || m_in > kSparseMaxRestart) return -6;
+    if (!bytes) return -7;
+    SparseLayout S{};
+    *bytes = plan_sparse(S, inner_prec, n, nnz, m_out, m_in);
+    return MIXLU_OK;
+}
+
+int mixlu_sparse_fgmres(mixlu_ctx_t ctx, int inner_prec, int n, int nnz, const int *rowptr,
+                        const int *colind, const double *vals, const double *b, double *x,
+                        int m_out, int m_in, void *work, size_t lwork, const mixlu_opts *o,
+                        mixlu_report *rep) {
+    if (!ctx) return -1;
+    ProfCall pc_(ctx);
+    if (inner_prec != MIXLU_FP32 && inner_prec != MIXLU_FP64) return -2;
+    if (n < 0) return -3;
+    if (nnz < 0) return -4;
+    if (n > 0 && !rowptr) return -5;
+    if (nnz > 0 && !colind) return -6;
+    if (nnz > 0 && !vals) return -7;
+    if (n > 0 && !b) return -8;
+    if (n > 0 && !x) return -9;
+    if (m_out < 1 || m_out > kSparseMaxRestart) return -10;
+    if (m_in < 1 || m_in > kSparseMaxRestart) return -11;
+    if (n > 0 && !work) return -12;
+    if (!rep) return -15;
+    std::memset(rep, 0, sizeof(*rep));
+    rep->prec = inner_prec;
+    SparseLayout S{};
+    if (lwork < plan_sparse(S, inner_prec, n, nnz, m_out, m_in)) return MIXLU_ERR_WORKSPACE;
+    if (n == 0) {
+        rep->converged = 1;
+        return MIXLU_OK;
+    }
+    const mixlu_opts op_ = opts_or_default(o);
+    RETCK(ensure_hbuf(ctx, (size_t)(2048 + 2 * kSparseMaxRestart + 16) * 8));
+    if (inner_prec == MIXLU_FP32)
+        return sparse_solve<float>(ctx, S, work, n, nnz, rowptr, colind, vals, b, x, m_out, m_in,
+                                   op_, rep);
+    return sparse_solve<double>(ctx, S, work, n, nnz, rowptr, colind, vals, b, x, m_out, m_in,
+                                op_, rep);
 }
 
 int mixlu_report_read(mixlu_ctx_t ctx, const mixlu_report *d, int count, mixlu_report *h) {

@@ -22,6 +22,7 @@ constexpr int kXbufWords = 2 * (kPanelMaxWG * (4 + 64) + 64);  // panel exchange
 constexpr int kXcdStride = 8;      // workgroups are dealt round-robin to 8 XCDs
 constexpr int kTrsvBS = 64;        // rows per block of the chained solves
 constexpr int kTrsvNRT = 8;        // right-hand sides per chained-solve launch
+constexpr int kSparseMaxRestart = 512;  // largest m_out / m_in of the sparse solver
 constexpr int kColChunks = 64;   // row chunks of the column-statistics pass
 constexpr unsigned kSpinLimit = 1u << 23;  // polls before a device wait gives up
 constexpr int kKrylov = 30;         // flexible GMRES restart length
@@ -300,6 +301,27 @@ hipError_t launch_batched(int prec, int batch, int nrhs, int equil, int itermax,
                           const double *const *B, double *const *X, mixlu_report *rep,
                           int *order, int *counter, void *slots, int nslots,
                           const BatchedTiles &t, int num_cu, hipStream_t s);
+
+// sparse inner-outer solver (k_sparse.hip)
+template <typename TV>
+hipError_t launch_csr_spmv(int n, const int *rowptr, const int *colind, const TV *vals, const TV *x,
+                           TV *y, hipStream_t s);
+hipError_t launch_csr_resid(int n, const int *rowptr, const int *colind, const double *vals,
+                            const double *x, const double *b, double *r, double *norms,
+                            hipStream_t s);
+hipError_t launch_csr_norm_inf(int n, const int *rowptr, const double *vals, double *norms,
+                               hipStream_t s);
+template <typename TS, typename TD>
+hipError_t launch_convert_vec(size_t n, const TS *x, TD *y, hipStream_t s);
+template <typename T>
+hipError_t launch_vdots(int n, int k, const T *V, size_t ldv, const T *w, T *h, hipStream_t s);
+template <typename T>
+hipError_t launch_vcombine(int n, int k, const T *V, size_t ldv, const T *h, T *w, hipStream_t s);
+template <typename T>
+hipError_t launch_vscale(int n, const T *x, const T *den, T *y, hipStream_t s);
+template <typename TZ, typename TX>
+hipError_t launch_vaxpy_basis(int n, int k, const TZ *Z, size_t ldz, const double *y, TX *x,
+                              hipStream_t s);
 
 // kappa_1 estimate (k_condest.hip)
 hipError_t launch_cond_start(double *x, int n, int alt, hipStream_t s);

@@ -1,0 +1,211 @@
+// Kernels of the sparse inner-outer solver (Section 3.2, Algorithm 2:
+// FGMRES(m_out) in double precision around GMRES(m_in) in single
+// precision) on matrices in CRS storage.
+//
+//   k_csr_spmv      y = A x with the values in the inner precision (FP32
+//                   copy for GMRES_SP) or in FP64; one thread per row (the
+//                   stencil rows hold a few nonzeros)
+//   k_csr_resid     r = b - A x in FP64, with ||r||_inf and ||x||_inf
+//   k_csr_norm_inf  ||A||_inf
+//   k_to_float      the FP32 copy of the values (and of vectors)
+//   k_vdots         h[j] = V_j . w for j < k (one workgroup per j)
+//   k_vcombine      w -= sum_j h[j] V_j  (one pass of Gram-Schmidt)
+//   k_vscale        y = x / ||w||_2 (the squared norm from device memory)
+//   k_vaxpy_basis   x += sum_j y[j] Z_j (the FGMRES update, FP64)
+#include "common.h"
+
+namespace mixlu {
+
+template <typename TV>
+__global__ __launch_bounds__(256) void k_csr_spmv(int n, const int *__restrict__ rowptr,
+                                                  const int *__restrict__ colind,
+                                                  const TV *__restrict__ vals,
+                                                  const TV *__restrict__ x, TV *__restrict__ y) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    TV s = (TV)0;
+    for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) s += vals[p] * x[colind[p]];
+    y[i] = s;
+}
+
+__device__ __forceinline__ void amax_nonneg(double *p, double v) {
+    // non-negative doubles order like their bit patterns as integers
+    atomicMax(reinterpret_cast<unsigned long long *>(p), (unsigned long long)__double_as_longlong(v));
+}
+
+__global__ __launch_bounds__(256) void k_csr_resid(int n, const int *__restrict__ rowptr,
+                                                   const int *__restrict__ colind,
+                                                   const double *__restrict__ vals,
+                                                   const double *__restrict__ x,
+                                                   const double *__restrict__ b,
+                                                   double *__restrict__ r,
+                                                   double *__restrict__ norms) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    double ar = 0.0, ax = 0.0;
+    if (i < n) {
+        double s = 0.0;
+        for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) s += vals[p] * x[colind[p]];
+        const double v = b[i] - s;
+        r[i] = v;
+        ar = fabs(v);
+        ax = fabs(x[i]);
+        if (ar != ar) ar = __longlong_as_double(0x7ff0000000000000LL);  // NaN -> +inf
+        if (ax != ax) ax = __longlong_as_double(0x7ff0000000000000LL);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        ar = fmax(ar, __shfl_xor(ar, off));
+        ax = fmax(ax, __shfl_xor(ax, off));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        amax_nonneg(&norms[0], ar);
+        amax_nonneg(&norms[1], ax);
+    }
+}
+
+// norms[0] = max over rows of sum |a_ij| (||A||_inf), by atomic maximum
+__global__ __launch_bounds__(256) void k_csr_norm_inf(int n, const int *__restrict__ rowptr,
+                                                      const double *__restrict__ vals,
+                                                      double *__restrict__ norms) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    double sum = 0.0;
+    if (i < n)
+        for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) sum += fabs(vals[p]);
+    if (sum != sum) sum = __longlong_as_double(0x7ff0000000000000LL);
+    for (int off = 32; off > 0; off >>= 1) sum = fmax(sum, __shfl_xor(sum, off));
+    if ((threadIdx.x & 63) == 0) amax_nonneg(&norms[0], sum);
+}
+
+template <typename TS, typename TD>
+__global__ __launch_bounds__(256) void k_convert_vec(size_t n, const TS *__restrict__ x,
+                                                     TD *__restrict__ y) {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+        y[i] = (TD)x[i];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_vdots(int n, int k, const T *__restrict__ V, size_t ldv,
+                                               const T *__restrict__ w, T *__restrict__ h) {
+    const int j = blockIdx.x;
+    if (j >= k) return;
+    const T *v = V + (size_t)j * ldv;
+    T s = (T)0;
+    for (int i = threadIdx.x; i < n; i += 256) s += v[i] * w[i];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    __shared__ T part[4];
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) h[j] = (part[0] + part[1]) + (part[2] + part[3]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_vcombine(int n, int k, const T *__restrict__ V,
+                                                  size_t ldv, const T *__restrict__ h,
+                                                  T *__restrict__ w) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    T s = w[i];
+    for (int j = 0; j < k; ++j) s -= h[j] * V[(size_t)j * ldv + i];
+    w[i] = s;
+}
+
+// y = x / sqrt(*sq) (sq on the device: the squared norm just computed)
+template <typename T>
+__global__ __launch_bounds__(256) void k_vscale(int n, const T *__restrict__ x,
+                                                const T *__restrict__ sq, T *__restrict__ y) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) y[i] = x[i] / sqrt(sq[0]);
+}
+
+// x += sum_{j < k} y[j] Z_j, y from host-written device memory
+template <typename TZ, typename TX>
+__global__ __launch_bounds__(256) void k_vaxpy_basis(int n, int k, const TZ *__restrict__ Z,
+                                                     size_t ldz, const double *__restrict__ y,
+                                                     TX *__restrict__ x) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int j = 0; j < k; ++j) s += y[j] * (double)Z[(size_t)j * ldz + i];
+    x[i] = (TX)((double)x[i] + s);
+}
+
+// ------------------------------------------------------------ launchers
+static unsigned blocks_of(size_t n) { return (unsigned)((n + 255) / 256); }
+
+template <typename TV>
+hipError_t launch_csr_spmv(int n, const int *rowptr, const int *colind, const TV *vals, const TV *x,
+                           TV *y, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_csr_spmv<TV><<<blocks_of(n), 256, 0, s>>>(n, rowptr, colind, vals, x, y);
+    return hipGetLastError();
+}
+hipError_t launch_csr_resid(int n, const int *rowptr, const int *colind, const double *vals,
+                            const double *x, const double *b, double *r, double *norms,
+                            hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_csr_resid<<<blocks_of(n), 256, 0, s>>>(n, rowptr, colind, vals, x, b, r, norms);
+    return hipGetLastError();
+}
+hipError_t launch_csr_norm_inf(int n, const int *rowptr, const double *vals, double *norms,
+                               hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_csr_norm_inf<<<blocks_of(n), 256, 0, s>>>(n, rowptr, vals, norms);
+    return hipGetLastError();
+}
+template <typename TS, typename TD>
+hipError_t launch_convert_vec(size_t n, const TS *x, TD *y, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const unsigned g = blocks_of(n) < 4096 ? blocks_of(n) : 4096;
+    k_convert_vec<TS, TD><<<g, 256, 0, s>>>(n, x, y);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_vdots(int n, int k, const T *V, size_t ldv, const T *w, T *h, hipStream_t s) {
+    if (k <= 0) return hipSuccess;
+    k_vdots<T><<<k, 256, 0, s>>>(n, k, V, ldv, w, h);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_vcombine(int n, int k, const T *V, size_t ldv, const T *h, T *w, hipStream_t s) {
+    if (n <= 0 || k <= 0) return hipSuccess;
+    k_vcombine<T><<<blocks_of(n), 256, 0, s>>>(n, k, V, ldv, h, w);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_vscale(int n, const T *x, const T *den, T *y, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_vscale<T><<<blocks_of(n), 256, 0, s>>>(n, x, den, y);
+    return hipGetLastError();
+}
+template <typename TZ, typename TX>
+hipError_t launch_vaxpy_basis(int n, int k, const TZ *Z, size_t ldz, const double *y, TX *x,
+                              hipStream_t s) {
+    if (n <= 0 || k <= 0) return hipSuccess;
+    k_vaxpy_basis<TZ, TX><<<blocks_of(n), 256, 0, s>>>(n, k, Z, ldz, y, x);
+    return hipGetLastError();
+}
+
+template hipError_t launch_csr_spmv<float>(int, const int *, const int *, const float *,
+                                           const float *, float *, hipStream_t);
+template hipError_t launch_csr_spmv<double>(int, const int *, const int *, const double *,
+                                            const double *, double *, hipStream_t);
+template hipError_t launch_convert_vec<double, float>(size_t, const double *, float *, hipStream_t);
+template hipError_t launch_convert_vec<float, double>(size_t, const float *, double *, hipStream_t);
+template hipError_t launch_convert_vec<double, double>(size_t, const double *, double *,
+                                                       hipStream_t);
+template hipError_t launch_vdots<float>(int, int, const float *, size_t, const float *, float *,
+                                        hipStream_t);
+template hipError_t launch_vdots<double>(int, int, const double *, size_t, const double *,
+                                         double *, hipStream_t);
+template hipError_t launch_vcombine<float>(int, int, const float *, size_t, const float *,
+                                           float *, hipStream_t);
+template hipError_t launch_vcombine<double>(int, int, const double *, size_t, const double *,
+                                            double *, hipStream_t);
+template hipError_t launch_vscale<float>(int, const float *, const float *, float *, hipStream_t);
+template hipError_t launch_vscale<double>(int, const double *, const double *, double *,
+                                          hipStream_t);
+template hipError_t launch_vaxpy_basis<float, double>(int, int, const float *, size_t,
+                                                      const double *, double *, hipStream_t);
+template hipError_t launch_vaxpy_basis<double, double>(int, int, const double *, size_t,
+                                                       const double *, double *, hipStream_t);
+
+}  // namespace mixlu

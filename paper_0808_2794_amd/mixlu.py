@@ -39,13 +39,14 @@ class mixlu_report(ctypes.Structure):
                 ("fallback_iter", ctypes.c_int), ("anorm", ctypes.c_double),
                 ("rnorm", ctypes.c_double), ("xnorm", ctypes.c_double),
                 ("berr", ctypes.c_double), ("converged", ctypes.c_int),
-                ("cond_est", ctypes.c_float), ("reserved", ctypes.c_int * 2)]
+                ("cond_est", ctypes.c_float), ("outer", ctypes.c_int),
+                ("reserved", ctypes.c_int * 1)]
 
     def as_dict(self) -> dict:
         return {"iter": self.iter, "info": self.info, "prec": PREC_NAME.get(self.prec, self.prec),
                 "fallback_iter": self.fallback_iter, "anorm": self.anorm, "rnorm": self.rnorm,
                 "xnorm": self.xnorm, "berr": self.berr, "converged": bool(self.converged),
-                "cond_est": float(self.cond_est)}
+                "cond_est": float(self.cond_est), "outer": self.outer}
 
 
 class mixlu_factor(ctypes.Structure):
@@ -80,7 +81,8 @@ EXPORTS = ("mixlu_status_string", "mixlu_default_opts", "mixlu_create", "mixlu_d
            "mixlu_dposv", "mixlu_outer_update", "mixlu_batched_workspace_size",
            "mixlu_dxgesv_batched", "mixlu_profile_enable", "mixlu_profile_read",
            "mixlu_sgesv", "mixlu_report_read", "mixlu_batched_tune", "mixlu_batched_get_tiles",
-           "mixlu_batched_set_tiles", "mixlu_condest")
+           "mixlu_batched_set_tiles", "mixlu_condest", "mixlu_sparse_workspace_size",
+           "mixlu_sparse_fgmres")
 
 _lib = None
 
@@ -120,6 +122,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "mixlu_batched_get_tiles": ([P, I, P], I),
         "mixlu_batched_set_tiles": ([P, I, P], I),
         "mixlu_condest": ([P, P, P], I),
+        "mixlu_sparse_workspace_size": ([P, I, I, I, I, I, P], I),
+        "mixlu_sparse_fgmres": ([P, I, I, I, P, P, P, P, P, I, I, P, S, P, P], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -290,6 +294,28 @@ def mixlu_condest(ctx, F: mixlu_factor) -> float:
     k = ctypes.c_double()
     check(load().mixlu_condest(ctx, ctypes.byref(F), ctypes.byref(k)), "mixlu_condest")
     return k.value
+
+
+def mixlu_sparse_workspace_size(ctx, inner_prec: int, n: int, nnz: int, m_out: int,
+                                m_in: int) -> int:
+    out = ctypes.c_size_t()
+    check(load().mixlu_sparse_workspace_size(ctx, inner_prec, n, nnz, m_out, m_in,
+                                             ctypes.byref(out)), "mixlu_sparse_workspace_size")
+    return out.value
+
+
+def mixlu_sparse_fgmres(ctx, inner_prec: int, rowptr, colind, vals, b, x, m_out: int, m_in: int,
+                        work, opts=None) -> mixlu_report:
+    """Algorithm 2 on device CRS arrays (int32 rowptr / colind, FP64 vals);
+    x (device, FP64) receives the solution."""
+    rep = mixlu_report()
+    n = b.numel()
+    check(load().mixlu_sparse_fgmres(ctx, inner_prec, n, vals.numel(), _p(rowptr), _p(colind),
+                                     _p(vals), _p(b), _p(x), m_out, m_in, _p(work),
+                                     work.numel() * work.element_size(),
+                                     None if opts is None else ctypes.byref(opts),
+                                     ctypes.byref(rep)), "mixlu_sparse_fgmres")
+    return rep
 
 
 def mixlu_refine(ctx, F: mixlu_factor, A, B, X, opts=None, trans: int = 0) -> mixlu_report:
@@ -485,6 +511,20 @@ class Solver:
         """Enqueue the batched solve on the context's stream (no sync)."""
         mixlu_dxgesv_batched(self.ctx, buf["prec"], buf["n"], buf["pA"], None, buf["pB"],
                              buf["pX"], buf["nrhs"], buf["work"], buf["reps"], buf["opts"])
+
+    def sparse_fgmres(self, rowptr, colind, vals, b, inner="fp32", m_out=20, m_in=30,
+                      opts=None) -> Result:
+        """FGMRES(m_out)-GMRES(m_in) (Algorithm 2) for the CRS matrix on the
+        device; inner "fp32" is GMRES_SP, "fp64" GMRES_DP."""
+        import torch
+
+        p = PREC[inner]
+        n, nnz = b.numel(), vals.numel()
+        need = mixlu_sparse_workspace_size(self.ctx, p, n, nnz, m_out, m_in)
+        work = torch.empty(max(need, 256), dtype=torch.uint8, device="cuda")
+        x = torch.empty(n, dtype=torch.float64, device="cuda")
+        rep = mixlu_sparse_fgmres(self.ctx, p, rowptr, colind, vals, b, x, m_out, m_in, work, opts)
+        return Result(x, rep.as_dict())
 
     def tune_batched(self, buf):
         """Autotune the tile set for this batch's precision on this batch (the

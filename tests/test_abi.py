@@ -72,6 +72,9 @@ def test_host_only_new_entry_points():
     # layout: the condest option follows refine; the estimate follows converged
     assert mixlu.mixlu_opts.condest.offset == mixlu.mixlu_opts.refine.offset + 4
     assert mixlu.mixlu_report.cond_est.offset == mixlu.mixlu_report.converged.offset + 4
+    assert mixlu.mixlu_report.outer.offset == mixlu.mixlu_report.cond_est.offset + 4
+    assert lib.mixlu_sparse_fgmres(None, 1, 0, 0, None, None, None, None, None, 1, 1, None, 0,
+                                   None, None) == -1
     assert ctypes.sizeof(mixlu.mixlu_report) == 64
     o = mixlu.default_opts()
     assert o.condest == 0 and o.refine == mixlu.REFINE_CLASSIC
