@@ -40,7 +40,8 @@ PEAK_MFMA_TFS = {"fp16": 2500.0, "bf16": 2500.0, "fp8": 5000.0, "fp32": 157.3, "
 PEAK_VALU_TFS = {"fp32": 78.6, "fp64": 78.6}
 METRIC = "time to FP64-accurate solve, mixed vs FP64 LU on 1 GPU; MFMA util"
 DTYPE = {"fp32": "f32", "fp16": "f16", "bf16": "bf16", "fp64": "f64"}
-DEFAULT_PREC = {"dense": "fp32", "spd": "fp16", "batched": "fp32", "adjoint": "fp32"}
+DEFAULT_PREC = {"dense": "fp32", "spd": "fp16", "batched": "fp32", "adjoint": "fp32",
+                "sparse": "fp32"}
 
 
 def parse():
@@ -48,7 +49,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="dense", choices=["dense", "spd", "batched", "adjoint"])
+    ap.add_argument("--workload", default="dense",
+                    choices=["dense", "spd", "batched", "adjoint", "sparse"])
     ap.add_argument("--prec", default=None, choices=["fp32", "fp16", "bf16", "fp64"])
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--kappa", type=float, default=None)
@@ -136,7 +138,7 @@ def roofline(kstats, prec, steps, workload):
     if name == "trailing_update":
         rec = {"bound": "mfma", "achieved": st["flops"] / sec / 1e12,
                "peak": PEAK_MFMA_TFS[prec], "unit": "TFLOP/s"}
-    elif name in ("trsv", "residual", "pack_operands"):
+    elif name in ("trsv", "residual", "pack_operands", "sparse_spmv"):
         rec = {"bound": "hbm", "achieved": st["bytes"] / sec / 1e9, "peak": PEAK_HBM_GBS,
                "unit": "GB/s"}
     else:  # panels and the batched kernel: dependent steps on the vector ALUs
@@ -389,6 +391,58 @@ def run_batched(args, prec):
                   "max_fwd_err_vs_x_true": fwd}}
 
 
+def run_sparse(args, prec):
+    """Algorithm 2 (FGMRES(20)-GMRES_SP(30)) on the 3-D convection-diffusion
+    stand-in (k^3 grid, Peclet 1), against the same solver with FP64 inner
+    solves (FGMRES-GMRES_DP, the paper's comparison)."""
+    import numpy as np
+    import torch
+
+    from paper_0808_2794_amd import mixlu
+    from synth import gen
+
+    k = args.n or 64
+    peclet = 1.0
+    seed = args.seed or 950
+    m_out, m_in = 20, 30
+    rp, ci, v, b, x_true = gen.sparse_convdiff3d(k, peclet, seed)
+    solver = mixlu.Solver()
+    d = [torch.from_numpy(a).cuda() for a in (rp, ci, v, b)]
+    sync()
+    res = {}
+    for _ in range(args.warmup):
+        solver.sparse_fgmres(*d, inner=prec, m_out=m_out, m_in=m_in)
+    mixlu.mixlu_profile_enable(solver.ctx, True)
+
+    def one():
+        res["r"] = solver.sparse_fgmres(*d, inner=prec, m_out=m_out, m_in=m_in)
+
+    ms, _ = time_calls(one, args.steps)
+    kst = mixlu.mixlu_profile_read(solver.ctx)
+    mixlu.mixlu_profile_enable(solver.ctx, False)
+    rep = res["r"].report
+    fwd = float(np.abs(res["r"].x.cpu().numpy() - x_true).max() / np.abs(x_true).max())
+    comp = {}
+    if args.compare_steps > 0 and prec != "fp64":
+        solver.sparse_fgmres(*d, inner="fp64", m_out=m_out, m_in=m_in)
+        out = {}
+
+        def dp():
+            out["r"] = solver.sparse_fgmres(*d, inner="fp64", m_out=m_out, m_in=m_in)
+
+        comp["fgmres_gmres_dp_ms"], _ = time_calls(dp, args.compare_steps)
+        comp["fgmres_gmres_dp_inner_cycles"] = out["r"].report["iter"]
+        comparator_speedup(comp, ms)
+    solver.close()
+    return ms, kst, None, comp, {
+        "config": {"workload": f"sparse_convdiff3d_k{k}_peclet{peclet:g}_mout{m_out}_min{m_in}",
+                   "n": k ** 3, "nnz": int(len(v)), "seed": seed, "inner_precision": prec,
+                   "outer": "fp64 fgmres"},
+        "solve": {"inner_cycles": rep["iter"], "outer_cycles": rep["outer"],
+                  "converged": rep["converged"], "berr": rep["berr"],
+                  "fwd_err_vs_x_true": fwd}}
+
+
 def run_adjoint(args, prec):
     import numpy as np
     import torch
@@ -466,7 +520,7 @@ def main():
         return
     prec = args.prec or DEFAULT_PREC[args.workload]
     fn = {"dense": run_dense, "spd": run_spd, "batched": run_batched,
-          "adjoint": run_adjoint}[args.workload]
+          "adjoint": run_adjoint, "sparse": run_sparse}[args.workload]
     ms, kst, cpu, comp, extra = fn(args, prec)
     rl = roofline(kst, prec, args.steps, args.workload)
     line = {

@@ -393,7 +393,8 @@ int mixlu_report_read(mixlu_ctx_t ctx, const mixlu_report *d, int count,
 /* ------------------------------------------------------ kernel timing */
 /* Per-kernel-class timing for measurement: with profiling enabled, the
    launches of the main kernel classes ("panel_getf2", "trailing_update",
-   "pack_operands", "trsv", "residual", "panel_potf2", "batched_solve") are bracketed by HIP events on the
+   "pack_operands", "trsv", "residual", "panel_potf2", "batched_solve",
+   "sparse_spmv") are bracketed by HIP events on the
    context's stream, and each class accumulates its launch count, total
    device time and the algorithmic flops and bytes of its launches (the work
    the method requires, not the traffic the kernels generate).  Enabling

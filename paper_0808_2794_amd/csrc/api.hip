@@ -29,10 +29,10 @@ struct ProfPending {
     hipEvent_t a, b;
     double flops, bytes;
 };
-enum ProfClass { PC_PANEL, PC_TRAIL, PC_PACK, PC_TRSV, PC_RESID, PC_CPANEL, PC_BATCH, PC_COUNT };
+enum ProfClass { PC_PANEL, PC_TRAIL, PC_PACK, PC_TRSV, PC_RESID, PC_CPANEL, PC_BATCH, PC_SPMV, PC_COUNT };
 static const char *const kProfNames[PC_COUNT] = {"panel_getf2", "trailing_update", "pack_operands",
                                                  "trsv", "residual", "panel_potf2",
-                                                 "batched_solve"};
+                                                 "batched_solve", "sparse_spmv"};
 struct Prof {
     bool on = false;
     std::vector<hipEvent_t> pool;
@@ -1107,6 +1107,7 @@ struct SparseLayout {
     size_t Vi, wi;  // inner basis (m_in + 1) and work vector, inner precision
     size_t h;       // device scalars: two Gram-Schmidt passes and a squared norm
     size_t y;       // least-squares solution staged for the basis update (doubles)
+    size_t part;    // partial sums of the dot products
     size_t norms;   // ||r||_inf, ||x||_inf
     size_t total;
 };
@@ -1130,6 +1131,7 @@ size_t plan_sparse(SparseLayout &S, int inner_prec, int n, int nnz, int m_out, i
     S.wi = take(nn * ts);
     S.h = take((size_t)3 * mh * 8);
     S.y = take((size_t)mh * 8);
+    S.part = take((size_t)mh * kVdotsChunks * 8);
     S.norms = take(4 * 8);
     S.total = off;
     return off;
@@ -1174,16 +1176,16 @@ void back_substitute(const std::vector<double> &H, int ld, int k, const std::vec
 // basis vectors V (Gram-Schmidt twice, classical), its squared norm formed;
 // the host receives H[0..k-1][j] (both passes summed) and ||w||_2.
 template <typename T>
-int arnoldi_orth(mixlu_ctx_s *ctx, int n, int k, const T *V, T *w, T *hdev, std::vector<double> &col,
-                 double &wnorm) {
+int arnoldi_orth(mixlu_ctx_s *ctx, int n, int k, const T *V, T *w, T *hdev, T *part,
+                 std::vector<double> &col, double &wnorm) {
     hipStream_t s = ctx->stream;
     const size_t nn = (size_t)n;
     T *h1 = hdev, *h2 = hdev + k, *hn = hdev + 2 * k;
-    HIPCK(launch_vdots<T>(n, k, V, nn, w, h1, s));
+    HIPCK(launch_vdots<T>(n, k, V, nn, w, h1, part, s));
     HIPCK(launch_vcombine<T>(n, k, V, nn, h1, w, s));
-    HIPCK(launch_vdots<T>(n, k, V, nn, w, h2, s));
+    HIPCK(launch_vdots<T>(n, k, V, nn, w, h2, part, s));
     HIPCK(launch_vcombine<T>(n, k, V, nn, h2, w, s));
-    HIPCK(launch_vdots<T>(n, 1, w, nn, w, hn, s));
+    HIPCK(launch_vdots<T>(n, 1, w, nn, w, hn, part, s));
     T *hb = reinterpret_cast<T *>(ctx->hbuf);
     HIPCK(hipMemcpyAsync(hb, hdev, (size_t)(2 * k + 1) * sizeof(T), hipMemcpyDeviceToHost, s));
     HIPCK(hipStreamSynchronize(s));
@@ -1195,9 +1197,9 @@ int arnoldi_orth(mixlu_ctx_s *ctx, int n, int k, const T *V, T *w, T *hdev, std:
 // One GMRES(m) cycle from z = 0 for A z = v in precision T (values vals_t),
 // v given in FP64 (v64); z (FP64) = V y.  Returns the steps taken in *steps.
 template <typename T>
-int inner_gmres(mixlu_ctx_s *ctx, const SparseLayout &S, void *work, int n, const int *rowptr,
-                const int *colind, const T *vals_t, const double *v64, double *z64, int m,
-                int *steps) {
+int inner_gmres(mixlu_ctx_s *ctx, const SparseLayout &S, void *work, int n, int nnz,
+                const int *rowptr, const int *colind, const T *vals_t, const double *v64,
+                double *z64, int m, int *steps) {
     hipStream_t s = ctx->stream;
     const size_t nn = (size_t)n;
     T *Vi = at<T>(work, S.Vi), *w = at<T>(work, S.wi);
@@ -1212,7 +1214,7 @@ int inner_gmres(mixlu_ctx_s *ctx, const SparseLayout &S, void *work, int n, cons
     double beta = 0.0;
     {
         T *hn = hdev;
-        HIPCK(launch_vdots<T>(n, 1, w, nn, w, hn, s));
+        HIPCK(launch_vdots<T>(n, 1, w, nn, w, hn, at<T>(work, S.part), s));
         T *hb = reinterpret_cast<T *>(ctx->hbuf);
         HIPCK(hipMemcpyAsync(hb, hn, sizeof(T), hipMemcpyDeviceToHost, s));
         HIPCK(hipStreamSynchronize(s));
@@ -1226,9 +1228,12 @@ int inner_gmres(mixlu_ctx_s *ctx, const SparseLayout &S, void *work, int n, cons
     g[0] = beta;
     int k = 0;
     for (int j = 0; j < m; ++j) {
-        HIPCK(launch_csr_spmv<T>(n, rowptr, colind, vals_t, Vi + (size_t)j * nn, w, s));
+        {
+            ProfScope ps(PC_SPMV, 2.0 * nnz, (double)nnz * (sizeof(T) + 4) + 2.0 * nn * sizeof(T), s);
+            HIPCK(launch_csr_spmv<T>(n, rowptr, colind, vals_t, Vi + (size_t)j * nn, w, s));
+        }
         double wn = 0.0;
-        RETCK(arnoldi_orth<T>(ctx, n, j + 1, Vi, w, hdev, col, wn));
+        RETCK(arnoldi_orth<T>(ctx, n, j + 1, Vi, w, hdev, at<T>(work, S.part), col, wn));
         for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = col[i];
         H[(size_t)(j + 1) * m + j] = wn;
         givens_column(H, m, j, cs, sn, g);
@@ -1284,7 +1289,7 @@ int sparse_solve(mixlu_ctx_s *ctx, const SparseLayout &S, void *work, int n, int
     for (int it = 0;; ++it) {
         HIPCK(launch_fill_f64(norms, 0.0, 2, s));
         HIPCK(launch_csr_resid(n, rowptr, colind, vals, x, b, r, norms, s));
-        HIPCK(launch_vdots<double>(n, 1, r, nn, r, hdev, s));
+        HIPCK(launch_vdots<double>(n, 1, r, nn, r, hdev, at<double>(work, S.part), s));
         HIPCK(hipMemcpyAsync(ctx->hbuf, norms, 16, hipMemcpyDeviceToHost, s));
         HIPCK(hipMemcpyAsync(ctx->hbuf + 2, hdev, 8, hipMemcpyDeviceToHost, s));
         HIPCK(hipStreamSynchronize(s));
@@ -1320,12 +1325,16 @@ int sparse_solve(mixlu_ctx_s *ctx, const SparseLayout &S, void *work, int n, int
         int k = 0;
         for (int j = 0; j < m_out; ++j) {
             int st = 0;
-            RETCK(inner_gmres<T>(ctx, S, work, n, rowptr, colind, vals_t, Vo + (size_t)j * nn,
-                                 Zo + (size_t)j * nn, m_in, &st));
+            RETCK(inner_gmres<T>(ctx, S, work, n, nnz, rowptr, colind, vals_t,
+                                 Vo + (size_t)j * nn, Zo + (size_t)j * nn, m_in, &st));
             ++inner_calls;
-            HIPCK(launch_csr_spmv<double>(n, rowptr, colind, vals, Zo + (size_t)j * nn, w, s));
+            {
+                ProfScope ps(PC_SPMV, 2.0 * nnz, (double)nnz * 12 + 2.0 * nn * 8, s);
+                HIPCK(launch_csr_spmv<double>(n, rowptr, colind, vals, Zo + (size_t)j * nn, w, s));
+            }
             double wn = 0.0;
-            RETCK(arnoldi_orth<double>(ctx, n, j + 1, Vo, w, hdev, col, wn));
+            RETCK(arnoldi_orth<double>(ctx, n, j + 1, Vo, w, hdev, at<double>(work, S.part),
+                                       col, wn));
             for (int i = 0; i <= j; ++i) H[(size_t)i * m_out + j] = col[i];
             H[(size_t)(j + 1) * m_out + j] = wn;
             givens_column(H, m_out, j, cs, sn, g);

@@ -314,7 +314,9 @@ hipError_t launch_csr_norm_inf(int n, const int *rowptr, const double *vals, dou
 template <typename TS, typename TD>
 hipError_t launch_convert_vec(size_t n, const TS *x, TD *y, hipStream_t s);
 template <typename T>
-hipError_t launch_vdots(int n, int k, const T *V, size_t ldv, const T *w, T *h, hipStream_t s);
+hipError_t launch_vdots(int n, int k, const T *V, size_t ldv, const T *w, T *h, T *part,
+                        hipStream_t s);
+constexpr int kVdotsChunks = 256;  // most partial sums per dot product
 template <typename T>
 hipError_t launch_vcombine(int n, int k, const T *V, size_t ldv, const T *h, T *w, hipStream_t s);
 template <typename T>

@@ -8,7 +8,8 @@
 //   k_csr_resid     r = b - A x in FP64, with ||r||_inf and ||x||_inf
 //   k_csr_norm_inf  ||A||_inf
 //   k_to_float      the FP32 copy of the values (and of vectors)
-//   k_vdots         h[j] = V_j . w for j < k (one workgroup per j)
+//   k_vdots(_fin)   h[j] = V_j . w for j < k (chunks over many workgroups,
+//                   then the partial sums in a fixed order)
 //   k_vcombine      w -= sum_j h[j] V_j  (one pass of Gram-Schmidt)
 //   k_vscale        y = x / ||w||_2 (the squared norm from device memory)
 //   k_vaxpy_basis   x += sum_j y[j] Z_j (the FGMRES update, FP64)
@@ -82,19 +83,36 @@ __global__ __launch_bounds__(256) void k_convert_vec(size_t n, const TS *__restr
         y[i] = (TD)x[i];
 }
 
+// Dot products h[j] = V_j . w in two stages: workgroup (j, g) sums chunk g
+// of the n entries into part[j * G + g]; k_vdots_fin adds the G partial
+// sums of each j in a fixed order (so the result does not depend on
+// scheduling).
 template <typename T>
 __global__ __launch_bounds__(256) void k_vdots(int n, int k, const T *__restrict__ V, size_t ldv,
-                                               const T *__restrict__ w, T *__restrict__ h) {
-    const int j = blockIdx.x;
+                                               const T *__restrict__ w, T *__restrict__ part) {
+    const int j = blockIdx.x, g = blockIdx.y, G = gridDim.y;
     if (j >= k) return;
+    const int chunk = (n + G - 1) / G;
+    const int i0 = g * chunk, i1 = i0 + chunk < n ? i0 + chunk : n;
     const T *v = V + (size_t)j * ldv;
     T s = (T)0;
-    for (int i = threadIdx.x; i < n; i += 256) s += v[i] * w[i];
+    for (int i = i0 + threadIdx.x; i < i1; i += 256) s += v[i] * w[i];
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    __shared__ T part[4];
-    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+    __shared__ T red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
-    if (threadIdx.x == 0) h[j] = (part[0] + part[1]) + (part[2] + part[3]);
+    if (threadIdx.x == 0) part[(size_t)j * G + g] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_vdots_fin(int k, int G, const T *__restrict__ part,
+                                                  T *__restrict__ h) {
+    const int j = blockIdx.x;
+    if (j >= k) return;
+    T s = (T)0;
+    for (int g = threadIdx.x; g < G; g += 64) s += part[(size_t)j * G + g];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (threadIdx.x == 0) h[j] = s;
 }
 
 template <typename T>
@@ -159,9 +177,17 @@ hipError_t launch_convert_vec(size_t n, const TS *x, TD *y, hipStream_t s) {
     return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_vdots(int n, int k, const T *V, size_t ldv, const T *w, T *h, hipStream_t s) {
+hipError_t launch_vdots(int n, int k, const T *V, size_t ldv, const T *w, T *h, T *part,
+                        hipStream_t s) {
     if (k <= 0) return hipSuccess;
-    k_vdots<T><<<k, 256, 0, s>>>(n, k, V, ldv, w, h);
+    // about 4096 entries per workgroup, at most kVdotsChunks chunks
+    int G = (n + 4095) / 4096;
+    if (G < 1) G = 1;
+    if (G > kVdotsChunks) G = kVdotsChunks;
+    k_vdots<T><<<dim3(k, G), 256, 0, s>>>(n, k, V, ldv, w, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_vdots_fin<T><<<k, 64, 0, s>>>(k, G, part, h);
     return hipGetLastError();
 }
 template <typename T>
@@ -193,9 +219,9 @@ template hipError_t launch_convert_vec<float, double>(size_t, const float *, dou
 template hipError_t launch_convert_vec<double, double>(size_t, const double *, double *,
                                                        hipStream_t);
 template hipError_t launch_vdots<float>(int, int, const float *, size_t, const float *, float *,
-                                        hipStream_t);
+                                        float *, hipStream_t);
 template hipError_t launch_vdots<double>(int, int, const double *, size_t, const double *,
-                                         double *, hipStream_t);
+                                         double *, double *, hipStream_t);
 template hipError_t launch_vcombine<float>(int, int, const float *, size_t, const float *,
                                            float *, hipStream_t);
 template hipError_t launch_vcombine<double>(int, int, const double *, size_t, const double *,
