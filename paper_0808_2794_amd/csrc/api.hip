@@ -1253,6 +1253,8 @@ int inner_gmres(mixlu_ctx_s *ctx, const SparseLayout &S, void *work, int n, int 
     return MIXLU_OK;
 }
 
+// Algorithm 2 (FGMRES(m_out) in FP64 around one GMRES(m_in) cycle in
+// precision T per outer step) from x = 0; see mixlu_sparse_fgmres.
 template <typename T>
 int sparse_solve(mixlu_ctx_s *ctx, const SparseLayout &S, void *work, int n, int nnz,
                  const int *rowptr, const int *colind, const double *vals, const double *b,
