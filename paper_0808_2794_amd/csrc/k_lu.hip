@@ -726,7 +726,8 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const T *__re
 // Large-tile GEMM C -= A B (row-major, no transposes) for the big trailing
 // updates: 128 x 128 output tile per workgroup, 4 waves of 64 x 64 (4 x 4
 // MFMA 16x16x4 blocks each), K step BK with the next K slab prefetched into
-// registers while the current one is multiplied out of LDS.  LDS pitches
+// registers while the current one is multiplied out of LDS, and stored into
+// the second LDS buffer (one barrier per K slab).  LDS pitches
 // make the MFMA operand reads conflict-free: A is kept [m][k] with pitch
 // BK + 4, B [k][n] with pitch 128 + 16.
 template <typename T, int BK>
@@ -739,8 +740,10 @@ __global__ __launch_bounds__(256) void k_gemm_big(int M, int N, int K, const T *
     constexpr int NLA = BM * BK / V / 256;            // A vectors per thread per slab
     constexpr int NLB = BK * BN / V / 256;            // B vectors per thread per slab
     typedef T vec_t __attribute__((ext_vector_type(V)));
-    __shared__ __attribute__((aligned(16))) T sA[BM * PA];
-    __shared__ __attribute__((aligned(16))) T sB[BK * PB];
+    // two LDS buffers: the next slab is stored into one while the other is
+    // read, so each slab costs one barrier
+    __shared__ __attribute__((aligned(16))) T sA2[2][BM * PA];
+    __shared__ __attribute__((aligned(16))) T sB2[2][BK * PB];
     using acc_t = typename Mfma<T>::acc_t;
     int tx = blockIdx.x, ty = blockIdx.y;
     if (!tile_of(spare_xcd0, (N + BN - 1) / BN, (M + BM - 1) / BM, tx, ty)) return;
@@ -782,7 +785,9 @@ __global__ __launch_bounds__(256) void k_gemm_big(int M, int N, int K, const T *
             }
         }
     };
-    auto store = [&]() {
+    auto store = [&](int buf) {
+        T *sA = sA2[buf];
+        T *sB = sB2[buf];
 #pragma unroll
         for (int q = 0; q < NLA; ++q) {
             const int e = tid + q * 256;
@@ -799,11 +804,14 @@ __global__ __launch_bounds__(256) void k_gemm_big(int M, int N, int K, const T *
     // A, B row-major with 16-byte aligned rows are required for the vector
     // loads; the launcher checks lda, ldb and the base pointers
     load(0);
-    store();
+    store(0);
     __syncthreads();
+    int cur = 0;
     for (int k0 = 0; k0 < K; k0 += BK) {
         const bool more = k0 + BK < K;
         if (more) load(k0 + BK);
+        const T *sA = sA2[cur];
+        const T *sB = sB2[cur];
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
             const int kr = kk + (lane >> 4);
@@ -817,11 +825,10 @@ __global__ __launch_bounds__(256) void k_gemm_big(int M, int N, int K, const T *
 #pragma unroll
                 for (int j = 0; j < 4; ++j) acc[i][j] = Mfma<T>::mac(a[i], b[j], acc[i][j]);
         }
+        // the other buffer was last read before the previous barrier
+        if (more) store(cur ^ 1);
         __syncthreads();
-        if (more) {
-            store();
-            __syncthreads();
-        }
+        cur ^= 1;
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
