@@ -80,7 +80,7 @@ __global__ __launch_bounds__(256) void k_trsv(int upper, const T *__restrict__ W
                                               unsigned long long *__restrict__ yx,
                                               int *__restrict__ status) {
     constexpr int BS = kTrsvBS, PWV = Words<T>::n;
-    constexpr int JB = 4;                          // off-diagonal blocks per round trip
+    constexpr int JB = 1;                          // off-diagonal blocks per round trip
     constexpr int NWMAX = JB * BS * NRT * PWV;     // words of JB solution blocks
     constexpr int WPT = (NWMAX + 255) / 256;       // words per thread
     __shared__ T sL[BS][BS + 1];
