@@ -296,105 +296,115 @@ template hipError_t launch_trsv<double>(int, int, const double *, int, int, doub
                                         unsigned long long *, int *, hipStream_t);
 
 // One step of the blocked solve for several right-hand sides: workgroup
-// (x, y) takes the four columns 4y .. 4y+3 (one wave each).  Every
-// workgroup solves the 64 x 64 diagonal block at j0 for its columns (the
-// block's rows in registers, values shared with readlane); workgroup x = 0
-// stores the solved rows in Yout (never in Y, whose block rows the other
-// workgroups of the launch may still be reading), and workgroup x = 1 + t
-// updates the 64-row tile t of the rows still to be solved, in place in Y:
-// Y[rows] -= M[rows, j0:j0+64] Yj.  MODE 0: unit lower L, forward; 1: U,
-// backward; 2: U^T (lower, non-unit), forward; 3: L^T (unit upper),
-// backward.  The triangular matrix is M[r][c] = W[r][c] (modes 0, 1) or
-// W[c][r] (modes 2, 3).  Rows to update: j0+64 .. npad-1 (forward) or
-// 0 .. j0-1 (backward).
+// (x, y) takes the 16 columns 16y .. 16y+15, four per wave.  Every workgroup
+// solves the 64 x 64 diagonal block at j0 for its columns (the block's rows
+// in registers, values shared with readlane); workgroup x = 0 stores the
+// solved rows in Yout (never in Y, whose block rows the other workgroups of
+// the launch may still be reading), and workgroup x = 1 + t updates the
+// 64-row tile t of the rows still to be solved, in place in Y:
+// Y[rows] -= M[rows, j0:j0+64] Yj.  The tile is read once per workgroup with
+// coalesced loads, issued before the diagonal solve, and staged in LDS.
+// MODE 0: unit lower L, forward; 1: U, backward; 2: U^T (lower, non-unit),
+// forward; 3: L^T (unit upper), backward.  The triangular matrix is
+// M[r][c] = W[r][c] (modes 0, 1) or W[c][r] (modes 2, 3).  Rows to update:
+// j0+64 .. npad-1 (forward) or 0 .. j0-1 (backward).
 template <typename T, int MODE>
 __global__ __launch_bounds__(256) void k_trsm_step(const T *__restrict__ W, int ldw, int j0,
                                                    int npad, T *__restrict__ Y,
                                                    T *__restrict__ Yout, int ldy, int nrhs) {
-    constexpr int BS = kTrsvBS;
+    constexpr int BS = kTrsvBS, CPW = 4, CPG = 4 * CPW;  // columns per wave / workgroup
+    constexpr int TPT = BS * BS / 256;                    // tile elements per thread
     constexpr bool TR = MODE >= 2;
     constexpr bool FWD = MODE == 0 || MODE == 2;
     constexpr bool UNIT = MODE == 0 || MODE == 3;
     __shared__ T sd[BS][BS + 1];
-    __shared__ T sy[BS][4];
+    __shared__ T sw[BS][BS + 1];
+    __shared__ T sy[BS][CPG + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int col = blockIdx.y * 4 + wave;
-    // this workgroup's tile (workgroups x >= 1): its loads do not depend on
-    // the diagonal solve, so they are issued first and their latency hides
-    // behind it (the tile of M in registers for FP32 storage)
+    const int c0 = blockIdx.y * CPG + wave * CPW;  // this wave's first column
     const int t = blockIdx.x - 1;
     const int r0 = FWD ? j0 + BS + t * BS : t * BS;
-    const int row = r0 + lane;
     const int rows_end = FWD ? npad : j0;
-    const bool upd = blockIdx.x > 0 && row < rows_end && col < nrhs;
-    constexpr bool PRE = sizeof(T) == 4;
-    T wpre[PRE ? BS : 1];
-    T ypre = (T)0;
-    // the diagonal block's right-hand sides, also loaded ahead of the barrier
-    const T ydiag = col < nrhs ? Y[(size_t)(j0 + lane) * ldy + col] : (T)0;
-    if (upd) {
-        ypre = Y[(size_t)row * ldy + col];
-        if constexpr (PRE) {
+    const bool tile = blockIdx.x > 0 && r0 < rows_end;
+    const int row = r0 + lane;
+    // element e = tid + 256 i of a 64 x 64 block: (e / 64, e % 64) is
+    // (row, column) of W, so consecutive threads read consecutive words
+    T tv[TPT];
+    if (tile) {
 #pragma unroll
-            for (int k = 0; k < BS; ++k)
-                wpre[k] = TR ? W[(size_t)(j0 + k) * ldw + row] : W[(size_t)row * ldw + j0 + k];
+        for (int i = 0; i < TPT; ++i) {
+            const int e = tid + 256 * i, a = e / BS, b = e % BS;
+            tv[i] = TR ? W[(size_t)(j0 + a) * ldw + r0 + b] : W[(size_t)(r0 + a) * ldw + j0 + b];
         }
     }
-    for (int e = tid; e < BS * BS; e += 256) {
-        const int r = e / BS, c = e % BS;
-        const T v = W[(size_t)(j0 + r) * ldw + j0 + c];
-        if (TR) sd[c][r] = v;
-        else sd[r][c] = v;
+    T ypre[CPW], y[CPW];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+        const bool ok = c0 + c < nrhs;
+        y[c] = ok ? Y[(size_t)(j0 + lane) * ldy + c0 + c] : (T)0;
+        ypre[c] = (ok && tile) ? Y[(size_t)row * ldy + c0 + c] : (T)0;
+    }
+#pragma unroll
+    for (int i = 0; i < TPT; ++i) {
+        const int e = tid + 256 * i, a = e / BS, b = e % BS;
+        const T v = W[(size_t)(j0 + a) * ldw + j0 + b];
+        if (TR) sd[b][a] = v;
+        else sd[a][b] = v;
     }
     __syncthreads();
-    if (col < nrhs) {
+    {
         T mrow[BS];
 #pragma unroll
         for (int k = 0; k < BS; ++k) mrow[k] = sd[lane][k];
-        T y = ydiag;
         // reciprocal of this lane's diagonal entry, formed off the chain
         const T dinv = UNIT ? (T)1 : (T)1 / sd[lane][lane];
-        if constexpr (FWD) {
 #pragma unroll
-            for (int k = 0; k < BS; ++k) {
-                if constexpr (!UNIT) {
-                    const T yk = readlane_t(y, k) * readlane_t(dinv, k);
-                    if (lane == k) y = yk;
-                    else if (lane > k) y -= mrow[k] * yk;
-                } else {
-                    const T yk = readlane_t(y, k);
-                    if (lane > k) y -= mrow[k] * yk;
+        for (int kk = 0; kk < BS; ++kk) {
+            const int k = FWD ? kk : BS - 1 - kk;
+            const bool below = FWD ? lane > k : lane < k;
+            if constexpr (!UNIT) {
+                const T rk = readlane_t(dinv, k);
+#pragma unroll
+                for (int c = 0; c < CPW; ++c) {
+                    const T yk = readlane_t(y[c], k) * rk;
+                    if (lane == k) y[c] = yk;
+                    else if (below) y[c] -= mrow[k] * yk;
                 }
-            }
-        } else {
+            } else {
 #pragma unroll
-            for (int k = BS - 1; k >= 0; --k) {
-                if constexpr (!UNIT) {
-                    const T yk = readlane_t(y, k) * readlane_t(dinv, k);
-                    if (lane == k) y = yk;
-                    else if (lane < k) y -= mrow[k] * yk;
-                } else {
-                    const T yk = readlane_t(y, k);
-                    if (lane < k) y -= mrow[k] * yk;
+                for (int c = 0; c < CPW; ++c) {
+                    const T yk = readlane_t(y[c], k);
+                    if (below) y[c] -= mrow[k] * yk;
                 }
             }
         }
-        sy[lane][wave] = y;
-        if (blockIdx.x == 0) Yout[(size_t)(j0 + lane) * ldy + col] = y;
     }
-    if (blockIdx.x == 0) return;
-    __syncthreads();
-    // tile update: thread (row, wave) = (row, column)
-    if (!upd) return;
-    T acc = (T)0;
 #pragma unroll
-    for (int k = 0; k < BS; ++k) {
-        T m;
-        if constexpr (PRE) m = wpre[k];
-        else m = TR ? W[(size_t)(j0 + k) * ldw + row] : W[(size_t)row * ldw + j0 + k];
-        acc += m * sy[k][wave];
+    for (int c = 0; c < CPW; ++c) {
+        sy[lane][wave * CPW + c] = y[c];
+        if (blockIdx.x == 0 && c0 + c < nrhs) Yout[(size_t)(j0 + lane) * ldy + c0 + c] = y[c];
     }
-    Y[(size_t)row * ldy + col] = ypre - acc;
+    if (!tile) return;  // uniform over the workgroup
+    // M[row][k] = sw[row - r0][k]
+#pragma unroll
+    for (int i = 0; i < TPT; ++i) {
+        const int e = tid + 256 * i, a = e / BS, b = e % BS;
+        if (TR) sw[b][a] = tv[i];
+        else sw[a][b] = tv[i];
+    }
+    __syncthreads();
+    T acc[CPW];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) acc[c] = (T)0;
+#pragma unroll 16
+    for (int k = 0; k < BS; ++k) {
+        const T m = sw[lane][k];
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) acc[c] += m * sy[k][wave * CPW + c];
+    }
+#pragma unroll
+    for (int c = 0; c < CPW; ++c)
+        if (c0 + c < nrhs) Y[(size_t)row * ldy + c0 + c] = ypre[c] - acc[c];
 }
 
 template <typename Tw>
@@ -408,7 +418,7 @@ hipError_t launch_trsm_blocked(int upper, int trans, const Tw *W, int ldw, int n
     for (int t = 0; t < nblk; ++t) {
         const int b = upper ? nblk - 1 - t : t;
         const int tiles = upper ? b : nblk - 1 - b;
-        const dim3 grid(1 + tiles, (nrhs + 3) / 4);
+        const dim3 grid(1 + tiles, (nrhs + 15) / 16);
         const int j0 = b * BS;
         switch (mode) {
             case 0: k_trsm_step<Tw, 0><<<grid, 256, 0, s>>>(W, ldw, j0, npad, Y, Yout, ldy, nrhs); break;
