@@ -102,11 +102,12 @@ def time_calls(fn, k):
     return (time.perf_counter() - t0) / k * 1e3, out
 
 
-def source_digest():
-    """Digest of the kernel sources, to tie stored counter readings to them."""
+def source_digest(names=None):
+    """Digest of the kernel sources (all of them, or the named files), to tie
+    stored counter readings to the code they were taken on."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_0808_2794_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
+    for name in sorted(names or os.listdir(csrc)):
         if name.endswith((".hip", ".h")):
             with open(os.path.join(csrc, name), "rb") as f:
                 h.update(name.encode() + f.read())
@@ -123,7 +124,9 @@ def stored_traffic(workload, kernel_class):
             rec = json.load(f).get(workload, {}).get(kernel_class)
     except (OSError, ValueError):
         return None
-    if not rec or rec.get("source_digest") != source_digest():
+    # a record names the files that define its kernel (the kernel's own file
+    # and the shared header); without that list every kernel source counts
+    if not rec or rec.get("source_digest") != source_digest(rec.get("sources")):
         return None
     return rec.get("bytes_per_launch")
 
