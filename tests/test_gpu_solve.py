@@ -315,3 +315,35 @@ def test_sgesv_empty(solver):
     A = torch.zeros((0, 0), dtype=torch.float64, device="cuda")
     B = torch.zeros((0, 1), dtype=torch.float64, device="cuda")
     assert solver.sgesv(A, B).report["info"] == 0
+
+
+@pytest.mark.parametrize("kind,trans", [("lu", 0), ("lu", 1), ("chol", 0)])
+@pytest.mark.parametrize("n,nrhs", [(300, 33), (200, 65)])
+def test_getrs_multi_rhs_fp32(solver, kind, trans, n, nrhs):
+    """Low-precision solve alone with FP32 factors and right-hand-side counts
+    that leave a ragged group of columns (16 per workgroup), in the plain and
+    the transposed modes, against a LAPACK solve (numpy).  With kappa = 1e2
+    the FP32 solve is accurate to about kappa * sqrt(n) * 2^-24 ~ 1e-4; an
+    index or layout mistake gives O(1) errors."""
+    import torch
+
+    from paper_0808_2794_amd import mixlu
+
+    if kind == "lu":
+        A, b, _ = gen.prescribed_cond_system(n, 1e2, 190 + n, nrhs=nrhs)
+    else:
+        A, b, _ = gen.spd_system(n, 1e2, 190 + n, nrhs=nrhs)
+    _say(f"getrs {kind} fp32 trans={trans} n={n} nrhs={nrhs}")
+    Ad, bd = _to_dev(A, b)
+    o = mixlu.default_opts(equilibrate=0)
+    op = mixlu.OP_GESV if kind == "lu" else mixlu.OP_POSV
+    work = solver.workspace(op, mixlu.FP32, n, nrhs, o)
+    fac = mixlu.mixlu_getrf if kind == "lu" else mixlu.mixlu_potrf
+    F, info = fac(solver.ctx, mixlu.FP32, Ad, work, o)
+    assert info == 0
+    X = torch.empty_like(bd)
+    mixlu.mixlu_getrs(solver.ctx, F, bd, X, trans=trans)
+    torch.cuda.synchronize()
+    x = X.cpu().numpy()
+    xr = np.linalg.solve(A.T if trans else A, b)
+    assert np.abs(x - xr).max() / np.abs(xr).max() <= 2e-3, np.abs(x - xr).max()
