@@ -207,10 +207,19 @@ __global__ __launch_bounds__(256) void k_trsv(int upper, const T *__restrict__ W
         T lrow[BS];
 #pragma unroll
         for (int k = 0; k < BS; ++k) lrow[k] = sL[lane][k];
-        // reciprocal of this lane's diagonal entry, computed off the chain:
-        // the dependent steps then multiply instead of divide
-        const T dinv = (T)1 / sL[lane][lane];
-        if (!upper && !TRANS) {  // unit lower
+        // non-unit triangles: scale this lane's row and value by the
+        // reciprocal of its diagonal entry before the chain (the system
+        // D^-1 M y = D^-1 r has a unit diagonal), so every dependent step is
+        // one broadcast and one FMA
+        const bool unit = upper == (int)TRANS;  // L (forward) or L^T (backward)
+        if (!unit) {
+            const T dinv = (T)1 / sL[lane][lane];
+#pragma unroll
+            for (int k = 0; k < BS; ++k) lrow[k] *= dinv;
+#pragma unroll
+            for (int c = 0; c < NRT; ++c) sv[c] *= dinv;
+        }
+        if (!upper) {  // forward
 #pragma unroll
             for (int k = 0; k < BS; ++k) {
 #pragma unroll
@@ -219,35 +228,13 @@ __global__ __launch_bounds__(256) void k_trsv(int upper, const T *__restrict__ W
                     if (lane > k) sv[c] -= lrow[k] * yk;
                 }
             }
-        } else if (!upper) {  // non-unit lower (U^T)
-#pragma unroll
-            for (int k = 0; k < BS; ++k) {
-                const T rk = bcast_lane(dinv, k);
-#pragma unroll
-                for (int c = 0; c < NRT; ++c) {
-                    const T yk = bcast_lane(sv[c], k) * rk;
-                    if (lane == k) sv[c] = yk;
-                    else if (lane > k) sv[c] -= lrow[k] * yk;
-                }
-            }
-        } else if (TRANS) {  // unit upper (L^T)
+        } else {  // backward
 #pragma unroll
             for (int k = BS - 1; k >= 0; --k) {
 #pragma unroll
                 for (int c = 0; c < NRT; ++c) {
                     const T yk = bcast_lane(sv[c], k);
                     if (lane < k) sv[c] -= lrow[k] * yk;
-                }
-            }
-        } else {
-#pragma unroll
-            for (int k = BS - 1; k >= 0; --k) {
-                const T rk = bcast_lane(dinv, k);
-#pragma unroll
-                for (int c = 0; c < NRT; ++c) {
-                    const T yk = bcast_lane(sv[c], k) * rk;
-                    if (lane == k) sv[c] = yk;
-                    else if (lane < k) sv[c] -= lrow[k] * yk;
                 }
             }
         }
@@ -356,26 +343,25 @@ __global__ __launch_bounds__(256) void k_trsm_step(const T *__restrict__ W, int 
         T mrow[BS];
 #pragma unroll
         for (int k = 0; k < BS; ++k) mrow[k] = sd[lane][k];
-        // reciprocal of this lane's diagonal entry, formed off the chain
-        const T dinv = UNIT ? (T)1 : (T)1 / sd[lane][lane];
+        // non-unit triangles: scale this lane's row and values by the
+        // reciprocal of its diagonal entry before the chain (the system
+        // D^-1 M y = D^-1 r has a unit diagonal), so every dependent step is
+        // one broadcast and one FMA per column
+        if constexpr (!UNIT) {
+            const T dinv = (T)1 / sd[lane][lane];
+#pragma unroll
+            for (int k = 0; k < BS; ++k) mrow[k] *= dinv;
+#pragma unroll
+            for (int c = 0; c < CPW; ++c) y[c] *= dinv;
+        }
 #pragma unroll
         for (int kk = 0; kk < BS; ++kk) {
             const int k = FWD ? kk : BS - 1 - kk;
             const bool below = FWD ? lane > k : lane < k;
-            if constexpr (!UNIT) {
-                const T rk = readlane_t(dinv, k);
 #pragma unroll
-                for (int c = 0; c < CPW; ++c) {
-                    const T yk = readlane_t(y[c], k) * rk;
-                    if (lane == k) y[c] = yk;
-                    else if (below) y[c] -= mrow[k] * yk;
-                }
-            } else {
-#pragma unroll
-                for (int c = 0; c < CPW; ++c) {
-                    const T yk = readlane_t(y[c], k);
-                    if (below) y[c] -= mrow[k] * yk;
-                }
+            for (int c = 0; c < CPW; ++c) {
+                const T yk = readlane_t(y[c], k);
+                if (below) y[c] -= mrow[k] * yk;
             }
         }
     }
