@@ -185,7 +185,9 @@ typedef struct {
     int kind;          /* 0 LU with partial pivoting, 1 Cholesky (lower)   */
     int layout;        /* layout of the A it was computed from             */
     int equilibrated;  /* 1 when R, C scaling was applied                  */
-    int lowp_status;   /* 0 ok; -2 conversion overflow; -3 breakdown       */
+    int lowp_status;   /* 0 ok; -2 conversion overflow; -3 breakdown;
+                          -1 the FP64 fallback factor that mixlu_refine
+                          left in the workspace is singular (X undefined) */
     int nrhs_max;      /* most right-hand sides one solve may have: what
                           the workspace given to the factorization holds  */
     void *work;        /* the workspace (device)                           */
@@ -234,7 +236,13 @@ int mixlu_getrs(mixlu_ctx_t ctx, const mixlu_factor *F, int trans, int nrhs,
    factorization in the workspace finishes the job).  trans = 1 refines
    A^T X = B (residual B - A^T X in FP64, stopping test with ||A||_1).
    B and X are n x nrhs, nrhs <= F->nrhs_max.  rep (host) is filled; the
-   stream is synchronized. */
+   stream is synchronized.  When the fallback runs, *F is rewritten to
+   describe the FP64 factor it leaves in the workspace (F->prec =
+   MIXLU_FP64, unit scales, no further fallback; F->lowp_status = -1 if that
+   factor is singular): the low-precision factor's pivots and scales are
+   overwritten by it, so later mixlu_getrs, mixlu_refine and mixlu_condest
+   calls with F solve with the FP64 factor (the adjoint of a solve that
+   fell back uses the FP64 factor too). */
 int mixlu_refine(mixlu_ctx_t ctx, mixlu_factor *F, int trans, int nrhs,
                  const double *A, int lda, const double *B, int ldb, double *X,
                  int ldx, const mixlu_opts *o, mixlu_report *rep);
@@ -301,6 +309,25 @@ int mixlu_dposv(mixlu_ctx_t ctx, int n, int nrhs, const double *A, int lda,
 int mixlu_outer_update(mixlu_ctx_t ctx, int n, int nrhs, const double *Gb,
                        int ldg, const double *X, int ldx, double *GA, int ldga,
                        double alpha, double GA_beta);
+
+/* The trailing-matrix update of the factorization on its own: C -= A B,
+   the one O(n^3) operation of the LU, which Section 2.1 performs in the low
+   precision eps_s.  A (m x k), B (k x n) and C (m x n) are row-major FP32
+   device matrices (leading dimensions lda >= k, ldb >= n, ldc >= n).  The
+   operands are used as the factorization uses L21 and U12:
+   MIXLU_FP32: as stored (FP32 MFMA); MIXLU_BF16 / MIXLU_FP16: rounded to
+   nearest even (k a multiple of 64); MIXLU_FP8: E4M3 codes (round to
+   nearest even, saturating at 448) with one E8M0 power-of-two scale per 32
+   consecutive k values of each row of A and each column of B, the scale
+   putting the block's largest magnitude in [2^7, 2^8) (k a multiple of
+   128).  Products accumulate in FP32.  work (device) holds the rounded
+   operands: lwork >= 2 (m + n) k + (m + n) k / 32 + 1024 bytes (unused for
+   FP32).  *overflow (host, may be NULL) receives the number of operands
+   outside the format's range (FP16: |x| > 65504; FP8: non-finite blocks);
+   passing it synchronizes the stream, otherwise the call is asynchronous. */
+int mixlu_gemm_update(mixlu_ctx_t ctx, int prec, int m, int n, int k,
+                      const float *A, int lda, const float *B, int ldb, float *C,
+                      int ldc, void *work, size_t lwork, int *overflow);
 
 /* ------------------------------------------------------------ batched */
 /* Many independent systems A_i x_i = b_i (each n_i <= 512), every one

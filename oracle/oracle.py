@@ -69,6 +69,8 @@ def _load():
     lib.orc_spotrf.restype = I
     lib.orc_dpotrs.argtypes = [I, I, P, I, P, I]
     lib.orc_dpotrs.restype = None
+    lib.orc_spotrs.argtypes = [I, I, P, I, P, I]
+    lib.orc_spotrs.restype = None
     lib.orc_residual.argtypes = [I, I, P, I, P, I, P, I, P, I, I]
     lib.orc_residual.restype = None
     lib.orc_residual_ld.argtypes = [I, I, P, I, P, I, P, I, P, P]
@@ -154,6 +156,17 @@ def spotrf(A):
     n = L.shape[0]
     info = _load().orc_spotrf(n, _ptr(L), n)
     return np.tril(L), info
+
+
+def spotrs(L, B):
+    """FP32 L L^T x = b with the factor of ``spotrf`` (the SPOTRS of the
+    single-precision variant)."""
+    L = _c(L, np.float32)
+    B2, vec = _as2d(B)
+    X = np.array(B2, dtype=np.float32, order="C", copy=True)
+    n, nrhs = X.shape
+    _load().orc_spotrs(n, nrhs, _ptr(L), L.shape[1], _ptr(X), nrhs)
+    return X.ravel() if vec else X
 
 
 def potrs(L, B):

@@ -1555,6 +1555,16 @@ int mixlu_refine(mixlu_ctx_t ctx, mixlu_factor *F, int trans, int nrhs, const do
     LoopResult fres{};
     RETCK(fp64_path(ctx, F->work, L, L.W64, A, lda, B, ldb, X, ldx, nrhs, op_, true, &info, &fres,
                     tr, cm));
+    // The FP64 factorization rewrote the pivots, permutation, scales and
+    // status words that the low-precision factor in W shares with it.  From
+    // here on F describes the FP64 factor in W64 (unit scales, no further
+    // fallback), so later solves, refinements and estimates with F use
+    // consistent data instead of mixing the two factorizations.
+    F->prec = MIXLU_FP64;
+    F->equilibrated = 0;
+    F->off[0] = L.W64;
+    F->off[1] = 0;
+    F->lowp_status = info ? -1 : 0;
     rep->info = info;
     rep->prec = MIXLU_FP64;
     rep->fallback_iter = fres.iters;
@@ -1841,6 +1851,68 @@ int mixlu_profile_read(mixlu_ctx_t ctx, mixlu_kstat *out, int max, int *count) {
         out[i].bytes = ctx->prof.acc[i].bytes;
     }
     *count = PC_COUNT;
+    return MIXLU_OK;
+}
+
+int mixlu_gemm_update(mixlu_ctx_t ctx, int prec, int m, int n, int k, const float *A, int lda,
+                      const float *B, int ldb, float *C, int ldc, void *work, size_t lwork,
+                      int *overflow) {
+    if (!ctx) return -1;
+    ProfCall pc_(ctx);
+    if (prec != MIXLU_FP32 && !is_lowp(prec)) return -2;
+    if (m < 0) return -3;
+    if (n < 0) return -4;
+    if (k < 0 || (is_lowp(prec) && k % (prec == MIXLU_FP8 ? 128 : 64))) return -5;
+    if (m > 0 && k > 0 && !A) return -6;
+    if (lda < (k > 1 ? k : 1)) return -7;
+    if (k > 0 && n > 0 && !B) return -8;
+    if (ldb < (n > 1 ? n : 1)) return -9;
+    if (m > 0 && n > 0 && !C) return -10;
+    if (ldc < (n > 1 ? n : 1)) return -11;
+    const size_t mk = (size_t)m * k, nk = (size_t)n * k;
+    const size_t need = 2 * (mk + nk) + (mk + nk) / 32 + 1024;
+    if (is_lowp(prec) && !work) return -12;
+    if (is_lowp(prec) && lwork < need) return MIXLU_ERR_WORKSPACE;
+    hipStream_t s = ctx->stream;
+    if (overflow) *overflow = 0;
+    if (m == 0 || n == 0 || k == 0) return MIXLU_OK;
+    if (prec == MIXLU_FP32) {
+        ProfScope ps(PC_TRAIL, 2.0 * m * n * k, 8.0 * m * n + 4.0 * (mk + nk), s);
+        HIPCK(launch_gemm<float>(m, n, k, A, lda, B, ldb, C, ldc, s));
+        return MIXLU_OK;
+    }
+    auto *base = static_cast<unsigned char *>(work);
+    int *status = reinterpret_cast<int *>(base);
+    const bool f8 = prec == MIXLU_FP8;
+    const size_t esz = f8 ? 1 : 2;
+    unsigned char *Ap = base + 256;
+    unsigned char *Bp = Ap + align_up(mk * esz, 256);
+    unsigned char *As = Bp + align_up(nk * esz, 256);
+    unsigned char *Bs = As + align_up(mk / 32, 256);
+    HIPCK(launch_fill_u32(reinterpret_cast<unsigned *>(status), 0u, ST_COUNT, s));
+    {
+        ProfScope ps(PC_PACK, 0.0, (4.0 + esz) * (mk + nk), s);
+        if (f8) {
+            HIPCK(launch_pack_fp8(A, lda, m, k, 0, Ap, As, status, s));
+            HIPCK(launch_pack_fp8(B, ldb, n, k, 1, Bp, Bs, status, s));
+        } else {
+            HIPCK(launch_pack(prec, A, lda, m, k, 0, Ap, status, s));
+            HIPCK(launch_pack(prec, B, ldb, k, n, 1, Bp, status, s));
+        }
+    }
+    {
+        ProfScope ps(PC_TRAIL, 2.0 * m * n * k, 8.0 * m * n + 1.0 * esz * (mk + nk), s);
+        if (f8)
+            HIPCK(launch_gemm_fp8(m, n, k, Ap, As, Bp, Bs, C, ldc, s));
+        else
+            HIPCK(launch_gemm_lowp(prec, m, n, k, Ap, Bp, C, ldc, s));
+    }
+    if (overflow) {
+        int h = 0;
+        HIPCK(hipMemcpyAsync(&h, status + ST_OVERFLOW, 4, hipMemcpyDeviceToHost, s));
+        HIPCK(hipStreamSynchronize(s));
+        *overflow = h;
+    }
     return MIXLU_OK;
 }
 

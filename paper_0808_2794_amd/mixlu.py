@@ -82,7 +82,7 @@ EXPORTS = ("mixlu_status_string", "mixlu_default_opts", "mixlu_create", "mixlu_d
            "mixlu_dxgesv_batched", "mixlu_profile_enable", "mixlu_profile_read",
            "mixlu_sgesv", "mixlu_report_read", "mixlu_batched_tune", "mixlu_batched_get_tiles",
            "mixlu_batched_set_tiles", "mixlu_condest", "mixlu_sparse_workspace_size",
-           "mixlu_sparse_fgmres")
+           "mixlu_sparse_fgmres", "mixlu_gemm_update")
 
 _lib = None
 
@@ -124,6 +124,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "mixlu_condest": ([P, P, P], I),
         "mixlu_sparse_workspace_size": ([P, I, I, I, I, I, P], I),
         "mixlu_sparse_fgmres": ([P, I, I, I, P, P, P, P, P, I, I, P, S, P, P], I),
+        "mixlu_gemm_update": ([P, I, I, I, I, P, I, P, I, P, I, P, S, P], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -327,6 +328,26 @@ def mixlu_refine(ctx, F: mixlu_factor, A, B, X, opts=None, trans: int = 0) -> mi
                               _p(X), _ld(X, cm), None if opts is None else ctypes.byref(opts),
                               ctypes.byref(rep)), "mixlu_refine")
     return rep
+
+
+def gemm_update_workspace_bytes(m: int, n: int, k: int) -> int:
+    """Workspace mixlu_gemm_update needs for the rounded operands."""
+    return 2 * (m + n) * k + (m + n) * k // 32 + 1024
+
+
+def mixlu_gemm_update(ctx, prec: int, A, B, C, work=None, overflow: bool = False):
+    """C -= A B (FP32 device tensors, row-major) with the operands rounded as
+    the factorization's trailing update rounds L21 and U12; returns the count
+    of out-of-range operands when ``overflow`` is set (synchronizes)."""
+    m, k = A.shape
+    n = B.shape[1]
+    cnt = ctypes.c_int()
+    nbytes = 0 if work is None else work.numel() * work.element_size()
+    check(load().mixlu_gemm_update(ctx, prec, m, n, k, _p(A), _ld(A), _p(B), _ld(B), _p(C),
+                                   _ld(C), _p(work), nbytes,
+                                   ctypes.byref(cnt) if overflow else None),
+          "mixlu_gemm_update")
+    return cnt.value if overflow else None
 
 
 def mixlu_outer_update(ctx, G, X, GA, alpha: float = -1.0, beta: float = 0.0) -> None:

@@ -207,3 +207,35 @@ def test_adjoint_full_size(solver):
     for i, j in idx:
         expect = -float(GBr[i] @ Xr[j])
         assert abs(float(ga[i, j]) - expect) <= 1e-11 * kappa * np.abs(GBr).max() * np.abs(Xr).max()
+
+
+def test_adjoint_full_size_fp8(solver):
+    """The differentiable-solve workload with FP8-E4M3 trailing-update
+    operands (per-32 power-of-two scales).  At kappa = 1e3, kappa eps_s is
+    far above one for E4M3 (eps_s = 2^-4), so Section 4 predicts that the
+    stationary refinement cannot converge: the forward pass ends in the FP64
+    fallback, and the report says so.  The backward pass then solves with the
+    FP64 factor the fallback left (no second factorization), and both passes
+    match the oracle's FP64 solves."""
+    import torch
+
+    from paper_0808_2794_amd.autograd import solve
+
+    n, nrhs, kappa = 4096, 64, 1e3
+    A, B, Wt = gen.grad_problem(n, nrhs, kappa, seed=501)
+    _say("adjoint n=4096 nrhs=64 fp8")
+    Ad = _dev(A).requires_grad_(True)
+    Bd = _dev(B).requires_grad_(True)
+    reps = {}
+    X = solve(Ad, Bd, "fp8", solver, reps)
+    (X * _dev(Wt)).sum().backward()
+    torch.cuda.synchronize()
+    _say(f"reports {reps}")
+    fwd, bwd = reps["forward"], reps["backward"]
+    assert fwd["converged"] and bwd["converged"], reps
+    assert fwd["prec"] == "fp64" and fwd["iter"] < 0, reps  # the FP8 refinement failed
+    assert bwd["prec"] == "fp64" and bwd["iter"] >= 0, reps  # same FP64 factor, refined
+    Xr, GBr, _ = _reference_grads(A, B, Wt)
+    assert np.abs(X.detach().cpu().numpy() - Xr).max() <= 1e-12 * kappa * np.abs(Xr).max()
+    gb = Bd.grad.cpu().numpy()
+    assert np.abs(gb - GBr).max() <= 1e-12 * kappa * np.abs(GBr).max()

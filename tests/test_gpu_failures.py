@@ -1,0 +1,187 @@
+"""GPU tests of the failure policy on the single-system path (Section 4: 30
+iterations mean failure; fall back to the FP64 solver when refinement cannot
+converge), each failure forced from the host with an ordinary input, and of
+reusing a factor after the fallback replaced it.
+
+Every case ends in the FP64 fallback, whose result must still pass the
+stopping test of Section 3 (residual recomputed on the CPU in extended
+precision) and agree with the oracle's FP64 refinement within 1e-12 kappa.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from synth import gen
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def solver():
+    import torch
+
+    from paper_0808_2794_amd import mixlu
+
+    torch.cuda.init()
+    s = mixlu.Solver()
+    yield s
+    s.close()
+
+
+def _dev(a):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _check(A, b, x, kappa, x_ref):
+    m = O.metrics(A, x, b, x_ref=x_ref)
+    assert m["passes"], f"stopping rule fails: {m['rnorm']} vs {m['anorm']} {m['xnorm']}"
+    assert float(np.max(m["fwd_ref"])) <= 1e-12 * kappa, m["fwd_ref"]
+
+
+def test_fp16_operand_overflow_falls_back(solver):
+    """A row of size 1e6 with equilibration off: its entries enter U12 beyond
+    the FP16 range (65504), the conversion count makes the factor unusable
+    (code -2), and the FP64 fallback solves the system."""
+    n = 700
+    A, b, _ = gen.prescribed_cond_system(n, 1e2, 71)
+    A[5, :] *= 1e6
+    b[5, :] *= 1e6
+    kappa = float(np.linalg.cond(A))
+    _say("overflow fp16 equilibrate=0")
+    r = solver.dxgesv(_dev(A), _dev(b), "fp16", equilibrate=0)
+    assert r.report["iter"] == -2, r.report
+    assert r.report["prec"] == "fp64" and r.report["converged"], r.report
+    _check(A, b, r.x.cpu().numpy(), kappa, O.gesv_ir(A, b).x)
+    # with equilibration the same system stays in the low precision
+    r2 = solver.dxgesv(_dev(A), _dev(b), "fp16")
+    assert r2.report["iter"] >= 0 and r2.report["prec"] == "fp16", r2.report
+    _check(A, b, r2.x.cpu().numpy(), kappa, O.gesv_ir(A, b).x)
+
+
+@pytest.mark.parametrize("itermax,prec,kappa", [(1, "fp32", 1e4), (5, "bf16", 1e2)])
+def test_itermax_reached_falls_back(solver, itermax, prec, kappa):
+    """A refinement cut short by itermax reports -(itermax + 1) and hands
+    over to the FP64 path.  (With itermax = 1 the code -2 coincides with the
+    overflow code; itermax = 5 gives -6, which is unambiguous.)  The stall
+    rule is disabled so that only the iteration limit can end the loop."""
+    n = 600
+    A, b, _ = gen.prescribed_cond_system(n, kappa, 72)
+    _say(f"itermax={itermax} {prec} kappa={kappa:g}")
+    r = solver.dxgesv(_dev(A), _dev(b), prec, itermax=itermax, stall=1e30)
+    assert r.report["iter"] == -(itermax + 1), r.report
+    assert r.report["prec"] == "fp64" and r.report["converged"], r.report
+    _check(A, b, r.x.cpu().numpy(), kappa, O.gesv_ir(A, b).x)
+
+
+def test_nan_right_hand_side(solver):
+    """A NaN in b makes every residual non-finite: the low-precision loop
+    stops at once (-4), the FP64 fallback cannot converge either, and the
+    report says so (converged = 0) instead of certifying a result."""
+    n = 300
+    A, b, _ = gen.prescribed_cond_system(n, 1e2, 73)
+    b[17, 0] = np.nan
+    _say("nan in b")
+    r = solver.dxgesv(_dev(A), _dev(b), "fp32")
+    assert r.report["iter"] == -4, r.report
+    assert r.report["prec"] == "fp64", r.report
+    assert not r.report["converged"], r.report
+    assert not np.isfinite(r.report["berr"]) or r.report["berr"] > 1.0
+
+
+def test_factor_reused_after_fallback(solver):
+    """FP16 factor of a kappa = 1e9 matrix: refinement falls back to FP64.
+    The factor description then points at the FP64 factor, so a later
+    getrs / refine / condest with it is consistent: getrs alone is an FP64
+    solve, a second refine converges without another factorization, and the
+    estimate matches the oracle's estimate from its FP64 factors."""
+    import torch
+
+    from paper_0808_2794_amd import mixlu
+
+    n, kappa = 500, 1e9
+    A, b, _ = gen.prescribed_cond_system(n, kappa, 74)
+    Ad, bd = _dev(A), _dev(b)
+    _say("fallback then reuse of F")
+    o = mixlu.default_opts()
+    work = solver.workspace(mixlu.OP_GESV, mixlu.FP16, n, 1, o)
+    F, info = mixlu.mixlu_getrf(solver.ctx, mixlu.FP16, Ad, work, o)
+    assert info == 0 and F.prec == mixlu.FP16
+    X = torch.empty_like(bd)
+    mixlu.mixlu_getrs(solver.ctx, F, bd, X)
+    rep = mixlu.mixlu_refine(solver.ctx, F, Ad, bd, X, o).as_dict()
+    assert rep["iter"] < 0 and rep["prec"] == "fp64" and rep["converged"], rep
+    assert F.prec == mixlu.FP64 and F.lowp_status == 0 and F.equilibrated == 0
+    ref = O.gesv_ir(A, b)
+    _check(A, b, X.cpu().numpy(), kappa, ref.x)
+    # getrs alone now solves with the FP64 factor: an FP64 direct solve
+    X2 = torch.empty_like(bd)
+    mixlu.mixlu_getrs(solver.ctx, F, bd, X2)
+    torch.cuda.synchronize()
+    err = np.abs(X2.cpu().numpy() - ref.x).max() / np.abs(ref.x).max()
+    assert err <= 1e-12 * kappa, err
+    # a second refinement starts from that x with the FP64 factor
+    rep2 = mixlu.mixlu_refine(solver.ctx, F, Ad, bd, X2, o).as_dict()
+    assert rep2["iter"] >= 0 and rep2["prec"] == "fp64" and rep2["converged"], rep2
+    _check(A, b, X2.cpu().numpy(), kappa, ref.x)
+    # the transposed solve uses the same FP64 factor
+    Xt = torch.empty_like(bd)
+    mixlu.mixlu_getrs(solver.ctx, F, bd, Xt, trans=1)
+    rep3 = mixlu.mixlu_refine(solver.ctx, F, Ad, bd, Xt, o, trans=1).as_dict()
+    assert rep3["converged"] and rep3["iter"] >= 0, rep3
+    _check(A.T.copy(), b, Xt.cpu().numpy(), kappa, O.gesv_ir(A, b, trans=True).x)
+    k1 = mixlu.mixlu_condest(solver.ctx, F)
+    k1_ref = O.condest1(A)
+    assert abs(k1 - k1_ref) <= 1e-6 * k1_ref, (k1, k1_ref)
+
+
+def test_autograd_after_forward_fallback(solver):
+    """A differentiable solve whose forward pass falls back: the backward
+    pass solves with the FP64 factor the fallback left (no second
+    factorization, no refinement from a wrong x_0) and the gradients match
+    the oracle's."""
+    from paper_0808_2794_amd.autograd import solve
+
+    n, nrhs, kappa = 300, 3, 1e9
+    A, B, Wt = gen.grad_problem(n, nrhs, kappa, seed=75)
+    _say("autograd after fallback")
+    Ad = _dev(A).requires_grad_(True)
+    Bd = _dev(B).requires_grad_(True)
+    reps = {}
+    X = solve(Ad, Bd, "fp16", solver, reps)
+    (X * _dev(Wt)).sum().backward()
+    assert reps["forward"]["prec"] == "fp64" and reps["forward"]["iter"] < 0, reps
+    assert reps["backward"]["prec"] == "fp64" and reps["backward"]["iter"] >= 0, reps
+    Xr = O.gesv_ir(A, B).x
+    GBr = O.gesv_ir(A, Wt, trans=True).x
+    assert np.abs(X.detach().cpu().numpy() - Xr).max() <= 1e-12 * kappa * np.abs(Xr).max()
+    assert np.abs(Bd.grad.cpu().numpy() - GBr).max() <= 1e-12 * kappa * np.abs(GBr).max()
+    GAr = -GBr @ Xr.T
+    assert np.abs(Ad.grad.cpu().numpy() - GAr).max() <= 1e-12 * kappa * np.abs(GAr).max()
+
+
+def test_autograd_twice_with_retained_graph(solver):
+    """Two backward passes over one graph (retain_graph) reuse the factor and
+    the context; the second gradient equals the first."""
+    import torch
+
+    from paper_0808_2794_amd.autograd import solve
+
+    n, nrhs, kappa = 200, 2, 1e3
+    A, B, Wt = gen.grad_problem(n, nrhs, kappa, seed=76)
+    _say("autograd retain_graph")
+    Ad = _dev(A).requires_grad_(True)
+    Bd = _dev(B).requires_grad_(True)
+    X = solve(Ad, Bd, "fp32")  # the Function creates (and owns) its solver
+    loss = (X * _dev(Wt)).sum()
+    loss.backward(retain_graph=True)
+    g1 = Bd.grad.clone()
+    Bd.grad = None
+    loss.backward()
+    torch.cuda.synchronize()
+    assert torch.equal(g1, Bd.grad)

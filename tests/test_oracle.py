@@ -69,6 +69,83 @@ def test_getrf_pivots_match_lapack():
     np.testing.assert_allclose(LU, lu_ref, rtol=0, atol=1e-12 * np.abs(lu_ref).max())
 
 
+def _gamma(n, u):
+    return n * u / (1 - n * u)
+
+
+@pytest.mark.parametrize("n,seed", [(1, 0), (2, 1), (17, 2), (64, 3), (150, 4), (150, 5)])
+def test_sgetrf_backward_error_and_lapack_pivots(n, seed):
+    """The FP32 elimination of Algorithm 1 step 1: |PA - LU| <= gamma_n u_s
+    |L||U| elementwise for the FP32 input (Higham, Thm 9.3 with the single
+    precision unit roundoff), |l_ij| <= 1, and the same pivot sequence as
+    LAPACK's sgetrf (scipy on the FP32 matrix) on random inputs."""
+    A = gen.uniform_system(n, 900 + seed)[0].astype(np.float32)
+    LU, ipiv, info = O.sgetrf(A)
+    assert info == 0 and LU.dtype == np.float32
+    L, U = _split_lu(LU.astype(np.float64))
+    P = _perm_matrix(ipiv, n)
+    ld = np.longdouble
+    PA = P.astype(ld) @ A.astype(ld)
+    prod = L.astype(ld) @ U.astype(ld)
+    absprod = np.abs(L).astype(ld) @ np.abs(U).astype(ld)
+    assert np.all(np.abs(PA - prod) <= _gamma(n, U_S) * absprod + 1e-300)
+    assert np.all(np.abs(np.tril(LU, -1)) <= 1.0)
+    lu_ref, piv_ref = scipy.linalg.lu_factor(A)
+    assert lu_ref.dtype == np.float32
+    np.testing.assert_array_equal(ipiv, piv_ref)
+    # the factors agree with LAPACK's to a few FP32 units of |L||U|
+    assert np.all(np.abs(LU.astype(np.float64) - lu_ref) <=
+                  8 * _gamma(n, U_S) * (np.abs(L) @ np.abs(U)) + 1e-30)
+
+
+@pytest.mark.parametrize("n", [1, 9, 80, 150])
+def test_sgetrs_triangular_solve_backward_error(n):
+    """The FP32 solves with the FP32 factors (Algorithm 1 steps 2-3): the
+    computed x satisfies |P b - L U x| <= (2 gamma_n + gamma_n^2) |L||U||x|
+    elementwise (Higham, the proof of Thm 9.4, in single precision), with
+    L, U, x exact FP32 numbers and the check evaluated in long double."""
+    A, b, _ = gen.prescribed_cond_system(n, 1e3, 950 + n, nrhs=2)
+    LU, ipiv, info = O.sgetrf(A.astype(np.float32))
+    assert info == 0
+    b32 = b.astype(np.float32)
+    x = O.sgetrs(LU, ipiv, b32)
+    assert x.dtype == np.float32
+    L, U = _split_lu(LU.astype(np.float64))
+    P = _perm_matrix(ipiv, n)
+    ld = np.longdouble
+    lhs = P.astype(ld) @ b32.astype(ld) - L.astype(ld) @ (U.astype(ld) @ x.astype(ld))
+    g = _gamma(n, U_S)
+    bound = (2 * g + g * g) * (np.abs(L).astype(ld) @ (np.abs(U).astype(ld) @ np.abs(x).astype(ld)))
+    assert np.all(np.abs(lhs) <= bound + 1e-300)
+
+
+@pytest.mark.parametrize("n", [1, 5, 64, 130])
+def test_spotrf_spotrs_backward_error(n):
+    """FP32 Cholesky (the SPOTRF of Section 3.1.1): |A - L L^T| <= gamma_{n+1}
+    u_s |L||L^T| (Higham, Thm 10.3), agreement with LAPACK's spotrf through
+    numpy on the FP32 matrix, and the FP32 solves satisfy |b - L L^T x| <=
+    (2 gamma_n + gamma_n^2) |L||L^T||x|."""
+    A, B, _ = gen.spd_system(n, 1e2, 960 + n, nrhs=2)
+    A32 = A.astype(np.float32)
+    L, info = O.spotrf(A32)
+    assert info == 0 and L.dtype == np.float32
+    Ld = L.astype(np.float64)
+    ld = np.longdouble
+    err = np.abs(A32.astype(ld) - Ld.astype(ld) @ Ld.T.astype(ld))
+    absprod = np.abs(Ld).astype(ld) @ np.abs(Ld.T).astype(ld)
+    assert np.all(err <= _gamma(n + 1, U_S) * absprod + 1e-300)
+    L_ref = np.linalg.cholesky(A32)
+    assert L_ref.dtype == np.float32
+    assert np.all(np.abs(Ld - L_ref) <= 8 * _gamma(n + 1, U_S) * np.sqrt(np.abs(np.diag(A32)))[None, :]
+                  * np.ones((n, 1)) + 1e-30)
+    b32 = B.astype(np.float32)
+    x = O.spotrs(L, b32)
+    g = _gamma(n, U_S)
+    lhs = b32.astype(ld) - Ld.astype(ld) @ (Ld.T.astype(ld) @ x.astype(ld))
+    bound = (2 * g + g * g) * (np.abs(Ld).astype(ld) @ (np.abs(Ld.T).astype(ld) @ np.abs(x).astype(ld)))
+    assert np.all(np.abs(lhs) <= bound + 1e-300)
+
+
 def test_getrf_tiny_pivot_swaps():
     """2x2 with a tiny leading entry must exchange the rows."""
     A = np.array([[1e-20, 1.0], [1.0, 1.0]])
