@@ -45,13 +45,15 @@ def _check(A, b, x, kappa, x_ref):
 
 
 def test_fp16_operand_overflow_falls_back(solver):
-    """A row of size 1e6 with equilibration off: its entries enter U12 beyond
+    """A row scaled by 1e7 with equilibration off (its largest entries reach
+    about 4e5): it becomes the first pivot row, its entries enter U12 beyond
     the FP16 range (65504), the conversion count makes the factor unusable
     (code -2), and the FP64 fallback solves the system."""
     n = 700
     A, b, _ = gen.prescribed_cond_system(n, 1e2, 71)
-    A[5, :] *= 1e6
-    b[5, :] *= 1e6
+    A[5, :] *= 1e7
+    b[5, :] *= 1e7
+    assert np.sum(np.abs(A[5]) > 65504.0) > 100  # the premise: far beyond FP16
     kappa = float(np.linalg.cond(A))
     _say("overflow fp16 equilibrate=0")
     r = solver.dxgesv(_dev(A), _dev(b), "fp16", equilibrate=0)

@@ -5,9 +5,11 @@ against the oracle's emulation of the same operand rounding
 
 Products of the rounded operands are exact in FP32 (at most 11 + 11
 significand bits), so the only error is the FP32 accumulation:
-|C_gpu - C_emul| <= (k + 2) 2^-24 (|C| + |A_q| |B_q|) elementwise.  A wrong
-block scale or a K block paired with the wrong scale moves entries by
-factors like 2^12, far outside that bound.
+|C_gpu - C_emul| <= (k + 2) 2^-24 (|C| + |A_q| |B_q|) elementwise.  The
+scaled FP8 instruction adds its 128 products in one step, after aligning
+products of different block scales, so FP8 is allowed a further
+2^-14 |A_q| |B_q|.  A wrong block scale or a K block paired with the wrong
+scale moves entries by factors like 2^12, far outside either bound.
 """
 import numpy as np
 import pytest
@@ -68,6 +70,13 @@ def test_gemm_update_vs_emulation(solver, prec, m, n, k, spread):
     got = Cd.cpu().numpy().astype(np.float64)
     expect, absprod = lowp.gemm_update(C, A, B, prec)
     tol = (k + 2) * 2.0 ** -24 * (np.abs(C) + absprod)
+    if prec == "fp8":
+        # One scaled FP8 MFMA sums 128 products whose block scales may differ
+        # by 2^24 here; the hardware aligns them before adding, and that
+        # alignment is not specified as exact.  Allow 2^-14 of the products'
+        # magnitude on top of the FP32 accumulation bound: a misplaced scale
+        # or K block still moves entries by 2^-3 of it or more.
+        tol = tol + 2.0 ** -14 * absprod
     bad = np.abs(got - expect) > tol
     assert not bad.any(), (int(bad.sum()), float(np.max(np.abs(got - expect) / np.maximum(tol, 1e-300))))
 
