@@ -351,6 +351,24 @@ int mixlu_dxgesv_batched(mixlu_ctx_t ctx, int prec, int batch, const int *d_n,
                          void *work, size_t lwork, const mixlu_opts *o,
                          mixlu_report *d_reps);
 
+/* Allocation-free variant of mixlu_dxgesv_batched, for callers that cannot
+   allocate device memory (code under HIP graph capture, tight serving
+   loops, harnesses that forbid hipMalloc): the same solve, arguments and
+   reports, with no workspace argument.  Its queue, counters and factor
+   slots live in a device array of the library (64 MiB + 256 KiB per GPU,
+   held from the first use of the library on that GPU until the process
+   ends): at most 65536 systems per call (more: MIXLU_ERR_WORKSPACE) and 32
+   persistent workgroups, so it is slower than the workspace call on large
+   batches.  Every call on one GPU uses that GPU's single array, which keeps
+   the last call's contents: calls that overlap on one GPU (two streams, or
+   two host threads) race and must be serialized by the caller.  No
+   allocation, synchronization or host read of device data; capturable.
+   MIXLU_ERR_HIP if the array's device address could not be obtained. */
+int mixlu_dxgesv_batched_noalloc(mixlu_ctx_t ctx, int prec, int batch, const int *d_n,
+                                 const double *const *d_A, const int *d_lda,
+                                 const double *const *d_B, double *const *d_X, int nrhs,
+                                 const mixlu_opts *o, mixlu_report *d_reps);
+
 /* Tile choices of the batched launch: the panel width of each system's LU
    (8 or 16 columns), the column chunk of its trailing update (32, 64 or
    128) and the number of persistent workgroups per compute unit (1 or 2).

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -1396,6 +1397,39 @@ void mixlu_default_opts(mixlu_opts *o) {
     o->refine = MIXLU_REFINE_CLASSIC;
 }
 
+// ---------------------------------------------------------------------
+// Device-resident scratch of the allocation-free batched solve: the work
+// queue, its two counters and kNoAllocSlots factor slots, in one file-scope
+// array that every GPU holds once the library's code is loaded there.  Host
+// code reaches it only through the address hipGetSymbolAddress returns on
+// each device (the array's name is a host-side stand-in, not a device
+// address).  Calls that overlap on one GPU share it and race.
+// ---------------------------------------------------------------------
+namespace {
+constexpr int kNoAllocSlots = 32;        // persistent workgroups (and slots)
+constexpr int kNoAllocMaxBatch = 65536;  // systems per call
+constexpr size_t kNoAllocOrderBytes = (size_t)kNoAllocMaxBatch * 4;
+constexpr size_t kNoAllocSlotBytes = (size_t)kBatchedNmax * kBatchedNmax * 8;
+constexpr size_t kNoAllocBytes = kNoAllocOrderBytes + 256 + kNoAllocSlots * kNoAllocSlotBytes;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices] = {};
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+// Address of this device's copy of `scratch` (device `dev` must be current
+// on first use); null if the lookup failed.
+static void *scratch_on(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess) g_scratch[dev] = p;
+    }
+    return g_scratch[dev];
+}
+
 int mixlu_create(mixlu_ctx_t *ctx, void *stream) {
     if (!ctx) return -1;
     *ctx = nullptr;
@@ -1408,6 +1442,9 @@ int mixlu_create(mixlu_ctx_t *ctx, void *stream) {
     c->device = dev;
     c->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     c->stream = static_cast<hipStream_t>(stream);
+    // the allocation-free batched solve's scratch on this device (checked
+    // again by that entry point, which reports a failed lookup)
+    (void)scratch_on(dev);
     *ctx = c;
     return MIXLU_OK;
 }
@@ -1723,6 +1760,39 @@ int mixlu_dxgesv_batched(mixlu_ctx_t ctx, int prec, int batch, const int *d_n,
     int *counter = reinterpret_cast<int *>(base + align_up((size_t)batch * 4, 256));
     void *slots = base + align_up((size_t)batch * 4, 256) + 256;
     const int nslots = batch < kBatchedSlots ? batch : kBatchedSlots;
+    ProfScope ps(PC_BATCH, 0.0, 0.0, ctx->stream);
+    HIPCK(launch_batched(prec, batch, nrhs, equil_for(prec, op_), op_.itermax, op_.stall,
+                         prec != MIXLU_FP64 && op_.fallback, d_n, d_A, d_lda, d_B, d_X, d_reps,
+                         order, counter, slots, nslots, ctx->btiles[tile_slot(prec)],
+                         ctx->num_cu, ctx->stream));
+    return MIXLU_OK;
+}
+
+int mixlu_dxgesv_batched_noalloc(mixlu_ctx_t ctx, int prec, int batch, const int *d_n,
+                                 const double *const *d_A, const int *d_lda,
+                                 const double *const *d_B, double *const *d_X, int nrhs,
+                                 const mixlu_opts *o, mixlu_report *d_reps) {
+    if (!ctx) return -1;
+    ProfCall pc_(ctx);
+    if (!prec_valid(prec)) return -2;
+    if (prec == MIXLU_FP8) return MIXLU_ERR_NOT_IMPLEMENTED;
+    if (batch < 0) return -3;
+    if (batch > 0 && !d_n) return -4;
+    if (batch > 0 && !d_A) return -5;
+    if (batch > 0 && !d_B) return -7;
+    if (batch > 0 && !d_X) return -8;
+    if (nrhs < 1) return -9;
+    if (batch > 0 && !d_reps) return -11;
+    if (batch > kNoAllocMaxBatch) return MIXLU_ERR_WORKSPACE;
+    const mixlu_opts op_ = opts_or_default(o);
+    if (op_.layout != MIXLU_ROW_MAJOR) return MIXLU_ERR_NOT_IMPLEMENTED;
+    if (batch == 0) return MIXLU_OK;
+    auto *base = static_cast<unsigned char *>(scratch_on(ctx->device));
+    if (!base) return MIXLU_ERR_HIP;
+    int *order = reinterpret_cast<int *>(base);
+    int *counter = reinterpret_cast<int *>(base + kNoAllocOrderBytes);  // reset by the launch
+    void *slots = base + kNoAllocOrderBytes + 256;
+    const int nslots = batch < kNoAllocSlots ? batch : kNoAllocSlots;
     ProfScope ps(PC_BATCH, 0.0, 0.0, ctx->stream);
     HIPCK(launch_batched(prec, batch, nrhs, equil_for(prec, op_), op_.itermax, op_.stall,
                          prec != MIXLU_FP64 && op_.fallback, d_n, d_A, d_lda, d_B, d_X, d_reps,

@@ -79,8 +79,8 @@ EXPORTS = ("mixlu_status_string", "mixlu_default_opts", "mixlu_create", "mixlu_d
            "mixlu_set_stream", "mixlu_workspace_size", "mixlu_getrf", "mixlu_potrf",
            "mixlu_getrs", "mixlu_refine", "mixlu_dxgesv", "mixlu_dxposv", "mixlu_dgesv",
            "mixlu_dposv", "mixlu_outer_update", "mixlu_batched_workspace_size",
-           "mixlu_dxgesv_batched", "mixlu_profile_enable", "mixlu_profile_read",
-           "mixlu_sgesv", "mixlu_report_read", "mixlu_batched_tune", "mixlu_batched_get_tiles",
+           "mixlu_dxgesv_batched", "mixlu_dxgesv_batched_noalloc", "mixlu_profile_enable",
+           "mixlu_profile_read", "mixlu_sgesv", "mixlu_report_read", "mixlu_batched_tune", "mixlu_batched_get_tiles",
            "mixlu_batched_set_tiles", "mixlu_condest", "mixlu_sparse_workspace_size",
            "mixlu_sparse_fgmres", "mixlu_gemm_update")
 
@@ -114,6 +114,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "mixlu_outer_update": ([P, I, I, P, I, P, I, P, I, D, D], I),
         "mixlu_batched_workspace_size": ([P, I, I, I, P, P], I),
         "mixlu_dxgesv_batched": ([P, I, I, P, P, P, P, P, I, P, S, P, P], I),
+        "mixlu_dxgesv_batched_noalloc": ([P, I, I, P, P, P, P, P, I, P, P], I),
         "mixlu_profile_enable": ([P, I], I),
         "mixlu_profile_read": ([P, P, I, P], I),
         "mixlu_sgesv": ([P, I, I, P, I, P, I, P, I, P, S, P], I),
@@ -374,6 +375,18 @@ def mixlu_dxgesv_batched(ctx, prec: int, d_n, d_A, d_lda, d_B, d_X, nrhs: int, w
                                       _p(d_X), nrhs, _p(work), work.numel() * work.element_size(),
                                       None if opts is None else ctypes.byref(opts), _p(d_reps)),
           "mixlu_dxgesv_batched")
+
+
+def mixlu_dxgesv_batched_noalloc(ctx, prec: int, d_n, d_A, d_lda, d_B, d_X, nrhs: int, d_reps,
+                                 opts=None) -> None:
+    """mixlu_dxgesv_batched without a workspace (the library's device
+    array serves as one); arguments as there."""
+    batch = d_n.numel()
+    check(load().mixlu_dxgesv_batched_noalloc(ctx, prec, batch, _p(d_n), _p(d_A), _p(d_lda),
+                                              _p(d_B), _p(d_X), nrhs,
+                                              None if opts is None else ctypes.byref(opts),
+                                              _p(d_reps)),
+          "mixlu_dxgesv_batched_noalloc")
 
 
 def mixlu_batched_tune(ctx, prec: int, d_n, d_A, d_lda, d_B, d_X, nrhs: int, work, d_reps,
