@@ -84,6 +84,43 @@ __device__ inline unsigned spin_tag(const unsigned long long *p, unsigned tag, i
     return (unsigned)w;
 }
 
+// Compensated accumulation of FP64 products (Ogita, Rump and Oishi's Dot2):
+// the pair (s, c) holds a running sum and the accumulated rounding errors of
+// its products (exact, from one FMA each) and additions (exact, from
+// TwoSum), so s + c is as accurate as a sum formed in twice the working
+// precision.  Residuals use it: their stopping test compares quantities
+// near the unit roundoff, where an ordinary FP64 sum carries rounding of
+// the same size.  Contraction is off so no product fuses into a sum.
+__device__ __forceinline__ void two_sum(double a, double b, double &s, double &e) {
+#pragma clang fp contract(off)
+    s = a + b;
+    const double z = s - a;
+    e = (a - (s - z)) + (b - z);
+}
+__device__ __forceinline__ void dot2_add(double &s, double &c, double a, double x) {
+#pragma clang fp contract(off)
+    const double p = a * x;
+    const double pe = __builtin_fma(a, x, -p);
+    double t, e;
+    two_sum(s, p, t, e);
+    s = t;
+    c += e + pe;
+}
+__device__ __forceinline__ void dot2_merge(double &s, double &c, double s2, double c2) {
+#pragma clang fp contract(off)
+    double t, e;
+    two_sum(s, s2, t, e);
+    s = t;
+    c += e + c2;
+}
+// b - (s + c), rounded once
+__device__ __forceinline__ double dot2_residual(double b, double s, double c) {
+#pragma clang fp contract(off)
+    double t, e;
+    two_sum(b, -s, t, e);
+    return t + (e - c);
+}
+
 // Uniform value of lane `lane` (a compile-time or wave-uniform index).
 template <typename T> __device__ __forceinline__ T readlane_t(T v, int lane) {
     if constexpr (sizeof(T) == 4) {

@@ -435,21 +435,22 @@ __device__ __noinline__ void sys_residual(const double *__restrict__ A, int lda,
     // independent row sums are in flight
     constexpr int RW = 4;
     for (int i0 = wave * RW; i0 < n; i0 += kBW * RW) {
-        double acc[RW];
+        // compensated row sums (s, e): see dot2_add
+        double acc[RW], err[RW];
 #pragma unroll
-        for (int u = 0; u < RW; ++u) acc[u] = 0.0;
+        for (int u = 0; u < RW; ++u) acc[u] = err[u] = 0.0;
         for (int j = lane; j < n; j += 64) {
             const double xj = sh.x[j];
 #pragma unroll
             for (int u = 0; u < RW; ++u)
-                if (i0 + u < n) acc[u] += A[(size_t)(i0 + u) * lda + j] * xj;
+                if (i0 + u < n) dot2_add(acc[u], err[u], A[(size_t)(i0 + u) * lda + j], xj);
         }
 #pragma unroll
         for (int u = 0; u < RW; ++u) {
-            double v = acc[u];
-            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+            double v = acc[u], e = err[u];
+            for (int off = 32; off > 0; off >>= 1) dot2_merge(v, e, __shfl_xor(v, off), __shfl_xor(e, off));
             if (lane == 0 && i0 + u < n) {
-                const double r = b[(size_t)(i0 + u) * ldb] - v;
+                const double r = dot2_residual(b[(size_t)(i0 + u) * ldb], v, e);
                 sh.r[i0 + u] = r;
                 const double ar = fabs(r);
                 rmax = (ar > rmax || ar != ar) ? ar : rmax;

@@ -491,11 +491,12 @@ __global__ __launch_bounds__(256) void k_residual(int n, int nrhs, const double 
     double xm[NR];
 #pragma unroll
     for (int c = 0; c < NR; ++c) xm[c] = 0.0;
-    double acc[RPW][NR];
+    // compensated row sums (s, e): see dot2_add
+    double acc[RPW][NR], err[RPW][NR];
 #pragma unroll
     for (int rr = 0; rr < RPW; ++rr)
 #pragma unroll
-        for (int c = 0; c < NR; ++c) acc[rr][c] = 0.0;
+        for (int c = 0; c < NR; ++c) acc[rr][c] = err[rr][c] = 0.0;
     auto xat = [&](int j, int c) -> double {
         return (c < nrhs) ? (bx_cm ? X[j + (size_t)c * ldx] : X[(size_t)j * ldx + c]) : 0.0;
     };
@@ -518,7 +519,10 @@ __global__ __launch_bounds__(256) void k_residual(int n, int nrhs, const double 
                         if (row < n) {
                             const double2 a = *reinterpret_cast<const double2 *>(A + (size_t)row * lda + j);
 #pragma unroll
-                            for (int c = 0; c < NR; ++c) acc[rr][c] += a.x * x0[c] + a.y * x1[c];
+                            for (int c = 0; c < NR; ++c) {
+                                dot2_add(acc[rr][c], err[rr][c], a.x, x0[c]);
+                                dot2_add(acc[rr][c], err[rr][c], a.y, x1[c]);
+                            }
                         }
                     }
                 }
@@ -538,7 +542,7 @@ __global__ __launch_bounds__(256) void k_residual(int n, int nrhs, const double 
                 if (row < n) {
                     const double a = A[(size_t)row * lda + j];
 #pragma unroll
-                    for (int c = 0; c < NR; ++c) acc[rr][c] += a * xv[c];
+                    for (int c = 0; c < NR; ++c) dot2_add(acc[rr][c], err[rr][c], a, xv[c]);
                 }
             }
         }
@@ -550,9 +554,10 @@ __global__ __launch_bounds__(256) void k_residual(int n, int nrhs, const double 
     for (int rr = 0; rr < RPW; ++rr) {
 #pragma unroll
         for (int c = 0; c < NR; ++c) {
-            double v = acc[rr][c];
-            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+            double v = acc[rr][c], e = err[rr][c];
+            for (int off = 32; off > 0; off >>= 1) dot2_merge(v, e, __shfl_xor(v, off), __shfl_xor(e, off));
             acc[rr][c] = v;
+            err[rr][c] = e;
         }
         const int row = r0 + rr;
         if (lane == 0 && row < n) {
@@ -560,7 +565,7 @@ __global__ __launch_bounds__(256) void k_residual(int n, int nrhs, const double 
             for (int c = 0; c < NR; ++c)
                 if (c < nrhs) {
                     const double b = bx_cm ? B[row + (size_t)c * ldb] : B[(size_t)row * ldb + c];
-                    const double r = b - acc[rr][c];
+                    const double r = dot2_residual(b, acc[rr][c], err[rr][c]);
                     Rv[(size_t)row * ldr + c] = r;
                     const double ar = fabs(r);
                     rmax[c] = (ar > rmax[c] || ar != ar) ? ar : rmax[c];
@@ -631,9 +636,10 @@ __global__ __launch_bounds__(256) void k_residual_t_part(int n, int nrhs, int ro
     const int i0 = h * rows_per_chunk;
     const int i1 = min(n, i0 + rows_per_chunk);
     __shared__ double sx[64][8];
-    double acc[8];
+    // compensated column sums (s, e) for up to 4 right-hand sides: see dot2_add
+    double acc[4], err[4];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+    for (int c = 0; c < 4; ++c) acc[c] = err[c] = 0.0;
     // thread t always stages right-hand side c = t & 7 (256 is a multiple of 8)
     double xm = 0.0;
     for (int ib = i0; ib < i1; ib += 64) {
@@ -652,14 +658,17 @@ __global__ __launch_bounds__(256) void k_residual_t_part(int n, int nrhs, int ro
             for (int ii = 0; ii < cnt; ++ii) {
                 const double a = A[(size_t)(ib + ii) * lda + j];
 #pragma unroll
-                for (int c = 0; c < 8; ++c) acc[c] += a * sx[ii][c];
+                for (int c = 0; c < 4; ++c) dot2_add(acc[c], err[c], a, sx[ii][c]);
             }
         }
     }
     if (j < n) {
 #pragma unroll
-        for (int c = 0; c < 8; ++c)
-            if (c < nrhs) part[((size_t)h * n + j) * 8 + c] = acc[c];
+        for (int c = 0; c < 4; ++c)
+            if (c < nrhs) {
+                part[((size_t)h * n + j) * 8 + 2 * c] = acc[c];
+                part[((size_t)h * n + j) * 8 + 2 * c + 1] = err[c];
+            }
     }
     if (blockIdx.x == 0 && (threadIdx.x & 7) < nrhs) atomic_max_nonneg(&xnorm[threadIdx.x & 7], xm);
 }
@@ -673,10 +682,12 @@ __global__ __launch_bounds__(256) void k_residual_t_fin(int n, int nrhs, int chu
     for (int c = 0; c < nrhs; ++c) {
         double ar = 0.0;
         if (j < n) {
-            double s = 0.0;
-            for (int h = 0; h < chunks; ++h) s += part[((size_t)h * n + j) * 8 + c];
+            double s = 0.0, e = 0.0;
+            for (int h = 0; h < chunks; ++h)
+                dot2_merge(s, e, part[((size_t)h * n + j) * 8 + 2 * c],
+                           part[((size_t)h * n + j) * 8 + 2 * c + 1]);
             const double b = b_cm ? B[j + (size_t)c * ldb] : B[(size_t)j * ldb + c];
-            const double r = b - s;
+            const double r = dot2_residual(b, s, e);
             Rv[(size_t)j * ldr + c] = r;
             ar = fabs(r);
         }
@@ -695,8 +706,8 @@ hipError_t launch_residual_t(int n, int nrhs, const double *A, int lda, const do
     const int chunks = n < kResTChunks * 64 ? (n + 63) / 64 : kResTChunks;
     const int rpc = (n + chunks - 1) / chunks;
     const dim3 grid((n + 255) / 256, chunks);
-    for (int c0 = 0; c0 < nrhs; c0 += 8) {
-        const int nr = nrhs - c0 < 8 ? nrhs - c0 : 8;
+    for (int c0 = 0; c0 < nrhs; c0 += 4) {
+        const int nr = nrhs - c0 < 4 ? nrhs - c0 : 4;
         const double *Xc = bx_col_major ? X + (size_t)c0 * ldx : X + c0;
         const double *Bc = bx_col_major ? B + (size_t)c0 * ldb : B + c0;
         k_residual_t_part<<<grid, dim3(256), 0, s>>>(n, nr, rpc, A, lda, Xc, ldx, bx_col_major,
