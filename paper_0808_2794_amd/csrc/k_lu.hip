@@ -3,8 +3,9 @@
 //
 //   k_panel       GEPP on a tall panel of B columns; the panel rows are held
 //                 in registers across up to 32 workgroups placed on one XCD;
-//                 per column: wavefront argmax (first index on ties), one
-//                 tagged cross-workgroup exchange, swap, scale, rank-1 update.
+//                 per column: argmax (first index on ties), the candidate
+//                 rows published as tagged words and gathered by one wave,
+//                 swap, scale; the rank-1 update overlaps the exchange.
 //   k_row_swaps   applies a block of pivots to the columns outside the panel
 //   k_swaps_compose, k_rows_apply: the same for wide blocks, in two launches
 //   k_trsm_diag   X = L^{-1} X with a unit lower diagonal block in LDS
@@ -23,122 +24,112 @@ namespace mixlu {
 // ======================================================================
 // Panel factorization
 // ======================================================================
-template <typename T, int B> struct PanelGeom {
-    static constexpr int PWV = Words<T>::n;
-    static_assert(2 * (kPanelMaxWG * (4 + B * Words<T>::n) + B * Words<T>::n) <= kXbufWords,
-                  "exchange buffer");
-    static constexpr int HDR = 4;               // key words (+ padding to 16 bytes)
-    static constexpr int SLOT = HDR + B * PWV;  // one workgroup's candidate row
-    static constexpr int PAR = kPanelMaxWG * SLOT + B * PWV;  // words per parity
+// One thread holds one panel row (B values) in registers, as NG = B / 16
+// blocks of 16.  Per column j (all rows' column j up to date):
+//   1. wave argmax of |a_j| (first row on ties), then the workgroup's after
+//      one barrier; the winner's signed value travels with it;
+//   2. the winning wave stages its winner's row in LDS and brings it up to
+//      date one element per lane (the pending rank-1 update of column j-1,
+//      see 3), then publishes it with a header (signed pivot, row) as tagged
+//      words; wave 1 of workgroup 0 does the same for row j (staged by its
+//      owner before the barrier);
+//   3. every row applies the pending rank-1 update of columns > j with the
+//      previous pivot row, broadcast across lanes by DPP inside the
+//      multiply-add, while the exchange is in flight;
+//   4. the last wave gathers: it polls the P headers and row j, picks the
+//      winner (largest |pivot|, then the smallest row: workgroups hold
+//      increasing rows), computes 1 / pivot while that workgroup's row is
+//      fetched, and leaves pivot, row j and the decision in LDS;
+//   5. after a second barrier: the interchange, the multipliers of column j
+//      and the update of column j + 1 only; the rest of that rank-1 update
+//      is the next column's pending update.
+// A single workgroup exchanges through LDS only.  The column loop runs over
+// groups of 16 columns; at the end of a group the register blocks rotate by
+// one, so the current block is always block 0 and the code of one group
+// serves all of them.
+
+// a += (lane K of every 16-lane row of nu) * l for K = 0..15, the broadcast
+// folded into the multiply-add (DPP row_newbcast); the leading s_nop covers
+// the hazard of a VALU write of nu just before a DPP read of it
+template <typename T> struct BcastFma;
+template <> struct BcastFma<float> {
+    template <int K> __device__ static __forceinline__ void one(float &a, float nu, float l) {
+        asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+            : "+v"(a)
+            : "v"(nu), "v"(l), "i"(K));
+    }
+    __device__ static __forceinline__ void block(float (&a)[16], float nu, float l) {
+#define MIXLU_FB(K) "v_fmac_f32_dpp %" #K ", %16, %17 row_newbcast:" #K " row_mask:0xf bank_mask:0xf\n\t"
+        asm("s_nop 1\n\t" MIXLU_FB(0) MIXLU_FB(1) MIXLU_FB(2) MIXLU_FB(3) MIXLU_FB(4) MIXLU_FB(5)
+                MIXLU_FB(6) MIXLU_FB(7) MIXLU_FB(8) MIXLU_FB(9) MIXLU_FB(10) MIXLU_FB(11)
+                    MIXLU_FB(12) MIXLU_FB(13) MIXLU_FB(14) MIXLU_FB(15)
+            : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3]), "+v"(a[4]), "+v"(a[5]), "+v"(a[6]),
+              "+v"(a[7]), "+v"(a[8]), "+v"(a[9]), "+v"(a[10]), "+v"(a[11]), "+v"(a[12]),
+              "+v"(a[13]), "+v"(a[14]), "+v"(a[15])
+            : "v"(nu), "v"(l));
+#undef MIXLU_FB
+    }
+};
+template <> struct BcastFma<double> {
+    template <int K> __device__ static __forceinline__ void one(double &a, double nu, double l) {
+        asm("s_nop 1\n\tv_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+            : "+v"(a)
+            : "v"(nu), "v"(l), "i"(K));
+    }
+    __device__ static __forceinline__ void block(double (&a)[16], double nu, double l) {
+#define MIXLU_FB(K) "v_fmac_f64_dpp %" #K ", %16, %17 row_newbcast:" #K " row_mask:0xf bank_mask:0xf\n\t"
+        asm("s_nop 1\n\t" MIXLU_FB(0) MIXLU_FB(1) MIXLU_FB(2) MIXLU_FB(3) MIXLU_FB(4) MIXLU_FB(5)
+                MIXLU_FB(6) MIXLU_FB(7) MIXLU_FB(8) MIXLU_FB(9) MIXLU_FB(10) MIXLU_FB(11)
+                    MIXLU_FB(12) MIXLU_FB(13) MIXLU_FB(14) MIXLU_FB(15)
+            : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3]), "+v"(a[4]), "+v"(a[5]), "+v"(a[6]),
+              "+v"(a[7]), "+v"(a[8]), "+v"(a[9]), "+v"(a[10]), "+v"(a[11]), "+v"(a[12]),
+              "+v"(a[13]), "+v"(a[14]), "+v"(a[15])
+            : "v"(nu), "v"(l));
+#undef MIXLU_FB
+    }
 };
 
-template <typename T, int NQ>
-__device__ __forceinline__ void row_to_lds(T *dst, const typename Vq<T>::type (&a)[NQ]) {
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) reinterpret_cast<typename Vq<T>::type *>(dst)[q] = a[q];
-}
-template <typename T, int NQ, int Q0 = 0>
-__device__ __forceinline__ void row_from_lds(typename Vq<T>::type (&a)[NQ], const T *src) {
-#pragma unroll
-    for (int q = Q0; q < NQ; ++q) a[q] = reinterpret_cast<const typename Vq<T>::type *>(src)[q];
+// LDS ordering between lanes of one wave
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Pointer into LDS that keeps its address space through a call, so that
-// accesses compile to ds_* instructions (not flat ones, which wait on both
-// the memory and the LDS counters).
-typedef __attribute__((address_space(3))) unsigned lds_u32;
-
-struct ExchangeResult {
-    int ok;  // 0: a bounded wait gave up
-    int p;   // winning row (panel position), -1 if none
-    int qs;  // slot (workgroup) holding it
-};
-
-// Cross-workgroup step of one column (P > 1): publish this workgroup's best
-// (header: |value| words and row; thread tid < B*PWV publishes row word
-// `rw`), plus row j's word `dw` from workgroup 0; gather every slot into
-// `words` (all loads issued first, late words polled); pick the winner with
-// one wave argmax over the slot headers.  Kept out of line: one copy serves
-// all columns.
-template <typename T, int B>
-__device__ __noinline__ ExchangeResult panel_exchange(unsigned long long *X, lds_u32 *words, int P,
-                                                      int w, unsigned tag, unsigned h0,
-                                                      unsigned h1, unsigned h2, unsigned rw,
-                                                      unsigned dw, int *timeout, int near) {
-    using G = PanelGeom<T, B>;
-    constexpr int TPB = kPanelTPB, PWV = G::PWV, HDR = G::HDR, SLOT = G::SLOT;
-    constexpr int DIAG = kPanelMaxWG * SLOT;
-    const int tid = threadIdx.x;
-    unsigned long long *slot = X + (size_t)w * SLOT;
-    const unsigned hword = tid == 0 ? h0 : (tid == 1 ? h1 : (tid == 2 ? h2 : 0u));
-    if (near) {
-        if (tid < HDR) xstore_near(slot + tid, tag, hword);
-        if (tid < B * PWV) {
-            xstore_near(slot + HDR + tid, tag, rw);
-            if (w == 0) xstore_near(X + DIAG + tid, tag, dw);
-        }
-    } else {
-        if (tid < HDR) xstore(slot + tid, tag, hword);
-        if (tid < B * PWV) {
-            xstore(slot + HDR + tid, tag, rw);
-            if (w == 0) xstore(X + DIAG + tid, tag, dw);
-        }
-    }
-    bool bad = false;
-    const int nslot = P * SLOT;
-    const int total = nslot + B * PWV;
-    constexpr int MAXW = (kPanelMaxWG * SLOT + B * PWV + TPB - 1) / TPB;
-    unsigned long long wv[MAXW];
+// Register row (NG blocks of 16, block b holding columns 16 ((g + b) % NG)
+// ..) to and from a B-value row in LDS.
+template <typename T, int NG>
+__device__ __forceinline__ void blocks_to_lds(T *dst, const T (&a)[NG][16], int g) {
+    using vq = typename Vq<T>::type;
+    constexpr int V = Vq<T>::V;
 #pragma unroll
-    for (int q = 0; q < MAXW; ++q) {
-        const int t = tid + q * TPB;
-        const int src = t < nslot ? t : DIAG + (t - nslot);
-        wv[q] = (t < total) ? xload(X + src) : 0ull;
-    }
+    for (int b = 0; b < NG; ++b) {
+        vq *d = reinterpret_cast<vq *>(dst + 16 * ((g + b) % NG));
 #pragma unroll
-    for (int q = 0; q < MAXW; ++q) {
-        const int t = tid + q * TPB;
-        if (t < total) {
-            const int src = t < nslot ? t : DIAG + (t - nslot);
-            unsigned v = (unsigned)wv[q];
-            if ((unsigned)(wv[q] >> 32) != tag && !bad) v = spin_tag(X + src, tag, timeout, bad);
-            words[src] = v;
+        for (int q = 0; q < 16 / V; ++q) {
+            vq v;
+#pragma unroll
+            for (int e = 0; e < V; ++e) v[e] = a[b][q * V + e];
+            d[q] = v;
         }
     }
-    ExchangeResult r{1, -1, 0};
-    if (__syncthreads_or(bad ? 1 : 0)) {
-        r.ok = 0;
-        return r;
+}
+template <typename T, int NG>
+__device__ __forceinline__ void blocks_from_lds(T (&a)[NG][16], const T *src, int g) {
+    using vq = typename Vq<T>::type;
+    constexpr int V = Vq<T>::V;
+#pragma unroll
+    for (int b = 0; b < NG; ++b) {
+        const vq *s = reinterpret_cast<const vq *>(src + 16 * ((g + b) % NG));
+#pragma unroll
+        for (int q = 0; q < 16 / V; ++q) {
+            const vq v = s[q];
+#pragma unroll
+            for (int e = 0; e < V; ++e) a[b][q * V + e] = v[e];
+        }
     }
-    // lane q of every wave takes slot header q; slots hold increasing rows,
-    // so the first lane with the maximum is also the smallest row
-    const int lane = tid & 63;
-    T hv = (T)-1;
-    int hp = 0;
-    if (lane < P) {
-        const unsigned w0 = words[lane * SLOT], w1 = words[lane * SLOT + 1];
-        if constexpr (sizeof(T) == 4) hv = __uint_as_float(w0);
-        else hv = __longlong_as_double((long long)(((unsigned long long)w1 << 32) | w0));
-        hp = (int)words[lane * SLOT + 2];
-    }
-    const WaveArgmax<T> best = wave_argmax(hv);
-    if (best.lane < P) {
-        r.p = __builtin_amdgcn_readlane(hp, best.lane);
-        r.qs = best.lane;
-    }
-    return r;
 }
 
-// One thread owns one panel row (position pos = w * TPB + tid, relative to
-// row k0), kept in registers; the B columns are unrolled so every register
-// access has a constant index.  Per column: each wave takes its argmax on
-// DPP (value) and a ballot (first row among equals) and its winning lane
-// stages its row in LDS; after one barrier every thread picks the
-// workgroup's winner the same way over the wave results.  When the panel
-// spans several workgroups they exchange (|value|, row index, row) and row j
-// through tagged words in global memory: one round trip and one more
-// barrier.  Multipliers use the reciprocal of the pivot when it is a normal
-// number (as LAPACK's getf2 does) and a division otherwise.
 template <typename T, int B>
 __global__ __launch_bounds__(kPanelTPB) void k_panel(T *__restrict__ W, int ldw, int k0, int m,
                                                      int *__restrict__ ipiv,
@@ -147,114 +138,294 @@ __global__ __launch_bounds__(kPanelTPB) void k_panel(T *__restrict__ W, int ldw,
     if (blockIdx.x % stride) return;
     const int w = blockIdx.x / stride;
     if (w >= P) return;
-    using G = PanelGeom<T, B>;
     constexpr int TPB = kPanelTPB, NW = TPB / 64;
-    constexpr int HDR = G::HDR, SLOT = G::SLOT, PAR = G::PAR, PWV = G::PWV;
-    constexpr int DIAG = kPanelMaxWG * SLOT;  // offset of row j's words in a parity
-    static_assert(kPanelRows == 1, "one row per thread");
-    static_assert(NW <= 8, "workgroup winner is picked over at most 8 waves");
+    static_assert(NW >= 2 && NW <= 8, "two to eight waves");
+    constexpr int GW = NW - 1;  // gathering wave
+    constexpr int DW = 1;       // wave that publishes row j (workgroup 0)
+    constexpr int NG = B / 16;
+    constexpr int PWV = Words<T>::n;
+    constexpr int RW = B * PWV;  // words of a row: one per lane
+    static_assert(RW == 64 && B % 16 == 0, "one word of a row per lane");
+    constexpr int HDR = 4, SLOT = HDR + RW;
+    constexpr int DIAG = kPanelMaxWG * SLOT;
+    constexpr int PAR = DIAG + RW;  // words per parity
+    static_assert(2 * PAR <= kXbufWords, "exchange buffer");
+    constexpr int HW = PWV + 1;     // header words: signed pivot, then row (~0u: no candidate)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int pos = w * TPB + tid;
     const bool live = pos < m;
 
-    __shared__ __attribute__((aligned(16))) T s_wrow[2][NW][B];  // each wave's best row
-    __shared__ __attribute__((aligned(16))) T s_drow[2][B];      // row j (held by workgroup 0)
-    __shared__ __attribute__((aligned(16))) unsigned s_words[2][kPanelMaxWG * SLOT + PWV * B];
-    __shared__ T s_wval[2][NW];
+    __shared__ __attribute__((aligned(16))) T s_u[2][B];     // pivot row of the column
+    __shared__ __attribute__((aligned(16))) T s_d[2][B];     // row j, moving to the pivot's place
+    __shared__ __attribute__((aligned(16))) T s_cand[2][B];  // the candidate row, staged raw
+    __shared__ __attribute__((aligned(16))) T s_draw[2][B];  // row j, staged raw
+    __shared__ T s_dlp[2];
+    __shared__ T s_wval[2][NW], s_wsv[2][NW];
     __shared__ int s_wpos[2][NW];
-    __shared__ int s_piv[B];  // pivot rows, written to global memory after the loop
+    __shared__ int s_p[2];
+    __shared__ T s_pv[2], s_rcp[2];
+    __shared__ int s_piv[B];
 
-    constexpr int V = Vq<T>::V, NQ = B / V;
-    using vq = typename Vq<T>::type;
-    vq a[NQ];
-    if (live) {
-        const vq *src = reinterpret_cast<const vq *>(W + (size_t)(k0 + pos) * ldw + k0);
+    T a[NG][16];
+    {
+        using vq = typename Vq<T>::type;
+        constexpr int V = Vq<T>::V;
+        const vq *src = reinterpret_cast<const vq *>(W + (size_t)(k0 + (live ? pos : 0)) * ldw + k0);
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) a[q] = src[q];
-    } else {
+        for (int b = 0; b < NG; ++b)
 #pragma unroll
-        for (int q = 0; q < NQ; ++q)
+            for (int q = 0; q < 16 / V; ++q) {
+                const vq v = live ? src[b * (16 / V) + q] : vq{};
 #pragma unroll
-            for (int e = 0; e < V; ++e) a[q][e] = (T)0;
+                for (int e = 0; e < V; ++e) a[b][q * V + e] = v[e];
+            }
     }
+    T lp = (T)0;      // pending multiplier of the previous pivot row
+    T nu[NG];         // that row negated, lane-replicated: nu[b] = -u[16 (g + b) + lane % 16]
+#pragma unroll
+    for (int b = 0; b < NG; ++b) nu[b] = (T)0;
     bool dead = false;
     const T tiny = sizeof(T) == 4 ? (T)1.17549435e-38f : (T)2.2250738585072014e-308;
+    const bool near = stride == kXcdStride;
+    auto put = [&](unsigned long long *p, unsigned tag, unsigned v) {
+        if (near) xstore_near(p, tag, v);
+        else xstore(p, tag, v);
+    };
 
-    sfor<0, B>([&](auto jc) {
-        constexpr int j = decltype(jc)::value;
-        constexpr int par = j & 1;
-        if (dead) return;
-        // --- wave argmax
-        const T av = fabs(a[j / V][j % V]);
-        const T cv = (live && pos >= j && av == av) ? av : (T)-1;
-        const WaveArgmax<T> wa = wave_argmax(cv);
-        if (lane == wa.lane) row_to_lds<T, NQ>(s_wrow[par][wave], a);
-        if (pos == j) row_to_lds<T, NQ>(s_drow[par], a);
-        if (lane == 0) {
-            s_wval[par][wave] = wa.val;
-            s_wpos[par][wave] = w * TPB + wave * 64 + wa.lane;
-        }
-        __syncthreads();
-        // --- workgroup winner (every wave, same answer): waves hold increasing rows
-        T kv = (T)-1;
-        int kp = 0;
-        if (lane < NW) {
-            kv = s_wval[par][lane];
-            kp = s_wpos[par][lane];
-        }
-        const T gmax = max8(kv);
-        const int qw = first_lane(lane < NW && gmax >= (T)0 && kv == gmax);
-        int p = qw < NW ? __builtin_amdgcn_readlane(kp, qw) : -1;
-        const T *prow = s_wrow[par][qw < NW ? qw : 0];
-        const T *drow = s_drow[par];
-        if (P > 1) {
-            const unsigned rw = tid < B * PWV ? Words<T>::get(prow[tid / PWV], tid % PWV) : 0u;
-            const unsigned dw = tid < B * PWV ? Words<T>::get(drow[tid / PWV], tid % PWV) : 0u;
-            const ExchangeResult ex = panel_exchange<T, B>(
-                xb + (size_t)par * PAR, (lds_u32 *)&s_words[par][0], P, w,
-                (unsigned)(k0 + j + 1), Words<T>::get(gmax, 0),
-                PWV > 1 ? Words<T>::get(gmax, PWV - 1) : 0u, (unsigned)p, rw, dw,
-                &status[ST_TIMEOUT], stride == kXcdStride);
-            if (!ex.ok) {
+    for (int g = 0; g < NG; ++g) {
+        sfor<0, 16>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            constexpr int par = k & 1;
+            const int j = 16 * g + k;
+            if (dead) return;
+            const unsigned tag = (unsigned)(k0 + j + 1);
+            const unsigned long long tagw = (unsigned long long)tag << 32;
+            unsigned long long *X = xb + (size_t)par * PAR;
+            // row j staged raw for its publisher (drains during the argmax)
+            if (pos == j) {
+                blocks_to_lds<T, NG>(s_draw[par], a, g);
+                s_dlp[par] = lp;
+            }
+            // --- 1. argmax of column j
+            const T aj = a[0][k];
+            const T av = fabs(aj);
+            const T cv = (live && pos >= j && av == av) ? av : (T)-1;
+            const WaveArgmax<T> wa = wave_argmax(cv);
+            const int wl = wa.lane < 64 ? wa.lane : 0;
+            if (lane == 0) {
+                s_wval[par][wave] = wa.val;
+                s_wsv[par][wave] = readlane_t(aj, wl);
+                s_wpos[par][wave] = w * TPB + wave * 64 + wl;
+            }
+            __syncthreads();
+            T kv = (T)-1, ks = (T)0;
+            int kp = 0;
+            if (lane < NW) {
+                kv = s_wval[par][lane];
+                ks = s_wsv[par][lane];
+                kp = s_wpos[par][lane];
+            }
+            const T gmax = max8(kv);
+            const int qw = first_lane(lane < NW && gmax >= (T)0 && kv == gmax);
+            const int pwg = qw < NW ? __builtin_amdgcn_readlane(kp, qw) : -1;
+            const T psv = readlane_t(ks, qw < NW ? qw : 0);
+            // --- 2. publish the candidate and row j, brought up to date
+            if (qw < NW && wave == qw) {
+                if (lane == wl) blocks_to_lds<T, NG>(s_cand[par], a, g);
+                const T lw = readlane_t(lp, wl);
+                wave_lds_sync();
+                T v = (T)0;
+                if (lane < B) {
+                    v = s_cand[par][lane];
+                    if (j > 0 && lane > j) v = fma(-s_u[par ^ 1][lane], lw, v);
+                }
+                if (P > 1) {
+                    unsigned long long *slot = X + (size_t)w * SLOT;
+                    if (lane < B) {
+#pragma unroll
+                        for (int h = 0; h < PWV; ++h)
+                            put(slot + HDR + lane * PWV + h, tag, Words<T>::get(v, h));
+                    }
+                    if (lane < HW)
+                        put(slot + lane, tag, lane < PWV ? Words<T>::get(psv, lane) : (unsigned)pwg);
+                } else {
+                    if (lane < B) s_u[par][lane] = v;
+                    if (lane == 0) {
+                        s_p[par] = pwg;
+                        s_pv[par] = psv;
+                        s_rcp[par] = (T)1 / psv;
+                    }
+                }
+            }
+            if (qw >= NW && wave == 0) {  // no candidate in this workgroup
+                if (P > 1) {
+                    if (lane < HW) put(X + (size_t)w * SLOT + lane, tag, lane < PWV ? 0u : ~0u);
+                } else if (lane == 0) {
+                    s_p[par] = -1;
+                }
+            }
+            if (w == 0 && wave == DW && lane < B) {
+                T v = s_draw[par][lane];
+                if (j > 0 && lane > j) v = fma(-s_u[par ^ 1][lane], s_dlp[par], v);
+                if (P > 1) {
+#pragma unroll
+                    for (int h = 0; h < PWV; ++h) put(X + DIAG + lane * PWV + h, tag, Words<T>::get(v, h));
+                } else {
+                    s_d[par][lane] = v;
+                }
+            }
+            // --- 3. pending update of columns > j, every row, all lanes active
+            if (j > 0) {
+                sfor<k + 1, 16>([&](auto cc) {
+                    constexpr int c = decltype(cc)::value;
+                    BcastFma<T>::template one<c>(a[0][c], nu[0], lp);
+                });
+#pragma unroll
+                for (int b = 1; b < NG; ++b)
+                    if (b < NG - g) BcastFma<T>::block(a[b], nu[b], lp);
+            }
+            lp = (T)0;
+            // --- 4. gather (last wave): headers and row j, then the winner's row
+            if (P > 1 && wave == GW) {
+                bool bad = false;
+                unsigned long long hv[HW];
+#pragma unroll
+                for (int h = 0; h < HW; ++h) hv[h] = lane < P ? xload(X + lane * SLOT + h) : tagw;
+                unsigned long long dv = xload(X + DIAG + lane);
+                unsigned spins = 0;
+                for (;;) {
+                    bool stale = (unsigned)(dv >> 32) != tag;
+#pragma unroll
+                    for (int h = 0; h < HW; ++h) stale |= (unsigned)(hv[h] >> 32) != tag;
+                    if (!__ballot(stale)) break;
+                    ++spins;
+                    if (spins > kSpinLimit ||
+                        ((spins & 1023u) == 0 && flag_set(&status[ST_TIMEOUT]))) {
+                        bad = true;
+                        break;
+                    }
+#pragma unroll
+                    for (int h = 0; h < HW; ++h)
+                        if ((unsigned)(hv[h] >> 32) != tag) hv[h] = xload(X + lane * SLOT + h);
+                    if ((unsigned)(dv >> 32) != tag) dv = xload(X + DIAG + lane);
+                }
+                T sval = (T)0;
+                int row = -1;
+                if (lane < P) {
+                    if constexpr (sizeof(T) == 4) {
+                        sval = __uint_as_float((unsigned)hv[0]);
+                    } else {
+                        sval = __longlong_as_double(
+                            (long long)(((hv[1] & 0xffffffffull) << 32) | (hv[0] & 0xffffffffull)));
+                    }
+                    row = (int)(unsigned)hv[PWV];
+                }
+                const T val = (!bad && lane < P && row >= 0) ? fabs(sval) : (T)-1;
+                const WaveArgmax<T> best = wave_argmax(val);
+                int p = -1;
+                T pv = (T)0;
+                unsigned long long uv = tagw;
+                if (best.lane < P) {
+                    p = __builtin_amdgcn_readlane(row, best.lane);
+                    pv = readlane_t(sval, best.lane);
+                    uv = xload(X + best.lane * SLOT + HDR + lane);
+                }
+                const T rcp = (T)1 / pv;  // while the row is in flight
+                if (best.lane < P) {
+                    spins = 0;
+                    while (!bad && __ballot((unsigned)(uv >> 32) != tag)) {
+                        ++spins;
+                        if (spins > kSpinLimit ||
+                            ((spins & 1023u) == 0 && flag_set(&status[ST_TIMEOUT]))) {
+                            bad = true;
+                            break;
+                        }
+                        if ((unsigned)(uv >> 32) != tag) uv = xload(X + best.lane * SLOT + HDR + lane);
+                    }
+                }
+                reinterpret_cast<unsigned *>(&s_u[par][0])[lane] = (unsigned)uv;
+                reinterpret_cast<unsigned *>(&s_d[par][0])[lane] = (unsigned)dv;
+                if (lane == 0) {
+                    s_p[par] = bad ? INT_MIN : p;
+                    s_pv[par] = pv;
+                    s_rcp[par] = rcp;
+                    if (bad)
+                        __hip_atomic_store(&status[ST_TIMEOUT], 1, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+            __syncthreads();
+            // --- 5. interchange, multipliers, column j + 1
+            int p = s_p[par];
+            if (p == INT_MIN) {  // a bounded wait gave up (uniform)
                 dead = true;
                 return;
             }
-            p = ex.p;
-            prow = reinterpret_cast<const T *>(&s_words[par][ex.qs * SLOT + HDR]);
-            drow = reinterpret_cast<const T *>(&s_words[par][DIAG]);
-        }
-        if (p < j || p >= m) {  // no usable candidate (all NaN): keep row j
-            p = j;
-            prow = drow;
-        }
-        const T piv = prow[j];
-        const bool normal = fabs(piv) >= tiny && isfinite(piv);
-        const T rcp = (T)1 / piv;
-        // no global stores inside the loop: a barrier waits for every
-        // outstanding store of the wave, which would put a memory round trip
-        // on each column
-        if (tid == 0) s_piv[j] = (!(piv != (T)0) || !isfinite(piv)) ? -(p + 1) : p;
-        // --- swap rows j and p (whole panel rows)
-        if (p != j) {
-            if (pos == j) row_from_lds<T, NQ>(a, prow);
-            else if (pos == p) row_from_lds<T, NQ>(a, drow);
-        }
-        // --- multiplier and rank-1 update of the remaining panel columns
-        if (live && pos > j && piv != (T)0) {
-            vq u[NQ];
-            row_from_lds<T, NQ, (j + 1) / V>(u, prow);
-            const T ajv = a[j / V][j % V];
-            const T l = normal ? ajv * rcp : ajv / piv;
-            a[j / V][j % V] = l;
+            T piv = s_pv[par], rcp = s_rcp[par];
+            const T *prow = s_u[par];
+            const T *drow = s_d[par];
+            if (p < j || p >= m) {  // no usable candidate (all NaN): keep row j
+                p = j;
+                prow = drow;
+                piv = drow[j];
+                rcp = (T)1 / piv;
+            }
+            const bool normal = fabs(piv) >= tiny && isfinite(piv);
+            // no global stores inside the loop: the pivots are kept in LDS
+            if (tid == 0) s_piv[j] = (!(piv != (T)0) || !isfinite(piv)) ? -(p + 1) : p;
+            if (p != j) {
+                if (pos == j) blocks_from_lds<T, NG>(a, prow, g);
+                else if (pos == p) blocks_from_lds<T, NG>(a, drow, g);
+            }
+            if (j + 1 < B) {
 #pragma unroll
-            for (int c = j + 1; c < B; ++c) a[c / V][c % V] -= l * u[c / V][c % V];
-        }
-    });
-    if (dead) return;  // uniform: every thread saw the same exchange result
+                for (int b = 0; b < NG; ++b)
+                    if (b < NG - g) nu[b] = -prow[16 * (g + b) + (lane & 15)];
+                const T u1 = prow[j + 1];
+                if (live && pos > j && piv != (T)0) {
+                    T l;
+                    if (normal) l = a[0][k] * rcp;
+                    else l = a[0][k] / piv;
+                    a[0][k] = l;
+                    lp = l;
+                    if constexpr (k + 1 < 16) a[0][k + 1] = fma(-u1, l, a[0][k + 1]);
+                    else if constexpr (NG > 1) a[1][0] = fma(-u1, l, a[1][0]);
+                }
+            } else if (live && pos > j && piv != (T)0) {
+                if (normal) a[0][k] = a[0][k] * rcp;
+                else a[0][k] = a[0][k] / piv;
+            }
+        });
+        if (dead) break;
+        // rotate: the finished block goes last
+        T t0[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) t0[e] = a[0][e];
+#pragma unroll
+        for (int b = 0; b + 1 < NG; ++b)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) a[b][e] = a[b + 1][e];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) a[NG - 1][e] = t0[e];
+        const T n0 = nu[0];
+#pragma unroll
+        for (int b = 0; b + 1 < NG; ++b) nu[b] = nu[b + 1];
+        nu[NG - 1] = n0;
+    }
+    if (dead) return;  // uniform: every thread saw the same gather result
     if (live) {
+        using vq = typename Vq<T>::type;
+        constexpr int V = Vq<T>::V;
         vq *dst = reinterpret_cast<vq *>(W + (size_t)(k0 + pos) * ldw + k0);
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) dst[q] = a[q];
+        for (int b = 0; b < NG; ++b)
+#pragma unroll
+            for (int q = 0; q < 16 / V; ++q) {
+                vq v;
+#pragma unroll
+                for (int e = 0; e < V; ++e) v[e] = a[b][q * V + e];
+                dst[b * (16 / V) + q] = v;
+            }
     }
     __syncthreads();
     if (w == 0 && tid < B) {
@@ -273,7 +444,7 @@ hipError_t launch_panel(T *W, int ldw, int k0, int m, int *ipiv, unsigned long l
                         int *status, hipStream_t s) {
     constexpr int B = PanelWidth<T>::v;
     const int P = (m + kPanelRowsPerWG - 1) / kPanelRowsPerWG;
-    if (P < 1 || P > kPanelMaxWG) return hipErrorInvalidValue;
+    if (P < 1 || P > kPanelMaxWG || m < B) return hipErrorInvalidValue;
     // workers are dealt round-robin over the 8 XCDs: with stride 8 all of them
     // land on one XCD (32 CUs) and exchange through its L2
     const int stride = P == 1 ? 1 : (P <= 32 ? kXcdStride : kXcdStride / 2);
