@@ -210,6 +210,8 @@ size_t mixlu::plan_layout(Layout &L, int op, int prec, int n, int nrhs, const mi
     L.status = take(ST_COUNT * 4);
     L.norms = take((size_t)(4 + 3 * L.nrhs) * 8);
     L.krylov = take(((size_t)(2 * kKrylov + 2) * np + 4 * kKrylov + 16) * 8);
+    L.dinv = take(2 * np * kTrsvBS * (L.prec == MIXLU_FP64 ? 8 : 4));
+    L.dinv64 = L.fallback ? take(2 * np * kTrsvBS * 8) : 0;
     L.total = off;
     return off;
 }
@@ -261,8 +263,17 @@ Layout layout_of(const mixlu_factor *F) {
     // norms and the Krylov area follow status (same rule as plan_layout)
     L.norms = align_up(L.status + ST_COUNT * 4, 256);
     L.krylov = align_up(L.norms + (size_t)(4 + 3 * L.nrhs) * 8, 256);
+    // then the inverse diagonal blocks (same rule as plan_layout)
+    const size_t np = (size_t)L.npad;
+    L.dinv = align_up(L.krylov + ((2 * (size_t)kKrylov + 2) * np + 4 * kKrylov + 16) * 8, 256);
+    L.dinv64 = L.fallback
+                   ? align_up(L.dinv + 2 * np * kTrsvBS * (L.prec == MIXLU_FP64 ? 8 : 4), 256)
+                   : 0;
     return L;
 }
+
+// Region of the inverse diagonal blocks that belongs to the factor at woff.
+size_t dinv_of(const Layout &L, size_t woff) { return (L.W64 && woff == L.W64) ? L.dinv64 : L.dinv; }
 
 // Blocked right-looking LU with partial pivoting of W (npad x npad, ld = npad)
 // in place: per outer block of nb columns, panels of B columns (GEPP with
@@ -516,8 +527,11 @@ int convert_and_factor(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t wof
         HIPCK(launch_col_stats(A, lda, n, np, R, tmp + 2 * (size_t)np, C, equil, norms, s));
     }
     HIPCK(launch_convert<T>(A, lda, n, np, R, C, at<T>(work, woff), np, status, s));
-    if (L.kind == 1) return factor_chol<T>(s, work, L, woff, trail_prec);
-    return factor_lu<T>(ctx, work, L, woff, trail_prec);
+    if (L.kind == 1) RETCK(factor_chol<T>(s, work, L, woff, trail_prec));
+    else RETCK(factor_lu<T>(ctx, work, L, woff, trail_prec));
+    // the solves apply the inverses of the factors' 64 x 64 diagonal blocks
+    HIPCK(launch_tri_inv<T>(at<T>(work, woff), np, np, at<T>(work, dinv_of(L, woff)), s));
+    return MIXLU_OK;
 }
 
 // Low-precision solve with the factors of W = R M C, P W = L U:
@@ -530,6 +544,7 @@ int lu_solve(hipStream_t s, void *work, const Layout &L, size_t woff, int nrhs,
              int trans) {
     const int n = L.n, np = L.npad;
     const Tw *W = at<Tw>(work, woff);
+    const Tw *Dinv = at<Tw>(work, dinv_of(L, woff));
     Tw *Y = at<Tw>(work, L.vec_y);
     int *status = at<int>(work, L.status);
     double *xnorm = at<double>(work, L.norms) + 4 + L.nrhs;
@@ -543,11 +558,11 @@ int lu_solve(hipStream_t s, void *work, const Layout &L, size_t woff, int nrhs,
         const double tb = 0.5 * np * (np + 64.0) * sizeof(Tw) + 2.0 * np * sizeof(Tw);
         {
             ProfScope ps(PC_TRSV, (double)np * np, tb, s);
-            HIPCK(launch_trsv<Tw>(0, trans, W, np, np, Y, 1, 1, ybuf, status, s));
+            HIPCK(launch_trsv<Tw>(0, trans, W, np, Dinv, np, Y, 1, 1, ybuf, status, s));
         }
         {
             ProfScope ps(PC_TRSV, (double)np * np, tb, s);
-            HIPCK(launch_trsv<Tw>(1, trans, W, np, np, Y, 1, 1, ybuf, status, s));
+            HIPCK(launch_trsv<Tw>(1, trans, W, np, Dinv, np, Y, 1, 1, ybuf, status, s));
         }
     } else {
         // several: diagonal blocks one column per thread plus GEMM updates
@@ -1602,6 +1617,13 @@ int mixlu_refine(mixlu_ctx_t ctx, mixlu_factor *F, int trans, int nrhs, const do
     F->off[0] = L.W64;
     F->off[1] = 0;
     F->lowp_status = info ? -1 : 0;
+    {
+        // the inverse diagonal blocks where the rewritten description looks
+        // for them (over the low-precision factor's, which are abandoned)
+        const Layout L2 = layout_of(F);
+        HIPCK(launch_tri_inv<double>(at<double>(F->work, L.W64), L.npad, L.npad,
+                                     at<double>(F->work, L2.dinv), ctx->stream));
+    }
     rep->info = info;
     rep->prec = MIXLU_FP64;
     rep->fallback_iter = fres.iters;

@@ -258,6 +258,8 @@ struct Layout {
     size_t tmp;      // scratch: row/column statistics (double[(kColChunks + 2) * npad])
     size_t status;   // int[ST_COUNT]
     size_t norms;    // double[4 + 3 * nrhs]: anorm, ..., rnorm[nrhs], xnorm[nrhs], prev[nrhs]
+    size_t dinv;     // inverse diagonal blocks of W's factors (2 npad x 64, W's element type)
+    size_t dinv64;   // the same for W64 (FP64), or 0
     size_t total;
 };
 
@@ -371,9 +373,13 @@ hipError_t launch_cond_test(const double *z, double *x, int n, double *out, hipS
 template <typename Tw>
 hipError_t launch_rhs_gather(int n, int npad, int nrhs, const double *B, int ldb, int b_col_major,
                              const int *perm, const double *R, Tw *Y, int ldy, hipStream_t s);
+// Inverses of the 64 x 64 diagonal blocks of L and U in W (dinv: 2 npad x 64)
+template <typename T>
+hipError_t launch_tri_inv(const T *W, int ldw, int npad, T *dinv, hipStream_t s);
 template <typename Tw>
-hipError_t launch_trsv(int upper, int trans, const Tw *W, int ldw, int npad, Tw *Y, int ldy,
-                       int nrhs, unsigned long long *ybuf, int *status, hipStream_t s);
+hipError_t launch_trsv(int upper, int trans, const Tw *W, int ldw, const Tw *dinv, int npad,
+                       Tw *Y, int ldy, int nrhs, unsigned long long *ybuf, int *status,
+                       hipStream_t s);
 template <typename Tw>
 hipError_t launch_x_update(int n, int npad, int nrhs, int assign, const Tw *Y, int ldy,
                            const int *perm, const double *C, double *X, int ldx, int x_col_major,

@@ -66,24 +66,73 @@ template hipError_t launch_rhs_gather<double>(int, int, int, const double *, int
                                               const int *, const double *, double *, int,
                                               hipStream_t);
 
+// Inverses of the 64 x 64 diagonal blocks of the factors stored in W
+// (npad x npad, ld = ldw): block b of the unit lower L (blockIdx.y = 0) into
+// dinv[b * 64 * 64 ..], of the upper U (blockIdx.y = 1) into
+// dinv[(npad + b * 64) * 64 ..], row-major 64 x 64.  One wave per block;
+// lane c forms column c of the inverse by substitution against the block
+// staged in LDS (rows read with broadcast loads).
+template <typename T>
+__global__ __launch_bounds__(64) void k_tri_inv(const T *__restrict__ W, int ldw, int npad,
+                                                T *__restrict__ dinv) {
+    constexpr int BS = kTrsvBS;
+    __shared__ __attribute__((aligned(16))) T sM[BS][BS];
+    const int b = blockIdx.x, upper = blockIdx.y, lane = threadIdx.x;
+    for (int r = 0; r < BS; ++r) sM[r][lane] = W[(size_t)(b * BS + r) * ldw + b * BS + lane];
+    __syncthreads();
+    T x[BS];
+    if (!upper) {  // L x = e_c: x_i = [i = c] - sum_{k < i} l_ik x_k
+#pragma unroll
+        for (int i = 0; i < BS; ++i) {
+            T v = (i == lane) ? (T)1 : (T)0;
+#pragma unroll
+            for (int k = 0; k < i; ++k) v -= sM[i][k] * x[k];
+            x[i] = v;
+        }
+    } else {  // U x = e_c: x_i = ([i = c] - sum_{k > i} u_ik x_k) / u_ii
+#pragma unroll
+        for (int i = BS - 1; i >= 0; --i) {
+            T v = (i == lane) ? (T)1 : (T)0;
+#pragma unroll
+            for (int k = i + 1; k < BS; ++k) v -= sM[i][k] * x[k];
+            x[i] = v / sM[i][i];
+        }
+    }
+    T *out = dinv + ((size_t)upper * npad + (size_t)b * BS) * BS;
+#pragma unroll
+    for (int r = 0; r < BS; ++r) out[r * BS + lane] = x[r];
+}
+
+template <typename T>
+hipError_t launch_tri_inv(const T *W, int ldw, int npad, T *dinv, hipStream_t s) {
+    if (npad == 0) return hipSuccess;
+    if (npad % kTrsvBS) return hipErrorInvalidValue;
+    k_tri_inv<T><<<dim3(npad / kTrsvBS, 2), dim3(64), 0, s>>>(W, ldw, npad, dinv);
+    return hipGetLastError();
+}
+template hipError_t launch_tri_inv<float>(const float *, int, int, float *, hipStream_t);
+template hipError_t launch_tri_inv<double>(const double *, int, int, double *, hipStream_t);
+
 // Chained block triangular solve, in place in Y (npad x nrhs, ldy), nrhs <=
 // NRT.  TRANS = false: upper = 0 solves with the unit lower L (below the
 // diagonal of W), forward; upper = 1 with U (on and above the diagonal),
 // backward.  TRANS = true solves with the transposed factors: upper = 0
 // with U^T (lower, non-unit), forward; upper = 1 with L^T (upper, unit),
-// backward.  yx holds the published solution words ((row * NRT + c) * PWV +
-// word), zeroed before the launch together with the ticket counter at
-// yx[npad * NRT * PWV].
+// backward.  Workgroup b (in ticket order) accumulates the products of its
+// block row with the solved blocks as they are published, then applies the
+// inverse of its diagonal block (from k_tri_inv: dinv, 2 npad x 64) as a
+// 64 x 64 product instead of 64 dependent substitution steps.  yx holds the
+// published solution words ((row * NRT + c) * PWV + word), zeroed before the
+// launch together with the ticket counter at yx[npad * NRT * PWV].
 template <typename T, int NRT, bool TRANS>
 __global__ __launch_bounds__(256) void k_trsv(int upper, const T *__restrict__ W, int ldw,
-                                              int nblk, T *__restrict__ Y, int ldy, int nrhs,
+                                              const T *__restrict__ dinv, int nblk,
+                                              T *__restrict__ Y, int ldy, int nrhs,
                                               unsigned long long *__restrict__ yx,
                                               int *__restrict__ status) {
     constexpr int BS = kTrsvBS, PWV = Words<T>::n;
-    constexpr int JB = 1;                          // off-diagonal blocks per round trip
-    constexpr int NWMAX = JB * BS * NRT * PWV;     // words of JB solution blocks
+    constexpr int NWMAX = BS * NRT * PWV;          // words of one solution block
     constexpr int WPT = (NWMAX + 255) / 256;       // words per thread
-    __shared__ T sL[BS][BS + 1];
     __shared__ unsigned swords[2][NWMAX];
     __shared__ T sy[BS][NRT];
     __shared__ int s_b, s_bad;
@@ -103,48 +152,43 @@ __global__ __launch_bounds__(256) void k_trsv(int upper, const T *__restrict__ W
     T acc[NRT];
 #pragma unroll
     for (int c = 0; c < NRT; ++c) acc[c] = (T)0;
-    // the diagonal tile is needed last but does not depend on anything:
-    // request it now so its latency is off the critical path
     // element (b*BS + r, jb*BS + q*16 + e) of the triangular matrix
     auto tile_ptr = [&](int jb) -> const T * {
         return TRANS ? W + (size_t)(jb * BS + q * 16) * ldw + (size_t)b * BS + r
                      : W + (size_t)(b * BS + r) * ldw + (size_t)jb * BS + q * 16;
     };
-    constexpr size_t ES = 1;
-    const size_t estride = TRANS ? (size_t)ldw : ES;
+    const size_t estride = TRANS ? (size_t)ldw : (size_t)1;
+    // row r, columns q*16 .. q*16+15 of the inverse diagonal block, requested
+    // now (it does not depend on anything): inv(L) or inv(U), transposed for
+    // the transposed solves (inv(U^T) = inv(U)^T)
     T dg[16];
     {
-        const T *drow = tile_ptr(b);
+        const bool inv_u = (upper != 0) != TRANS;  // U (not transposed) or U^T
+        const T *dblk = dinv + ((size_t)(inv_u ? nblk : 0) * BS + (size_t)b * BS) * BS;
 #pragma unroll
-        for (int e = 0; e < 16; ++e) dg[e] = TRANS ? drow[e * estride] : drow[e];
+        for (int e = 0; e < 16; ++e)
+            dg[e] = TRANS ? dblk[(q * 16 + e) * BS + r] : dblk[r * BS + q * 16 + e];
     }
 
     const int nsteps = upper ? nblk - 1 - b : b;
     int par = 0;
-    for (int st0 = 0; st0 < nsteps; st0 += JB, par ^= 1) {
-        const int nb_ = nsteps - st0 < JB ? nsteps - st0 : JB;
-        // L (or U) tile rows for up to JB blocks, and their solution words,
-        // all requested before any wait
-        T lv[JB][16];
-#pragma unroll
-        for (int u = 0; u < JB; ++u) {
-            const int st = st0 + u;
-            const int j = upper ? nblk - 1 - st : st;
+    for (int st = 0; st < nsteps; ++st, par ^= 1) {
+        const int j = upper ? nblk - 1 - st : st;
+        // the tile row and the solution words of block j, all requested
+        // before any wait
+        T lv[16];
+        {
             const T *lrow = tile_ptr(j);
 #pragma unroll
-            for (int e = 0; e < 16; ++e)
-                lv[u][e] = (u < nb_) ? (TRANS ? lrow[e * estride] : lrow[e]) : (T)0;
+            for (int e = 0; e < 16; ++e) lv[e] = TRANS ? lrow[e * estride] : lrow[e];
         }
         unsigned long long wv[WPT];
 #pragma unroll
         for (int p = 0; p < WPT; ++p) {
             const int t = tid + p * 256;
             wv[p] = 0ull;
-            if (t < nb_ * wblk) {
-                const int u = t / wblk, rem = t - u * wblk;
-                const int st = st0 + u;
-                const int j = upper ? nblk - 1 - st : st;
-                const int i = rem / (nrhs * PWV), rr = rem - i * (nrhs * PWV);
+            if (t < wblk) {
+                const int i = t / (nrhs * PWV), rr = t - i * (nrhs * PWV);
                 wv[p] = xload(yx + ((size_t)(j * BS + i) * NRT) * PWV + rr);
             }
         }
@@ -152,13 +196,10 @@ __global__ __launch_bounds__(256) void k_trsv(int upper, const T *__restrict__ W
 #pragma unroll
         for (int p = 0; p < WPT; ++p) {
             const int t = tid + p * 256;
-            if (t < nb_ * wblk) {
+            if (t < wblk) {
                 unsigned v = (unsigned)wv[p];
                 if ((unsigned)(wv[p] >> 32) != 1u && !bad) {
-                    const int u = t / wblk, rem = t - u * wblk;
-                    const int st = st0 + u;
-                    const int j = upper ? nblk - 1 - st : st;
-                    const int i = rem / (nrhs * PWV), rr = rem - i * (nrhs * PWV);
+                    const int i = t / (nrhs * PWV), rr = t - i * (nrhs * PWV);
                     v = spin_tag(yx + ((size_t)(j * BS + i) * NRT) * PWV + rr, 1u,
                                  &status[ST_TIMEOUT], bad);
                 }
@@ -169,18 +210,11 @@ __global__ __launch_bounds__(256) void k_trsv(int upper, const T *__restrict__ W
         __syncthreads();
         if (s_bad) return;
 #pragma unroll
-        for (int u = 0; u < JB; ++u) {
-            if (u < nb_) {
+        for (int e = 0; e < 16; ++e) {
+            const int i = q * 16 + e;
 #pragma unroll
-                for (int e = 0; e < 16; ++e) {
-                    const int i = q * 16 + e;
-#pragma unroll
-                    for (int c = 0; c < NRT; ++c)
-                        if (c < nrhs)
-                            acc[c] += lv[u][e] *
-                                      Words<T>::make(&swords[par][u * wblk + (i * nrhs + c) * PWV]);
-                }
-            }
+            for (int c = 0; c < NRT; ++c)
+                if (c < nrhs) acc[c] += lv[e] * Words<T>::make(&swords[par][(i * nrhs + c) * PWV]);
         }
     }
     // combine the four k-quarters of each row
@@ -194,66 +228,37 @@ __global__ __launch_bounds__(256) void k_trsv(int upper, const T *__restrict__ W
         for (int c = 0; c < NRT; ++c)
             if (c < nrhs) sy[r][c] = Y[(size_t)(b * BS + r) * ldy + c] - acc[c];
     }
-#pragma unroll
-    for (int e = 0; e < 16; ++e) sL[r][q * 16 + e] = dg[e];
     __syncthreads();
-    if (tid < 64) {
-        const int lane = tid;
-        T sv[NRT];
+    // y_b = inv(M_bb) (rhs_b - sum_j M_bj y_j): 16 products per thread, then
+    // the four quarters of each row
+    T yv[NRT];
 #pragma unroll
-        for (int c = 0; c < NRT; ++c) sv[c] = (c < nrhs) ? sy[lane][c] : (T)0;
-        // this lane's row of the diagonal block, in registers: the sequential
-        // steps below then touch no memory at all
-        T lrow[BS];
+    for (int c = 0; c < NRT; ++c) {
+        T v = (T)0;
 #pragma unroll
-        for (int k = 0; k < BS; ++k) lrow[k] = sL[lane][k];
-        // non-unit triangles: scale this lane's row and value by the
-        // reciprocal of its diagonal entry before the chain (the system
-        // D^-1 M y = D^-1 r has a unit diagonal), so every dependent step is
-        // one broadcast and one FMA
-        const bool unit = upper == (int)TRANS;  // L (forward) or L^T (backward)
-        if (!unit) {
-            const T dinv = (T)1 / sL[lane][lane];
-#pragma unroll
-            for (int k = 0; k < BS; ++k) lrow[k] *= dinv;
-#pragma unroll
-            for (int c = 0; c < NRT; ++c) sv[c] *= dinv;
-        }
-        if (!upper) {  // forward
-#pragma unroll
-            for (int k = 0; k < BS; ++k) {
-#pragma unroll
-                for (int c = 0; c < NRT; ++c) {
-                    const T yk = bcast_lane(sv[c], k);
-                    if (lane > k) sv[c] -= lrow[k] * yk;
-                }
-            }
-        } else {  // backward
-#pragma unroll
-            for (int k = BS - 1; k >= 0; --k) {
-#pragma unroll
-                for (int c = 0; c < NRT; ++c) {
-                    const T yk = bcast_lane(sv[c], k);
-                    if (lane < k) sv[c] -= lrow[k] * yk;
-                }
-            }
-        }
-        const int row = b * BS + lane;
+        for (int e = 0; e < 16; ++e) v += dg[e] * sy[q * 16 + e][c];
+        v += __shfl_xor(v, 1);
+        v += __shfl_xor(v, 2);
+        yv[c] = v;
+    }
+    if (q == 0) {
+        const int row = b * BS + r;
 #pragma unroll
         for (int c = 0; c < NRT; ++c) {
             if (c < nrhs) {
-                Y[(size_t)row * ldy + c] = sv[c];
+                Y[(size_t)row * ldy + c] = yv[c];
 #pragma unroll
                 for (int wv = 0; wv < PWV; ++wv)
-                    xstore(yx + ((size_t)row * NRT + c) * PWV + wv, 1u, Words<T>::get(sv[c], wv));
+                    xstore(yx + ((size_t)row * NRT + c) * PWV + wv, 1u, Words<T>::get(yv[c], wv));
             }
         }
     }
 }
 
 template <typename Tw, bool TRANS>
-hipError_t launch_trsv_t(int upper, const Tw *W, int ldw, int npad, Tw *Y, int ldy, int nrhs,
-                         unsigned long long *ybuf, int *status, hipStream_t s) {
+hipError_t launch_trsv_t(int upper, const Tw *W, int ldw, const Tw *dinv, int npad, Tw *Y,
+                         int ldy, int nrhs, unsigned long long *ybuf, int *status,
+                         hipStream_t s) {
     if (npad == 0 || nrhs == 0) return hipSuccess;
     if (nrhs > kTrsvNRT || npad % kTrsvBS) return hipErrorInvalidValue;
     const int nblk = npad / kTrsvBS;
@@ -263,24 +268,27 @@ hipError_t launch_trsv_t(int upper, const Tw *W, int ldw, int npad, Tw *Y, int l
     if (e != hipSuccess) return e;
     // each instantiation lays its words (and ticket) out inside the zeroed region
     if (nrhs == 1)
-        k_trsv<Tw, 1, TRANS><<<dim3(nblk), dim3(256), 0, s>>>(upper, W, ldw, nblk, Y, ldy, nrhs,
-                                                              ybuf, status);
+        k_trsv<Tw, 1, TRANS><<<dim3(nblk), dim3(256), 0, s>>>(upper, W, ldw, dinv, nblk, Y, ldy,
+                                                              nrhs, ybuf, status);
     else
-        k_trsv<Tw, kTrsvNRT, TRANS><<<dim3(nblk), dim3(256), 0, s>>>(upper, W, ldw, nblk, Y, ldy,
-                                                                     nrhs, ybuf, status);
+        k_trsv<Tw, kTrsvNRT, TRANS><<<dim3(nblk), dim3(256), 0, s>>>(upper, W, ldw, dinv, nblk, Y,
+                                                                     ldy, nrhs, ybuf, status);
     return hipGetLastError();
 }
 
 template <typename Tw>
-hipError_t launch_trsv(int upper, int trans, const Tw *W, int ldw, int npad, Tw *Y, int ldy,
-                       int nrhs, unsigned long long *ybuf, int *status, hipStream_t s) {
-    return trans ? launch_trsv_t<Tw, true>(upper, W, ldw, npad, Y, ldy, nrhs, ybuf, status, s)
-                 : launch_trsv_t<Tw, false>(upper, W, ldw, npad, Y, ldy, nrhs, ybuf, status, s);
+hipError_t launch_trsv(int upper, int trans, const Tw *W, int ldw, const Tw *dinv, int npad,
+                       Tw *Y, int ldy, int nrhs, unsigned long long *ybuf, int *status,
+                       hipStream_t s) {
+    return trans ? launch_trsv_t<Tw, true>(upper, W, ldw, dinv, npad, Y, ldy, nrhs, ybuf, status, s)
+                 : launch_trsv_t<Tw, false>(upper, W, ldw, dinv, npad, Y, ldy, nrhs, ybuf, status,
+                                            s);
 }
-template hipError_t launch_trsv<float>(int, int, const float *, int, int, float *, int, int,
-                                       unsigned long long *, int *, hipStream_t);
-template hipError_t launch_trsv<double>(int, int, const double *, int, int, double *, int, int,
-                                        unsigned long long *, int *, hipStream_t);
+template hipError_t launch_trsv<float>(int, int, const float *, int, const float *, int, float *,
+                                       int, int, unsigned long long *, int *, hipStream_t);
+template hipError_t launch_trsv<double>(int, int, const double *, int, const double *, int,
+                                        double *, int, int, unsigned long long *, int *,
+                                        hipStream_t);
 
 // One step of the blocked solve for several right-hand sides: workgroup
 // (x, y) takes the 16 columns 16y .. 16y+15, four per wave.  Every workgroup
