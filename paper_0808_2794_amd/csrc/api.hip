@@ -45,7 +45,7 @@ struct mixlu_ctx_s {
     int device = 0;
     hipStream_t stream = nullptr;
     hipStream_t side = nullptr;  // look-ahead: trailing updates overlapped with panels
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_next = nullptr;
     double *hbuf = nullptr;  // pinned host mirror of the norms / status
     size_t hbuf_bytes = 0;
     int num_cu = 256;
@@ -105,6 +105,7 @@ int ensure_side(mixlu_ctx_s *ctx) {
     HIPCK(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
     HIPCK(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
     HIPCK(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
+    HIPCK(hipEventCreateWithFlags(&ctx->ev_next, hipEventDisableTiming));
     return MIXLU_OK;
 }
 
@@ -191,11 +192,11 @@ size_t mixlu::plan_layout(Layout &L, int op, int prec, int n, int nrhs, const mi
     };
     L.W = take(wbytes);
     L.W64 = L.fallback ? take(np * np * 8) : 0;
-    // packed trailing-update operands, two sets (look-ahead: the next block
-    // packs while the previous block's update still reads its set)
+    // packed trailing-update operands, three sets (look-ahead: the next
+    // blocks pack while an earlier block's update still reads its set)
     const size_t pk = is_lowp(L.prec) ? np * L.nb * 2 : 0;
-    L.Ap = take(2 * pk);
-    L.Bp = take(2 * pk);
+    L.Ap = take(3 * pk);
+    L.Bp = take(3 * pk);
     L.ipiv = take(np * 4);
     L.perm = take(np * 4);
     L.R = take(np * 8);
@@ -205,7 +206,7 @@ size_t mixlu::plan_layout(Layout &L, int op, int prec, int n, int nrhs, const mi
     L.vec_z = L.nrhs > 1 ? take(np * L.nrhs * 8) : L.vec_y;
     L.xbuf = take((size_t)kXbufWords * 8);
     L.ybuf = take((np * kTrsvNRT * 2 + 64) * 8);
-    L.moves = take((size_t)(4 + 2 * 1024) * 4);
+    L.moves = take((size_t)2 * kMovesInts * 4);
     L.tmp = take((size_t)(2 * kColChunks + 2) * np * 8);
     L.status = take(ST_COUNT * 4);
     L.norms = take((size_t)(4 + 3 * L.nrhs) * 8);
@@ -276,11 +277,19 @@ Layout layout_of(const mixlu_factor *F) {
 size_t dinv_of(const Layout &L, size_t woff) { return (L.W64 && woff == L.W64) ? L.dinv64 : L.dinv; }
 
 // Blocked right-looking LU with partial pivoting of W (npad x npad, ld = npad)
-// in place: per outer block of nb columns, panels of B columns (GEPP with
-// pivot search), their row interchanges on the rest of the outer block, the
-// triangular solve and FP32/FP64 update inside the block; then the
-// interchanges on the other columns, U12 = L11^{-1} A12 and the trailing
-// update A22 -= L21 U12 (in FP32/FP64, or with BF16/FP16 operands on MFMA).
+// in place, with look-ahead over two streams.  Per outer block K of nb
+// columns, the main stream factors the block's panels of B columns (GEPP with
+// pivot search; their row interchanges, triangular solve and FP32/FP64
+// update inside the block), then brings only the next block's columns up to
+// date: its row interchanges, U12 = L11^{-1} A12 and A22 -= L21 U12 for
+// those nb columns, and goes on to the next block's panels.  The side stream
+// does the rest of block K: the interchanges on the columns left of the
+// block and right of the next one, their U12, and their trailing update
+// (in FP32/FP64, or with BF16/FP16/FP8 operands on MFMA), the block after
+// next first, so that the main stream can take it at its next step.
+// Events: ev_fork (main -> side: block K factored, its pivots composed and
+// L21 packed), ev_next (side -> main: the block after next is up to date
+// with block K), ev_join (side -> main at the end).
 template <typename T>
 int factor_lu(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t woff, int trail_prec) {
     constexpr int B = sizeof(T) == 4 ? kPanelBF : kPanelBD;
@@ -291,20 +300,87 @@ int factor_lu(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t woff, int tr
     int *perm = at<int>(work, L.perm);
     int *status = at<int>(work, L.status);
     auto *xbuf = at<unsigned long long>(work, L.xbuf);
-    int *moves = at<int>(work, L.moves);  // row-move list of the wide (outer) pivot blocks
-    if (nb % B || nb % 64 || nb > 512) return MIXLU_ERR_NOT_IMPLEMENTED;
+    // row-move lists of the wide (outer) pivot blocks, one per parity: the
+    // side stream may still apply block K's while block K+1 composes
+    int *moves2[2] = {at<int>(work, L.moves), at<int>(work, L.moves) + kMovesInts};
+    if (nb % B || nb % 64 || nb > kMaxOuterBlock) return MIXLU_ERR_NOT_IMPLEMENTED;
     RETCK(ensure_side(ctx));
     hipStream_t s2 = ctx->side;
     HIPCK(launch_iota(perm, np, s));
     HIPCK(launch_fill_u32(reinterpret_cast<unsigned *>(xbuf), 0u, (size_t)kXbufWords * 2, s));
     auto Wp = [&](int r, int c) { return W + (size_t)r * np + c; };
-    const size_t pk = (size_t)np * nb;  // elements of one packed operand set
-    bool side_busy = false;             // the side stream holds an update of W
-    int par = 0;
+    const bool lowp = !(trail_prec == MIXLU_FP64 || trail_prec == MIXLU_FP32);
+    if (lowp && sizeof(T) != 4) return MIXLU_ERR_NOT_IMPLEMENTED;
+    const bool f8 = trail_prec == MIXLU_FP8;
+    const int esz = f8 ? 1 : 2;                 // bytes per packed operand
+    const size_t pk = (size_t)np * nb;          // elements of one packed operand set
+    const bool wide = nb > kSwapsFused;         // interchanges composed once, applied per range
+    bool side_used = false;   // the side stream holds work of this factorization
+    bool next_ready = false;  // ev_next marks the next block's columns up to date
+    int par = 0;              // move-list parity
+    // packed-operand set of this block: three sets, because the side
+    // stream's update of block K may still read L21(K) until the main stream
+    // has waited for the side's next-block event of block K+1
+    int pset = 0;
+    // interchanges of block K on [c0, c1) minus [skip0, skip1), on stream st
+    auto swaps = [&](int K0, int c0, int c1, int skip0, int skip1, hipStream_t st) -> int {
+        if (wide)
+            HIPCK(launch_swaps_apply<T>(W, np, moves2[par], nb, c0, c1, skip0, skip1, st));
+        else
+            HIPCK(launch_row_swaps<T>(ipiv, K0, nb, np, nullptr, W, np, c0, c1, skip0, skip1,
+                                      nullptr, st));
+        return MIXLU_OK;
+    };
+    // U12 = L11^{-1} A12 for the columns [c0, c0 + ncol) of block K's rows
+    auto u12 = [&](int K0, int c0, int ncol, hipStream_t st) -> int {
+        if (ncol <= 0) return MIXLU_OK;
+        for (int ib = 0; ib < nb; ib += B) {
+            HIPCK(launch_trsm_diag<T>(Wp(K0 + ib, K0 + ib), np, Wp(K0 + ib, c0), np, ncol, st));
+            if (ib + B < nb)
+                HIPCK(launch_gemm<T>(nb - ib - B, ncol, B, Wp(K0 + ib + B, K0 + ib), np,
+                                     Wp(K0 + ib, c0), np, Wp(K0 + ib + B, c0), np, st));
+        }
+        return MIXLU_OK;
+    };
+    // A22[:, c0 : c0 + ncol] -= L21 U12[:, c0 : c0 + ncol] (rows kend..), with
+    // U12's columns packed first on the low-precision path
+    auto update = [&](int K0, int c0, int ncol, hipStream_t st, int spare) -> int {
+        if (ncol <= 0) return MIXLU_OK;
+        const int kend = K0 + nb, nr = np - kend, cr = c0 - kend;  // cr: column within U12
+        if (!lowp) {
+            ProfScope ps(PC_TRAIL, 2.0 * nr * ncol * nb,
+                         (2.0 * nr * ncol + 1.0 * (nr + ncol) * nb) * sizeof(T), st);
+            HIPCK(launch_gemm<T>(nr, ncol, nb, Wp(kend, K0), np, Wp(K0, c0), np, Wp(kend, c0), np,
+                                 st, 0, 0, 0, spare));
+            return MIXLU_OK;
+        }
+        if constexpr (sizeof(T) == 4) {
+            auto *Ap = at<unsigned char>(work, L.Ap) + pset * pk * 2;
+            auto *Bp = at<unsigned char>(work, L.Bp) + pset * pk * 2;
+            auto *As = Ap + pk, *Bs = Bp + pk;  // FP8: codes, then one scale byte per 32 codes
+            {
+                ProfScope ps(PC_PACK, 0.0, 1.0 * ncol * nb * (4 + esz), st);
+                if (f8)
+                    HIPCK(launch_pack_fp8(Wp(K0, c0), np, ncol, nb, 1, Bp + (size_t)cr * nb,
+                                          Bs + (size_t)cr * (nb / 32), status, st));
+                else
+                    HIPCK(launch_pack(trail_prec, Wp(K0, c0), np, nb, ncol, 1,
+                                      Bp + (size_t)cr * nb * 2, status, st));
+            }
+            ProfScope ps(PC_TRAIL, 2.0 * nr * ncol * nb, 8.0 * nr * ncol + 1.0 * esz * (nr + ncol) * nb,
+                         st);
+            if (f8)
+                HIPCK(launch_gemm_fp8(nr, ncol, nb, Ap, As, Bp + (size_t)cr * nb,
+                                      Bs + (size_t)cr * (nb / 32), Wp(kend, c0), np, st, 0, spare));
+            else
+                HIPCK(launch_gemm_lowp(trail_prec, nr, ncol, nb, Ap, Bp + (size_t)cr * nb * 2,
+                                       Wp(kend, c0), np, st, 0, spare));
+        }
+        return MIXLU_OK;
+    };
     for (int K0 = 0; K0 < np; K0 += nb) {
         const int kend = K0 + nb;
-        // panels of this block: only columns K0..kend-1, which the previous
-        // block updated first, so they overlap the rest of its update
+        // panels of this block: only its columns, which are up to date
         for (int k = K0; k < kend; k += B) {
             {
                 const double m = np - k;
@@ -313,7 +389,7 @@ int factor_lu(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t woff, int tr
                 ProfScope ps(PC_PANEL, fl, 2.0 * m * B * sizeof(T), s);
                 HIPCK(launch_panel<T>(W, np, k, np - k, ipiv, xbuf, status, s));
             }
-            HIPCK(launch_row_swaps<T>(ipiv, k, B, np, perm, W, np, K0, kend, k, k + B, moves,
+            HIPCK(launch_row_swaps<T>(ipiv, k, B, np, perm, W, np, K0, kend, k, k + B, nullptr,
                                       s));
             if (k + B < kend) {
                 HIPCK(launch_trsm_diag<T>(Wp(k, k), np, Wp(k, k + B), np, kend - k - B, s));
@@ -321,90 +397,54 @@ int factor_lu(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t woff, int tr
                                      np, Wp(k + B, k + B), np, s));
             }
         }
-        // the interchanges reach every other column: the side stream's update
-        // of the previous block must be complete
-        if (side_busy) {
-            HIPCK(hipStreamWaitEvent(s, ctx->ev_join, 0));
-            side_busy = false;
-        }
-        HIPCK(launch_row_swaps<T>(ipiv, K0, nb, np, nullptr, W, np, 0, np, K0, kend, moves, s));
-        if (kend >= np) break;
         const int nr = np - kend;
-        for (int ib = 0; ib < nb; ib += B) {
-            HIPCK(launch_trsm_diag<T>(Wp(K0 + ib, K0 + ib), np, Wp(K0 + ib, kend), np, nr, s));
-            if (ib + B < nb)
-                HIPCK(launch_gemm<T>(nb - ib - B, nr, B, Wp(K0 + ib + B, K0 + ib), np,
-                                     Wp(K0 + ib, kend), np, Wp(K0 + ib + B, kend), np, s));
+        if (nr == 0) {
+            // last block: its interchanges on the columns to the left, once
+            // the side stream has finished
+            if (side_used) HIPCK(hipStreamWaitEvent(s, ctx->ev_join, 0));
+            side_used = false;
+            if (wide) HIPCK(launch_swaps_compose(ipiv, K0, nb, np, nullptr, moves2[par], s));
+            RETCK(swaps(K0, 0, K0, K0, K0, s));
+            break;
         }
-        // trailing update: the next block's columns now (stream s), the rest
-        // on the side stream, overlapping the next block's panels
-        const int nx = nr < nb ? nr : nb;
+        const int nx = nr < nb ? nr : nb;  // the next block's columns
         const int rest = nr - nx;
-        if (trail_prec == MIXLU_FP64 || trail_prec == MIXLU_FP32) {
-            {
-                ProfScope ps(PC_TRAIL, 2.0 * nr * nx * nb, (2.0 * nr * nx + 1.0 * (nr + nx) * nb) * sizeof(T), s);
-                HIPCK(launch_gemm<T>(nr, nx, nb, Wp(kend, K0), np, Wp(K0, kend), np,
-                                     Wp(kend, kend), np, s));
-            }
-            if (rest > 0) {
-                HIPCK(hipEventRecord(ctx->ev_fork, s));
-                HIPCK(hipStreamWaitEvent(s2, ctx->ev_fork, 0));
-                {
-                    ProfScope ps(PC_TRAIL, 2.0 * nr * rest * nb,
-                                 (2.0 * nr * rest + 1.0 * (nr + rest) * nb) * sizeof(T), s2);
-                    HIPCK(launch_gemm<T>(nr, rest, nb, Wp(kend, K0), np, Wp(K0, kend + nx), np,
-                                         Wp(kend, kend + nx), np, s2, 0, 0, 0, 1));
-                }
-                HIPCK(hipEventRecord(ctx->ev_join, s2));
-                side_busy = true;
-            }
-        } else {
+        if (wide) HIPCK(launch_swaps_compose(ipiv, K0, nb, np, nullptr, moves2[par], s));
+        if (lowp) {
             if constexpr (sizeof(T) == 4) {
-                // one packed set: 2 * pk bytes for A (L21) and for B (U12)
-                auto *Ap = at<unsigned char>(work, L.Ap) + par * pk * 2;
-                auto *Bp = at<unsigned char>(work, L.Bp) + par * pk * 2;
-                par ^= 1;
-                const bool f8 = trail_prec == MIXLU_FP8;
-                // FP8: codes then one scale byte per 32 codes
-                auto *As = Ap + pk, *Bs = Bp + pk;
-                const int esz = f8 ? 1 : 2;
-                {
-                    ProfScope ps(PC_PACK, 0.0, 1.0 * nr * nb * (4 + esz) * 2, s);
-                    if (f8) {
-                        HIPCK(launch_pack_fp8(Wp(kend, K0), np, nr, nb, 0, Ap, As, status, s));
-                        HIPCK(launch_pack_fp8(Wp(K0, kend), np, nr, nb, 1, Bp, Bs, status, s));
-                    } else {
-                        HIPCK(launch_pack(trail_prec, Wp(kend, K0), np, nr, nb, 0, Ap, status, s));
-                        HIPCK(launch_pack(trail_prec, Wp(K0, kend), np, nb, nr, 1, Bp, status, s));
-                    }
-                }
-                auto update = [&](int ncol, int c0, hipStream_t st, int spare) -> int {
-                    ProfScope ps(PC_TRAIL, 2.0 * nr * ncol * nb,
-                                 8.0 * nr * ncol + 1.0 * esz * (nr + ncol) * nb, st);
-                    if (f8)
-                        HIPCK(launch_gemm_fp8(nr, ncol, nb, Ap, As, Bp + (size_t)c0 * nb,
-                                              Bs + (size_t)c0 * (nb / 32), Wp(kend, kend + c0), np,
-                                              st, 0, spare));
-                    else
-                        HIPCK(launch_gemm_lowp(trail_prec, nr, ncol, nb, Ap,
-                                               Bp + (size_t)c0 * nb * 2, Wp(kend, kend + c0), np,
-                                               st, 0, spare));
-                    return MIXLU_OK;
-                };
-                RETCK(update(nx, 0, s, 0));
-                if (rest > 0) {
-                    HIPCK(hipEventRecord(ctx->ev_fork, s));
-                    HIPCK(hipStreamWaitEvent(s2, ctx->ev_fork, 0));
-                    RETCK(update(rest, nx, s2, 1));
-                    HIPCK(hipEventRecord(ctx->ev_join, s2));
-                    side_busy = true;
-                }
-            } else {
-                return MIXLU_ERR_NOT_IMPLEMENTED;
+                auto *Ap = at<unsigned char>(work, L.Ap) + pset * pk * 2;
+                auto *As = Ap + pk;
+                ProfScope ps(PC_PACK, 0.0, 1.0 * nr * nb * (4 + esz), s);
+                if (f8) HIPCK(launch_pack_fp8(Wp(kend, K0), np, nr, nb, 0, Ap, As, status, s));
+                else HIPCK(launch_pack(trail_prec, Wp(kend, K0), np, nr, nb, 0, Ap, status, s));
             }
         }
+        // hand block K to the side stream
+        HIPCK(hipEventRecord(ctx->ev_fork, s));
+        HIPCK(hipStreamWaitEvent(s2, ctx->ev_fork, 0));
+        side_used = true;
+        // main: the next block's columns (the side stream brought them up to
+        // date with the previous block)
+        if (next_ready) HIPCK(hipStreamWaitEvent(s, ctx->ev_next, 0));
+        RETCK(swaps(K0, kend, kend + nx, kend, kend, s));
+        RETCK(u12(K0, kend, nx, s));
+        RETCK(update(K0, kend, nx, s, 0));
+        // side: the columns left of the block and right of the next one
+        RETCK(swaps(K0, 0, np, K0, kend + nx, s2));
+        RETCK(u12(K0, kend + nx, rest, s2));
+        next_ready = false;
+        if (rest > 0) {
+            const int nx2 = rest < nb ? rest : nb;  // the block after next first
+            RETCK(update(K0, kend + nx, nx2, s2, 1));
+            HIPCK(hipEventRecord(ctx->ev_next, s2));
+            next_ready = true;
+            RETCK(update(K0, kend + nx + nx2, rest - nx2, s2, 1));
+        }
+        HIPCK(hipEventRecord(ctx->ev_join, s2));
+        par ^= 1;
+        pset = pset == 2 ? 0 : pset + 1;
     }
-    if (side_busy) HIPCK(hipStreamWaitEvent(s, ctx->ev_join, 0));
+    if (side_used) HIPCK(hipStreamWaitEvent(s, ctx->ev_join, 0));
     return MIXLU_OK;
 }
 
@@ -422,7 +462,7 @@ int factor_chol(hipStream_t s, void *work, const Layout &L, size_t woff, int tra
     T *W = at<T>(work, woff);
     T *diag = at<T>(work, L.tmp);
     int *status = at<int>(work, L.status);
-    if (nb % B || nb > 512) return MIXLU_ERR_NOT_IMPLEMENTED;
+    if (nb % B || nb > kMaxOuterBlock) return MIXLU_ERR_NOT_IMPLEMENTED;
     HIPCK(launch_iota(at<int>(work, L.perm), np, s));
     HIPCK(launch_iota(at<int>(work, L.ipiv), np, s));
     auto Wp = [&](int r, int c) { return W + (size_t)r * np + c; };
@@ -1472,6 +1512,7 @@ int mixlu_destroy(mixlu_ctx_t ctx) {
         (void)hipStreamDestroy(ctx->side);
         (void)hipEventDestroy(ctx->ev_fork);
         (void)hipEventDestroy(ctx->ev_join);
+        (void)hipEventDestroy(ctx->ev_next);
     }
     for (auto &q : ctx->prof.pending) {
         (void)hipEventDestroy(q.a);

@@ -26,6 +26,8 @@ constexpr int kSparseMaxRestart = 512;  // largest m_out / m_in of the sparse so
 constexpr int kColChunks = 64;   // row chunks of the column-statistics pass
 constexpr unsigned kSpinLimit = 1u << 23;  // polls before a device wait gives up
 constexpr int kKrylov = 30;         // flexible GMRES restart length
+constexpr int kMaxOuterBlock = 1024;  // widest outer block (pivots per wide row interchange)
+constexpr int kMovesInts = 4 + 4 * kMaxOuterBlock;  // one composed row-move list
 constexpr int kBatchedNmax = 512;   // largest order of a batched system
 constexpr int kBatchedSlots = 512;  // workgroups (and workspace slots) of a batched launch
 
@@ -294,6 +296,15 @@ hipError_t launch_row_swaps(const int *ipiv, int k0, int cnt, int npad, int *per
 // blocks of more pivots than this (with a moves buffer of 2 + 4 cnt ints)
 // compose once in a separate launch
 constexpr int kSwapsFused = 64;
+// The two halves of a wide interchange, for one composition applied to
+// several column ranges (possibly on different streams): the pivots
+// ipiv[k0 .. k0+cnt-1] composed into moves (and perm, when given) once, then
+// the rows of [c0, c1) minus [skip0, skip1) moved by that list.
+hipError_t launch_swaps_compose(const int *ipiv, int k0, int cnt, int npad, int *perm, int *moves,
+                                hipStream_t s);
+template <typename T>
+hipError_t launch_swaps_apply(T *W, int ldw, const int *moves, int cnt, int c0, int c1, int skip0,
+                              int skip1, hipStream_t s);
 template <typename T>
 hipError_t launch_trsm_diag(const T *Ldiag, int ldl, T *X, int ldx, int ncols, hipStream_t s);
 // C -= op(A) op(B) with K split over nsplit workgroup slices: partial

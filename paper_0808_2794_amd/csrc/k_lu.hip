@@ -551,8 +551,8 @@ __global__ __launch_bounds__(1024) void k_swaps_compose(const int *__restrict__ 
                                                         int *__restrict__ moves) {
     extern __shared__ int cur[];
     __shared__ int s_count;
-    __shared__ int s_pv[512];
-    __shared__ int s_dst[1024], s_src[1024];
+    __shared__ int s_pv[kMaxOuterBlock];
+    __shared__ int s_dst[2 * kMaxOuterBlock], s_src[2 * kMaxOuterBlock];
     const int m = npad - k0;
     for (int i = threadIdx.x; i < m; i += blockDim.x) cur[i] = i;
     for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
@@ -582,17 +582,24 @@ __global__ __launch_bounds__(1024) void k_swaps_compose(const int *__restrict__ 
         }
     }
     __syncthreads();
-    const int count = s_count;  // <= 2 cnt <= 1024 = blockDim.x
-    const int t = threadIdx.x;
-    int keep = 0;
-    if (t < count) {
-        moves[2 + 2 * t] = s_dst[t];
-        moves[3 + 2 * t] = s_src[t];
-        if (perm) keep = perm[s_src[t]];
+    const int count = s_count;  // <= 2 cnt <= 2 blockDim.x
+    int keep[2] = {0, 0};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int t = threadIdx.x + h * blockDim.x;
+        if (t < count) {
+            moves[2 + 2 * t] = s_dst[t];
+            moves[3 + 2 * t] = s_src[t];
+            if (perm) keep[h] = perm[s_src[t]];
+        }
     }
     __syncthreads();
-    if (perm && t < count) perm[s_dst[t]] = keep;
-    if (t == 0) moves[0] = count;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int t = threadIdx.x + h * blockDim.x;
+        if (perm && t < count) perm[s_dst[t]] = keep[h];
+    }
+    if (threadIdx.x == 0) moves[0] = count;
 }
 
 template <typename T, int CW>
@@ -627,7 +634,7 @@ hipError_t launch_row_swaps(const int *ipiv, int k0, int cnt, int npad, int *per
                             int c0, int c1, int skip0, int skip1, int *moves, hipStream_t s) {
     constexpr int CW = sizeof(T) == 4 ? 16 : 8;
     constexpr size_t kMaxLds = 152 * 1024;  // of the 160 KiB, leaving room for static LDS
-    if (cnt > 512) return hipErrorInvalidValue;
+    if (cnt > kMaxOuterBlock) return hipErrorInvalidValue;
     if (skip0 < c0) skip0 = c0;
     if (skip1 > c1) skip1 = c1;
     if (skip1 < skip0) skip1 = skip0;
@@ -639,12 +646,12 @@ hipError_t launch_row_swaps(const int *ipiv, int k0, int cnt, int npad, int *per
         // compose once, then apply in a second launch
         const size_t lds_c = (size_t)m * sizeof(int);
         const size_t lds_a = (size_t)2 * cnt * CW * sizeof(T);
-        if (lds_c > kMaxLds - 16 * 1024 || lds_a > kMaxLds) return hipErrorInvalidValue;
+        if (lds_c > kMaxLds - 24 * 1024 || lds_a > kMaxLds) return hipErrorInvalidValue;
         static bool attr2_done = false;
         if (!attr2_done) {
             hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_swaps_compose),
                                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                                               (int)(kMaxLds - 16 * 1024));
+                                               (int)(kMaxLds - 24 * 1024));
             if (e == hipSuccess)
                 e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rows_apply<T, CW>),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds);
@@ -674,6 +681,55 @@ hipError_t launch_row_swaps(const int *ipiv, int k0, int cnt, int npad, int *per
                                                           nleft, gap, ncols);
     return hipGetLastError();
 }
+hipError_t launch_swaps_compose(const int *ipiv, int k0, int cnt, int npad, int *perm, int *moves,
+                                hipStream_t s) {
+    constexpr size_t kMaxLds = 152 * 1024;
+    if (cnt > kMaxOuterBlock || cnt < 0 || k0 < 0 || k0 > npad) return hipErrorInvalidValue;
+    const size_t lds_c = (size_t)(npad - k0) * sizeof(int);
+    if (lds_c > kMaxLds - 24 * 1024) return hipErrorInvalidValue;
+    static bool attr_done = false;
+    if (!attr_done) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_swaps_compose),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)(kMaxLds - 24 * 1024));
+        if (e != hipSuccess) return e;
+        attr_done = true;
+    }
+    k_swaps_compose<<<dim3(1), dim3(1024), lds_c, s>>>(ipiv, k0, cnt, npad, perm, moves);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_swaps_apply(T *W, int ldw, const int *moves, int cnt, int c0, int c1, int skip0,
+                              int skip1, hipStream_t s) {
+    constexpr int CW = sizeof(T) == 4 ? 16 : 8;
+    constexpr size_t kMaxLds = 152 * 1024;
+    if (cnt > kMaxOuterBlock || cnt < 0) return hipErrorInvalidValue;
+    if (skip0 < c0) skip0 = c0;
+    if (skip1 > c1) skip1 = c1;
+    if (skip1 < skip0) skip1 = skip0;
+    const int nleft = skip0 - c0;
+    const int gap = skip1 - skip0;
+    const int ncols = (c1 - c0) - gap;
+    if (ncols <= 0) return hipSuccess;
+    const size_t lds_a = (size_t)2 * cnt * CW * sizeof(T);
+    if (lds_a > kMaxLds) return hipErrorInvalidValue;
+    static bool attr_done = false;
+    if (!attr_done) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rows_apply<T, CW>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds);
+        if (e != hipSuccess) return e;
+        attr_done = true;
+    }
+    k_rows_apply<T, CW><<<dim3((ncols + CW - 1) / CW), dim3(256), lds_a, s>>>(W, ldw, moves, c0,
+                                                                            nleft, gap, ncols);
+    return hipGetLastError();
+}
+template hipError_t launch_swaps_apply<float>(float *, int, const int *, int, int, int, int, int,
+                                              hipStream_t);
+template hipError_t launch_swaps_apply<double>(double *, int, const int *, int, int, int, int, int,
+                                               hipStream_t);
+
 template hipError_t launch_row_swaps<float>(const int *, int, int, int, int *, float *, int, int,
                                             int, int, int, int *, hipStream_t);
 template hipError_t launch_row_swaps<double>(const int *, int, int, int, int *, double *, int, int,
