@@ -545,6 +545,30 @@ int read_status(mixlu_ctx_s *ctx, const Layout &L, void *work, int st[ST_COUNT],
     return MIXLU_OK;
 }
 
+// Norms, power-of-two scales and conversion of the n x n FP64 input into the
+// working factor at woff, with equilibration or for Cholesky (three passes
+// over A: row statistics, column statistics with the row scales, conversion).
+template <typename T>
+int stats_and_convert(hipStream_t s, void *work, const Layout &L, size_t woff, const double *A,
+                      int lda, int equil) {
+    const int n = L.n, np = L.npad;
+    double *tmp = at<double>(work, L.tmp);
+    double *R = at<double>(work, L.R), *C = at<double>(work, L.C);
+    double *norms = at<double>(work, L.norms);
+    int *status = at<int>(work, L.status);
+    HIPCK(launch_row_stats(A, lda, n, tmp, tmp + np, s));
+    if (L.kind == 1) {
+        // ||A||_inf from the row sums; symmetric scaling keeps W symmetric
+        HIPCK(launch_finish_rows(n, np, tmp, tmp + np, R, 0, norms, s));
+        HIPCK(launch_sym_scale(A, lda, n, np, R, C, equil, s));
+    } else {
+        HIPCK(launch_finish_rows(n, np, tmp, tmp + np, R, equil, norms, s));
+        HIPCK(launch_col_stats(A, lda, n, np, R, tmp + 2 * (size_t)np, C, equil, norms, s));
+    }
+    HIPCK(launch_convert<T>(A, lda, n, np, R, C, at<T>(work, woff), np, status, s));
+    return MIXLU_OK;
+}
+
 // Norms, scales, conversion and LU of the n x n FP64 input into the working
 // factor at woff (FP32 or FP64 storage).
 template <typename T>
@@ -557,16 +581,13 @@ int convert_and_factor(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t wof
     double *norms = at<double>(work, L.norms);
     int *status = at<int>(work, L.status);
     HIPCK(init_status(s, status));
-    HIPCK(launch_row_stats(A, lda, n, tmp, tmp + np, s));
-    if (L.kind == 1) {
-        // ||A||_inf from the row sums; symmetric scaling keeps W symmetric
-        HIPCK(launch_finish_rows(n, np, tmp, tmp + np, R, 0, norms, s));
-        HIPCK(launch_sym_scale(A, lda, n, np, R, C, equil, s));
+    if (L.kind == 0 && !equil) {
+        // no scaling: conversion and both norms in one pass over A
+        HIPCK(launch_convert_stats<T>(A, lda, n, np, at<T>(work, woff), np, tmp, R, C, norms,
+                                      status, s));
     } else {
-        HIPCK(launch_finish_rows(n, np, tmp, tmp + np, R, equil, norms, s));
-        HIPCK(launch_col_stats(A, lda, n, np, R, tmp + 2 * (size_t)np, C, equil, norms, s));
+        RETCK(stats_and_convert<T>(s, work, L, woff, A, lda, equil));
     }
-    HIPCK(launch_convert<T>(A, lda, n, np, R, C, at<T>(work, woff), np, status, s));
     if (L.kind == 1) RETCK(factor_chol<T>(s, work, L, woff, trail_prec));
     else RETCK(factor_lu<T>(ctx, work, L, woff, trail_prec));
     // the solves apply the inverses of the factors' 64 x 64 diagonal blocks

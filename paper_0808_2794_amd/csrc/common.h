@@ -283,6 +283,12 @@ hipError_t launch_col_stats(const double *A, int lda, int n, int npad, const dou
 template <typename Tw>
 hipError_t launch_convert(const double *A, int lda, int n, int npad, const double *R,
                           const double *C, Tw *W, int ldw, int *status, hipStream_t s);
+// Without equilibration: conversion, ||M||_inf and ||M||_1 in one pass over
+// A (tmp: (2 kColChunks + 2) npad doubles), R = C = 1.
+template <typename Tw>
+hipError_t launch_convert_stats(const double *A, int lda, int n, int npad, Tw *W, int ldw,
+                                double *tmp, double *R, double *C, double *norms, int *status,
+                                hipStream_t s);
 
 // a3: factorization kernels (k_lu.hip)
 template <typename T>
