@@ -155,6 +155,56 @@ def roofline(kstats, prec, steps, workload):
     return rec
 
 
+def stored_record(workload, kernel_class, key):
+    """A stored rocprofv3 counter record (profiles/traffic.json), only if it
+    was taken on the current sources of the files that define the kernel."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f).get(workload, {}).get(kernel_class)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("source_digest") != source_digest(rec.get("sources")):
+        return None
+    return rec.get(key)
+
+
+def class_measures(kst, prec, steps, workload, columns):
+    """Per-class figures of the hot path: the panel's time per eliminated
+    column (latency-bound), the trailing update's FLOP rate and MFMA
+    utilization (from the timed flops, and from the MfmaUtil counter when a
+    current record exists), and the algorithmic GB/s of the triangular solves
+    and of the FP64 residual (with the counter-measured HBM bytes beside them
+    when recorded)."""
+    out = {}
+    for name in ("panel_getf2", "panel_potf2"):
+        st = kst.get(name)
+        if st and st["launches"] and columns:
+            out["panel_us_per_column"] = st["ms"] / steps / columns * 1e3
+    st = kst.get("trailing_update")
+    if st and st["ms"] > 0:
+        tf = st["flops"] / (st["ms"] / 1e3) / 1e12
+        out["trailing_tflops"] = tf
+        out["mfma_util_timed"] = tf / PEAK_MFMA_TFS[prec]
+        cnt = stored_record(workload, "trailing_update", "mfma_util")
+        if cnt is not None:
+            out["mfma_util"] = cnt
+            out["mfma_util_source"] = "rocprofv3 MfmaUtil, duration-weighted over the update kernels"
+        else:
+            out["mfma_util"] = out["mfma_util_timed"]
+            out["mfma_util_source"] = "timed flops / peak (no current counter record)"
+    for name, key in (("trsv", "trsv"), ("residual", "residual")):
+        st = kst.get(name)
+        if st and st["ms"] > 0 and st["launches"]:
+            sec = st["ms"] / 1e3
+            out[f"{key}_gbs"] = st["bytes"] / sec / 1e9
+            out[f"{key}_hbm_frac"] = out[f"{key}_gbs"] / PEAK_HBM_GBS
+            tb = stored_record(workload, name, "bytes_per_launch")
+            if tb is not None:
+                out[f"{key}_traffic_gbs"] = tb * st["launches"] / sec / 1e9
+    return out
+
+
 def kernel_table(kst, steps):
     return {k: {"ms_per_step": v["ms"] / steps, "launches_per_step": v["launches"] / steps}
             for k, v in kst.items() if v["launches"]}
@@ -242,6 +292,7 @@ def run_dense(args, prec):
     solver.close()
     rep = res.report
     return ms, kst, cpu, comp, {
+        "columns": n,
         "config": {"workload": (f"dense_nonsym_prescribed_cond_n{n}_kappa{kappa:g}_nrhs1"
                                 if args.matrix == "prescribed" else f"dense_nonsym_uniform_n{n}_nrhs1"),
                    "n": n, "kappa": kappa, "nrhs": 1, "seed": seed, "factor_precision": prec,
@@ -307,6 +358,7 @@ def run_spd(args, prec):
     solver.close()
     rep = res.report
     return ms, kst, cpu, comp, {
+        "columns": n,
         "config": {"workload": f"dense_spd_n{n}_kappa{kappa:g}_nrhs{nrhs}", "n": n, "kappa": kappa,
                    "nrhs": nrhs, "seed": seed, "factor_precision": prec, "factorization": "cholesky",
                    "refinement": "fp64"},
@@ -543,6 +595,7 @@ def main():
         "solve": extra["solve"],
         "comparators": comp,
         "kernels": kernel_table(kst, args.steps),
+        **class_measures(kst, prec, args.steps, args.workload, extra.get("columns")),
         "roofline": rl,
         "cpu_baseline": cpu,
     }
