@@ -100,16 +100,20 @@ typedef struct {
                          kappa_1 eps_s >= 1 skip the refinement and take
                          the FP64 path at once (report.iter = -5).  0
                          (default): no estimate.  mixlu_dxgesv/dxposv.     */
-    int reserved[4];
+    int restart;      /* flexible GMRES restart length (MIXLU_REFINE_FGMRES):
+                         0 = default 30, at most 128 (larger values use 128) */
+    int reserved[3];
 } mixlu_opts;
 
 /* Refinement after the low-precision factorization.  CLASSIC is the
    stationary iteration of Algorithm 1.  FGMRES is the flexible GMRES outer
    loop of Algorithm 2, with one application of the low-precision LU solve
    as the (right) preconditioner in place of the inner single-precision
-   GMRES: FP64 Arnoldi, restarts every 30 steps, the stopping test of
-   Section 3 on the true FP64 residual at every restart; `itermax` and
-   `stall` then count restarts, and report.iter counts preconditioner
+   GMRES: FP64 Arnoldi, restarts every `restart` steps (default 30), the
+   stopping test of Section 3 on the true FP64 residual at every restart;
+   `itermax` counts restart cycles, a cycle that cuts the true residual by
+   less than 1% makes no progress and two such cycles in a row end the
+   iteration (`stall` is not used), and report.iter counts preconditioner
    applications.  It keeps converging where kappa eps_s approaches or
    exceeds 1 (BF16/FP16/FP8 factors), where CLASSIC stalls.  FGMRES applies
    to one right-hand side of op(A) = A; other calls use CLASSIC. */
@@ -456,6 +460,14 @@ int mixlu_profile_enable(mixlu_ctx_t ctx, int on);
 /* Copies up to max class records into out (host) and the number of classes
    into *count; synchronizes the stream. */
 int mixlu_profile_read(mixlu_ctx_t ctx, mixlu_kstat *out, int max, int *count);
+
+/* The true-residual norms ||b - A x||_inf (largest over the right-hand
+   sides) that the last mixlu_refine / mixlu_dxgesv / mixlu_dxposv call on
+   this context evaluated, in order: one per iteration of the stationary
+   refinement, one per restart cycle of FGMRES, then those of the FP64
+   fallback if it ran.  h (host) receives the first min(count, max); *count
+   the number recorded.  A diagnostic: tells slow convergence from a stall. */
+int mixlu_refine_history(mixlu_ctx_t ctx, double *h, int max, int *count);
 
 #ifdef __cplusplus
 }

@@ -53,6 +53,7 @@ struct mixlu_ctx_s {
                                      {16, 128, 1}};  // by mixlu_prec; FP64 last
     int btuned[5] = {0, 0, 0, 0, 0};
     Prof prof;
+    std::vector<double> hist;  // true-residual norms of the last refinement, in order
 };
 
 namespace {
@@ -210,7 +211,7 @@ size_t mixlu::plan_layout(Layout &L, int op, int prec, int n, int nrhs, const mi
     L.tmp = take((size_t)(2 * kColChunks + 2) * np * 8);
     L.status = take(ST_COUNT * 4);
     L.norms = take((size_t)(4 + 3 * L.nrhs) * 8);
-    L.krylov = take(((size_t)(2 * kKrylov + 2) * np + 4 * kKrylov + 16) * 8);
+    L.krylov = take(((size_t)(2 * kKrylovMax + 2) * np + 4 * kKrylovMax + 16) * 8);
     L.dinv = take(2 * np * kTrsvBS * (L.prec == MIXLU_FP64 ? 8 : 4));
     L.dinv64 = L.fallback ? take(2 * np * kTrsvBS * 8) : 0;
     L.total = off;
@@ -266,7 +267,7 @@ Layout layout_of(const mixlu_factor *F) {
     L.krylov = align_up(L.norms + (size_t)(4 + 3 * L.nrhs) * 8, 256);
     // then the inverse diagonal blocks (same rule as plan_layout)
     const size_t np = (size_t)L.npad;
-    L.dinv = align_up(L.krylov + ((2 * (size_t)kKrylov + 2) * np + 4 * kKrylov + 16) * 8, 256);
+    L.dinv = align_up(L.krylov + ((2 * (size_t)kKrylovMax + 2) * np + 4 * kKrylovMax + 16) * 8, 256);
     L.dinv64 = L.fallback
                    ? align_up(L.dinv + 2 * np * kTrsvBS * (L.prec == MIXLU_FP64 ? 8 : 4), 256)
                    : 0;
@@ -676,7 +677,7 @@ int refine_loop(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t woff, cons
     if (nrhs > 1) {
         const bool w64_free = L.W64 && woff != L.W64;
         split_buf = at<double>(work, w64_free ? L.W64 : L.krylov);
-        const size_t cap = w64_free ? (size_t)L.npad * L.npad : (size_t)(2 * kKrylov + 2) * L.npad;
+        const size_t cap = w64_free ? (size_t)L.npad * L.npad : (size_t)(2 * kKrylovMax + 2) * L.npad;
         const size_t per = (size_t)n * nrhs;
         const size_t smax = 1 + cap / per;
         const int want = n / 512 < 16 ? (n / 512 > 1 ? n / 512 : 1) : 16;
@@ -709,6 +710,11 @@ int refine_loop(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t woff, cons
         if (stl[ST_TIMEOUT]) return MIXLU_ERR_DEVICE_TIMEOUT;
         const double *rn = ctx->hbuf;
         const double *xn = ctx->hbuf + nrhs;
+        {
+            double rmax = 0.0;
+            for (int c = 0; c < nrhs; ++c) rmax = (rn[c] > rmax || rn[c] != rn[c]) ? rn[c] : rmax;
+            ctx->hist.push_back(rmax);
+        }
         bool all_ok = true, nonfinite = false, stalled = false;
         res.rnorm = 0.0;
         res.xnorm = 0.0;
@@ -751,18 +757,20 @@ int refine_loop(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t woff, cons
 // application of the low-precision LU solve M = (LU)^{-1} P as the
 // preconditioner in place of the inner single-precision GMRES): FP64
 // Arnoldi with classical Gram-Schmidt applied twice, Givens rotations on the
-// host, restarts every kKrylov steps.  At each restart the true residual is
+// host, restarts every o.restart steps (default kKrylov).  At each restart the true residual is
 // formed in FP64 and the stopping test of Section 3 decides; within a cycle
 // the rotated residual norm ends the cycle early once it is below the
 // threshold.  One right-hand side, A not transposed.  res.iters counts
 // preconditioner applications; failure codes as for refine_loop, with the
-// cycle count playing the role of the iteration count (itermax cycles).
+// cycle count playing the role of the iteration count (itermax cycles) and
+// a stall being two cycles in a row that cut the true residual by < 1%.
 template <typename Tw>
 int fgmres_loop(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t woff, const double *A,
                 int lda, const double *B, double *X, double anorm, const mixlu_opts &o,
                 LoopResult &res) {
     hipStream_t s = ctx->stream;
-    const int n = L.n, np = L.npad, m = kKrylov;
+    const int n = L.n, np = L.npad;
+    const int m = o.restart > 0 ? (o.restart < kKrylovMax ? o.restart : kKrylovMax) : kKrylov;
     double *Rv = at<double>(work, L.vec_r);
     double *norms = at<double>(work, L.norms);
     double *rnorm = norms + 4, *xnorm = norms + 4 + L.nrhs;
@@ -799,6 +807,7 @@ int fgmres_loop(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t woff, cons
         std::memcpy(stl, hb + 4, ST_COUNT * 4);
         if (stl[ST_TIMEOUT]) return MIXLU_ERR_DEVICE_TIMEOUT;
         const double r = hb[0], xn = hb[1], beta = std::sqrt(hb[2]);
+        ctx->hist.push_back(r);
         res.rnorm = r;
         res.xnorm = xn;
         res.berr = anorm * xn > 0 ? r / (anorm * xn) : (r > 0 ? INFINITY : 0.0);
@@ -813,13 +822,16 @@ int fgmres_loop(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t woff, cons
             res.iters = -4;
             return MIXLU_OK;
         }
+        // a restart cycle that does not cut the true residual by 1% made no
+        // progress; two such cycles in a row end the iteration (a slowly
+        // converging solve keeps going until itermax cycles)
         if (cyc >= 1 && prev > 0) {
-            const double rho = r / prev;
-            if ((cyc >= 2 && rho >= o.stall && ratio_prev >= o.stall) || (cyc >= 3 && rho >= 1.0)) {
+            const bool none = !(r < 0.99 * prev);
+            if (none && ratio_prev >= 1.0) {
                 res.iters = -4;
                 return MIXLU_OK;
             }
-            ratio_prev = rho;
+            ratio_prev = none ? 1.0 : 0.0;
         }
         prev = r;
         if (cyc == o.itermax) {
@@ -1079,6 +1091,7 @@ int condest_impl(mixlu_ctx_s *ctx, const mixlu_factor *F, double *kappa1) {
 int dx_entry(mixlu_ctx_s *ctx, int op, int prec, int n, int nrhs, const double *A, int lda,
              const double *B, int ldb, double *X, int ldx, void *work, size_t lwork,
              const mixlu_opts *o, mixlu_report *rep) {
+    ctx->hist.clear();
     if (!prec_valid(prec)) return -2;
     const mixlu_opts op_ = opts_or_default(o);
     if (op_.layout != MIXLU_ROW_MAJOR && op_.layout != MIXLU_COL_MAJOR) return -13;
@@ -1471,6 +1484,7 @@ void mixlu_default_opts(mixlu_opts *o) {
     o->layout = MIXLU_ROW_MAJOR;
     o->stall = 0.9;
     o->refine = MIXLU_REFINE_CLASSIC;
+    o->restart = 0;
 }
 
 // ---------------------------------------------------------------------
@@ -1604,6 +1618,7 @@ int mixlu_refine(mixlu_ctx_t ctx, mixlu_factor *F, int trans, int nrhs, const do
                  mixlu_report *rep) {
     if (!ctx) return -1;
     ProfCall pc_(ctx);
+    ctx->hist.clear();
     if (!F || !F->work) return -2;
     if (trans != 0 && trans != 1) return -3;
     if (nrhs < 0 || nrhs > F->nrhs_max) return -4;
@@ -2005,6 +2020,16 @@ int mixlu_profile_read(mixlu_ctx_t ctx, mixlu_kstat *out, int max, int *count) {
         out[i].bytes = ctx->prof.acc[i].bytes;
     }
     *count = PC_COUNT;
+    return MIXLU_OK;
+}
+
+int mixlu_refine_history(mixlu_ctx_t ctx, double *h, int max, int *count) {
+    if (!ctx) return -1;
+    if (max < 0 || (max > 0 && !h)) return -3;
+    if (!count) return -4;
+    const int c = (int)ctx->hist.size();
+    *count = c;
+    for (int i = 0; i < c && i < max; ++i) h[i] = ctx->hist[i];
     return MIXLU_OK;
 }
 

@@ -25,7 +25,8 @@ constexpr int kTrsvNRT = 8;        // right-hand sides per chained-solve launch
 constexpr int kSparseMaxRestart = 512;  // largest m_out / m_in of the sparse solver
 constexpr int kColChunks = 64;   // row chunks of the column-statistics pass
 constexpr unsigned kSpinLimit = 1u << 23;  // polls before a device wait gives up
-constexpr int kKrylov = 30;         // flexible GMRES restart length
+constexpr int kKrylov = 30;         // default flexible GMRES restart length
+constexpr int kKrylovMax = 128;     // longest restart (the Krylov area's capacity)
 constexpr int kMaxOuterBlock = 1024;  // widest outer block (pivots per wide row interchange)
 constexpr int kMovesInts = 4 + 4 * kMaxOuterBlock;  // one composed row-move list
 constexpr int kBatchedNmax = 512;   // largest order of a batched system
@@ -253,7 +254,7 @@ struct Layout {
     size_t vec_r;    // double[npad * nrhs] residual
     size_t vec_y;    // double[npad * nrhs] solve vector (float or double view)
     size_t vec_z;    // double[npad * nrhs] second solve vector (blocked solves)
-    size_t krylov;   // flexible GMRES: V (kKrylov + 1 vectors), Z (kKrylov), h, y (doubles)
+    size_t krylov;   // flexible GMRES: V (kKrylovMax + 1 vectors), Z (kKrylovMax), h, y (doubles)
     size_t xbuf;     // panel exchange words
     size_t ybuf;     // chained-solve exchange words + tickets
     size_t moves;    // int[2 * (2 * nb + 64) + 4] row-move lists

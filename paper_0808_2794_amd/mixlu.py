@@ -31,7 +31,8 @@ class mixlu_opts(ctypes.Structure):
     _fields_ = [("itermax", ctypes.c_int), ("equilibrate", ctypes.c_int),
                 ("fallback", ctypes.c_int), ("nb", ctypes.c_int), ("layout", ctypes.c_int),
                 ("stall", ctypes.c_double), ("refine", ctypes.c_int),
-                ("condest", ctypes.c_int), ("reserved", ctypes.c_int * 4)]
+                ("condest", ctypes.c_int), ("restart", ctypes.c_int),
+                ("reserved", ctypes.c_int * 3)]
 
 
 class mixlu_report(ctypes.Structure):
@@ -82,7 +83,7 @@ EXPORTS = ("mixlu_status_string", "mixlu_default_opts", "mixlu_create", "mixlu_d
            "mixlu_dxgesv_batched", "mixlu_dxgesv_batched_noalloc", "mixlu_profile_enable",
            "mixlu_profile_read", "mixlu_sgesv", "mixlu_report_read", "mixlu_batched_tune", "mixlu_batched_get_tiles",
            "mixlu_batched_set_tiles", "mixlu_condest", "mixlu_sparse_workspace_size",
-           "mixlu_sparse_fgmres", "mixlu_gemm_update")
+           "mixlu_sparse_fgmres", "mixlu_gemm_update", "mixlu_refine_history")
 
 _lib = None
 
@@ -115,6 +116,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "mixlu_batched_workspace_size": ([P, I, I, I, P, P], I),
         "mixlu_dxgesv_batched": ([P, I, I, P, P, P, P, P, I, P, S, P, P], I),
         "mixlu_dxgesv_batched_noalloc": ([P, I, I, P, P, P, P, P, I, P, P], I),
+        "mixlu_refine_history": ([P, P, I, P], I),
         "mixlu_profile_enable": ([P, I], I),
         "mixlu_profile_read": ([P, P, I, P], I),
         "mixlu_sgesv": ([P, I, I, P, I, P, I, P, I, P, S, P], I),
@@ -375,6 +377,16 @@ def mixlu_dxgesv_batched(ctx, prec: int, d_n, d_A, d_lda, d_B, d_X, nrhs: int, w
                                       _p(d_X), nrhs, _p(work), work.numel() * work.element_size(),
                                       None if opts is None else ctypes.byref(opts), _p(d_reps)),
           "mixlu_dxgesv_batched")
+
+
+def mixlu_refine_history(ctx) -> list:
+    """True-residual norms evaluated by the last refinement on ctx, in order."""
+    cnt = ctypes.c_int()
+    check(load().mixlu_refine_history(ctx, None, 0, ctypes.byref(cnt)), "mixlu_refine_history")
+    buf = (ctypes.c_double * max(cnt.value, 1))()
+    check(load().mixlu_refine_history(ctx, buf, cnt.value, ctypes.byref(cnt)),
+          "mixlu_refine_history")
+    return list(buf[:cnt.value])
 
 
 def mixlu_dxgesv_batched_noalloc(ctx, prec: int, d_n, d_A, d_lda, d_B, d_X, nrhs: int, d_reps,

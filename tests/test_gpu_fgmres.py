@@ -87,3 +87,84 @@ def test_fgmres_multi_rhs_uses_classic(solver):
     ref = O.gesv_ir(A, b)
     m = O.metrics(A, r.x.cpu().numpy(), b, x_ref=ref.x)
     assert m["passes"] and r.report["converged"]
+
+
+def test_history_matches_report(solver):
+    """The residual history of a stationary refinement has one entry per
+    iteration (the corrections plus the final test), ending at the reported
+    residual; FGMRES records one entry per restart cycle."""
+    from paper_0808_2794_amd import mixlu
+
+    n = 500
+    A, b, _ = gen.prescribed_cond_system(n, 1e3, 85)
+    _say("history classic fp32")
+    r = solver.dxgesv(_dev(A), _dev(b), "fp32")
+    h = mixlu.mixlu_refine_history(solver.ctx)
+    assert r.report["converged"] and r.report["prec"] == "fp32", r.report
+    assert len(h) == r.report["iter"] + 1 and h[-1] == r.report["rnorm"], (h, r.report)
+    _say("history fgmres fp16")
+    o = mixlu.default_opts(refine=mixlu.REFINE_FGMRES)
+    o.restart = 8
+    r = solver.dxgesv(_dev(A), _dev(b), "fp16", o)
+    h = mixlu.mixlu_refine_history(solver.ctx)
+    assert r.report["converged"] and r.report["prec"] == "fp16", r.report
+    assert h[-1] == r.report["rnorm"] and len(h) >= 2, (h, r.report)
+    # at most `restart` preconditioner applications per completed cycle
+    assert r.report["iter"] <= 8 * (len(h) - 1), (h, r.report)
+
+
+@pytest.mark.parametrize("prec,kappa,seed", [("fp16", 1e3, 231), ("bf16", 1e2, 232)])
+def test_fgmres_n8192(solver, prec, kappa, seed):
+    """Benchmarked size, kappa eps_s near 1/2: FGMRES finishes in the low
+    precision (no fallback), the answer meets the stopping rule with the
+    residual recomputed on the CPU and agrees with the oracle's FP64 solve."""
+    import torch
+
+    from paper_0808_2794_amd import mixlu
+
+    n = 8192
+    _say(f"fgmres n={n} {prec} kappa={kappa:g}: generate")
+    Ad, bd, x_true = gen.prescribed_cond_system(n, kappa, seed, backend="torch", device="cuda")
+    _say("solve")
+    r = solver.dxgesv(Ad, bd, prec, refine=mixlu.REFINE_FGMRES)
+    torch.cuda.synchronize()
+    h = mixlu.mixlu_refine_history(solver.ctx)
+    _say(f"  report {r.report} history {h}")
+    assert r.report["converged"] and r.report["prec"] == prec, (r.report, h)
+    A, b, x = Ad.cpu().numpy(), bd.cpu().numpy(), r.x.cpu().numpy()
+    del Ad, bd
+    _say("oracle")
+    ref = O.gesv_ir(A, b)
+    m = O.metrics(A, x, b, x_ref=ref.x, x_true=x_true)
+    assert m["passes"], m["rnorm"]
+    assert float(np.max(m["fwd_ref"])) <= 1e-12 * kappa, m["fwd_ref"]
+
+
+def test_fgmres_no_progress_ends_in_fallback(solver):
+    """kappa eps_s = 5 (FP16 operands, kappa = 1e4, n = 4096): the restart
+    cycles stop cutting the residual; two cycles in a row with less than 1%
+    progress end the iteration well before itermax, and the FP64 fallback
+    returns a certified answer."""
+    import torch
+
+    from paper_0808_2794_amd import mixlu
+
+    n = 4096
+    _say(f"fgmres stall n={n} fp16 kappa=1e4")
+    Ad, bd, x_true = gen.prescribed_cond_system(n, 1e4, 233, backend="torch", device="cuda")
+    o = mixlu.default_opts(refine=mixlu.REFINE_FGMRES)
+    o.itermax = 30
+    r = solver.dxgesv(Ad, bd, "fp16", o)
+    torch.cuda.synchronize()
+    h = mixlu.mixlu_refine_history(solver.ctx)
+    _say(f"  report {r.report} history {h}")
+    if r.report["prec"] == "fp16":  # converged after all: must then be certified
+        assert r.report["converged"], r.report
+    else:
+        assert r.report["prec"] == "fp64" and r.report["iter"] == -4 and r.report["converged"]
+        lp = h[:-(r.report["fallback_iter"] + 1)]  # the FGMRES cycles
+        assert 3 <= len(lp) < 30, h
+        assert not (lp[-1] < 0.99 * lp[-2]) and not (lp[-2] < 0.99 * lp[-3]), lp
+    x = r.x.cpu().numpy()
+    fwd = np.abs(x - x_true).max() / np.abs(x_true).max()
+    assert fwd <= 1e-12 * 1e4, fwd
