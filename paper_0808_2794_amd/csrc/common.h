@@ -21,6 +21,7 @@ constexpr int kPanelBD = 32;       // panel width, FP64 factors
 constexpr int kXbufWords = 2 * (kPanelMaxWG * (4 + 64) + 64);  // panel exchange words
 constexpr int kXcdStride = 8;      // workgroups are dealt round-robin to 8 XCDs
 constexpr int kTrsvBS = 64;        // rows per block of the chained solves
+constexpr int kTrsvPrefetch = 4;   // tile rows requested ahead in the chained solves
 constexpr int kTrsvNRT = 8;        // right-hand sides per chained-solve launch
 constexpr int kSparseMaxRestart = 512;  // largest m_out / m_in of the sparse solver
 constexpr int kColChunks = 64;   // row chunks of the column-statistics pass

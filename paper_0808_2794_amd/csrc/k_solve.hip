@@ -171,51 +171,72 @@ __global__ __launch_bounds__(256) void k_trsv(int upper, const T *__restrict__ W
     }
 
     const int nsteps = upper ? nblk - 1 - b : b;
+    // tile rows of the next PF steps are requested ahead (they depend on
+    // nothing), so a step costs the wait for its solution block, not a
+    // memory latency of its own
+    constexpr int PF = kTrsvPrefetch;
+    T lv[PF][16];
+    auto request = [&](int st, T(&dst)[16]) {
+        if (st < nsteps) {
+            const T *lrow = tile_ptr(upper ? nblk - 1 - st : st);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) dst[e] = TRANS ? lrow[e * estride] : lrow[e];
+        }
+    };
+    sfor<0, PF>([&](auto dc) { request(decltype(dc)::value, lv[decltype(dc)::value]); });
     int par = 0;
-    for (int st = 0; st < nsteps; ++st, par ^= 1) {
-        const int j = upper ? nblk - 1 - st : st;
-        // the tile row and the solution words of block j, all requested
-        // before any wait
-        T lv[16];
-        {
-            const T *lrow = tile_ptr(j);
+    bool stop = false;  // uniform: a bounded wait gave up
+    for (int st0 = 0; st0 < nsteps; st0 += PF) {
+        sfor<0, PF>([&](auto dc) {
+            constexpr int d = decltype(dc)::value;
+            const int st = st0 + d;
+            if (st >= nsteps || stop) return;  // uniform
+            const int j = upper ? nblk - 1 - st : st;
+            // the solution words of block j, requested before the next tile
+            unsigned long long wv[WPT];
 #pragma unroll
-            for (int e = 0; e < 16; ++e) lv[e] = TRANS ? lrow[e * estride] : lrow[e];
-        }
-        unsigned long long wv[WPT];
-#pragma unroll
-        for (int p = 0; p < WPT; ++p) {
-            const int t = tid + p * 256;
-            wv[p] = 0ull;
-            if (t < wblk) {
-                const int i = t / (nrhs * PWV), rr = t - i * (nrhs * PWV);
-                wv[p] = xload(yx + ((size_t)(j * BS + i) * NRT) * PWV + rr);
-            }
-        }
-        bool bad = false;
-#pragma unroll
-        for (int p = 0; p < WPT; ++p) {
-            const int t = tid + p * 256;
-            if (t < wblk) {
-                unsigned v = (unsigned)wv[p];
-                if ((unsigned)(wv[p] >> 32) != 1u && !bad) {
+            for (int p = 0; p < WPT; ++p) {
+                const int t = tid + p * 256;
+                wv[p] = 0ull;
+                if (t < wblk) {
                     const int i = t / (nrhs * PWV), rr = t - i * (nrhs * PWV);
-                    v = spin_tag(yx + ((size_t)(j * BS + i) * NRT) * PWV + rr, 1u,
-                                 &status[ST_TIMEOUT], bad);
+                    wv[p] = xload(yx + ((size_t)(j * BS + i) * NRT) * PWV + rr);
                 }
-                swords[par][t] = v;
             }
-        }
-        if (bad) s_bad = 1;
-        __syncthreads();
-        if (s_bad) return;
+            T cur[16];
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const int i = q * 16 + e;
+            for (int e = 0; e < 16; ++e) cur[e] = lv[d][e];
+            request(st + PF, lv[d]);
+            bool bad = false;
 #pragma unroll
-            for (int c = 0; c < NRT; ++c)
-                if (c < nrhs) acc[c] += lv[e] * Words<T>::make(&swords[par][(i * nrhs + c) * PWV]);
-        }
+            for (int p = 0; p < WPT; ++p) {
+                const int t = tid + p * 256;
+                if (t < wblk) {
+                    unsigned v = (unsigned)wv[p];
+                    if ((unsigned)(wv[p] >> 32) != 1u && !bad) {
+                        const int i = t / (nrhs * PWV), rr = t - i * (nrhs * PWV);
+                        v = spin_tag(yx + ((size_t)(j * BS + i) * NRT) * PWV + rr, 1u,
+                                     &status[ST_TIMEOUT], bad);
+                    }
+                    swords[par][t] = v;
+                }
+            }
+            if (bad) s_bad = 1;
+            __syncthreads();
+            if (s_bad) {
+                stop = true;
+                return;
+            }
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int i = q * 16 + e;
+#pragma unroll
+                for (int c = 0; c < NRT; ++c)
+                    if (c < nrhs) acc[c] += cur[e] * Words<T>::make(&swords[par][(i * nrhs + c) * PWV]);
+            }
+            par ^= 1;
+        });
+        if (stop) return;
     }
     // combine the four k-quarters of each row
 #pragma unroll
