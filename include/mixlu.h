@@ -191,7 +191,10 @@ typedef struct {
     int equilibrated;  /* 1 when R, C scaling was applied                  */
     int lowp_status;   /* 0 ok; -2 conversion overflow; -3 breakdown;
                           -1 the FP64 fallback factor that mixlu_refine
-                          left in the workspace is singular (X undefined) */
+                          left in the workspace is singular (X undefined);
+                          MIXLU_FACTOR_PENDING after an asynchronous
+                          factorization, until mixlu_refine reads the
+                          outcome from the device                         */
     int nrhs_max;      /* most right-hand sides one solve may have: what
                           the workspace given to the factorization holds  */
     void *work;        /* the workspace (device)                           */
@@ -223,6 +226,28 @@ int mixlu_getrf(mixlu_ctx_t ctx, int prec, int n, const double *A, int lda,
 int mixlu_potrf(mixlu_ctx_t ctx, int prec, int n, const double *A, int lda,
                 void *work, size_t lwork, const mixlu_opts *o,
                 mixlu_factor *F, int *info);
+
+/* Stream-ordered forms of mixlu_getrf and mixlu_potrf: the same
+   conversion and factorization, enqueued on the context's stream without
+   any synchronization or host read-back, so that a caller can overlap them
+   with its own work or capture them in a HIP graph (with the context bound
+   to the capturing stream by mixlu_set_stream; the context's second stream
+   joins the capture through events and is joined back before the call
+   returns).  The outcome is written to *d_info (device int) when the
+   factorization ends: 0; k+1 for an exact zero pivot in column k of an FP64
+   factor; -2 (overflow or non-finite value on conversion) or -3 (zero,
+   non-finite or, for Cholesky, non-positive pivot) for a low-precision
+   factor; -100 when a bounded cross-workgroup wait gave up.  *F (host) is
+   filled at once, with F->lowp_status = MIXLU_FACTOR_PENDING; mixlu_getrs
+   may follow on the same stream, and mixlu_refine reads the outcome itself.
+   Argument errors as for mixlu_getrf (-10: d_info is NULL). */
+#define MIXLU_FACTOR_PENDING 1
+int mixlu_getrf_async(mixlu_ctx_t ctx, int prec, int n, const double *A, int lda,
+                      void *work, size_t lwork, const mixlu_opts *o,
+                      mixlu_factor *F, int *d_info);
+int mixlu_potrf_async(mixlu_ctx_t ctx, int prec, int n, const double *A, int lda,
+                      void *work, size_t lwork, const mixlu_opts *o,
+                      mixlu_factor *F, int *d_info);
 
 /* Low-precision solve only (Algorithm 1 steps 2-3): X = op(A)^{-1} B with
    the stored factors, computed in the factor's precision and promoted to

@@ -953,16 +953,25 @@ int fp64_path(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t woff, const 
 
 // Conversion and factorization of A into the workspace for op GESV (LU) or
 // POSV (Cholesky) and fill F; status words are read back (synchronizes).
+// d_info != null: stream-ordered, no synchronization; the outcome goes to
+// *d_info (device) and F->lowp_status is left pending.
 int factor_into(mixlu_ctx_s *ctx, const Layout &L, int prec, const double *A, int lda,
-                void *work, size_t lwork, const mixlu_opts &o, mixlu_factor *F, int *info) {
+                void *work, size_t lwork, const mixlu_opts &o, mixlu_factor *F, int *info,
+                int *d_info = nullptr) {
     fill_factor(F, L, work, lwork, o.layout);
-    *info = 0;
+    if (info) *info = 0;
     const int equil = equil_for(prec, o);
     F->equilibrated = equil;
     if (prec == MIXLU_FP64)
         RETCK(convert_and_factor<double>(ctx, work, L, L.W, A, lda, equil, MIXLU_FP64));
     else
         RETCK(convert_and_factor<float>(ctx, work, L, L.W, A, lda, equil, prec));
+    if (d_info) {
+        HIPCK(launch_factor_info(at<int>(work, L.status), L.kind == 1, prec == MIXLU_FP64, d_info,
+                                 ctx->stream));
+        F->lowp_status = MIXLU_FACTOR_PENDING;
+        return MIXLU_OK;
+    }
     int st[ST_COUNT];
     double nrm[2];
     RETCK(read_status(ctx, L, work, st, nrm));
@@ -978,14 +987,15 @@ int factor_into(mixlu_ctx_s *ctx, const Layout &L, int prec, const double *A, in
 }
 
 int factor_entry(mixlu_ctx_s *ctx, int op, int prec, int n, const double *A, int lda, void *work,
-                 size_t lwork, const mixlu_opts *o, mixlu_factor *F, int *info) {
+                 size_t lwork, const mixlu_opts *o, mixlu_factor *F, int *info,
+                 int *d_info = nullptr) {
     if (!prec_valid(prec)) return -2;
     if (n < 0) return -3;
     if (n > 0 && !A) return -4;
     if (lda < (n > 1 ? n : 1)) return -5;
     if (!work) return -6;
     if (!F) return -9;
-    if (!info) return -10;
+    if (!info && !d_info) return -10;
     const mixlu_opts op_ = opts_or_default(o);
     if (op_.layout != MIXLU_ROW_MAJOR && op_.layout != MIXLU_COL_MAJOR) return -8;
     Layout L{};
@@ -1009,10 +1019,11 @@ int factor_entry(mixlu_ctx_s *ctx, int op, int prec, int n, const double *A, int
     }
     if (n == 0) {
         fill_factor(F, L, work, lwork, op_.layout);
-        *info = 0;
+        if (d_info) HIPCK(launch_fill_u32(reinterpret_cast<unsigned *>(d_info), 0u, 1, ctx->stream));
+        else *info = 0;
         return MIXLU_OK;
     }
-    return factor_into(ctx, L, prec, A, lda, work, lwork, op_, F, info);
+    return factor_into(ctx, L, prec, A, lda, work, lwork, op_, F, info, d_info);
 }
 
 // Unit roundoff of the low-precision factor (C1 of the readings: eps_s).
@@ -1592,6 +1603,20 @@ int mixlu_potrf(mixlu_ctx_t ctx, int prec, int n, const double *A, int lda, void
     return factor_entry(ctx, MIXLU_OP_POSV, prec, n, A, lda, work, lwork, o, F, info);
 }
 
+int mixlu_getrf_async(mixlu_ctx_t ctx, int prec, int n, const double *A, int lda, void *work,
+                      size_t lwork, const mixlu_opts *o, mixlu_factor *F, int *d_info) {
+    if (!ctx) return -1;
+    ProfCall pc_(ctx);
+    return factor_entry(ctx, MIXLU_OP_GESV, prec, n, A, lda, work, lwork, o, F, nullptr, d_info);
+}
+
+int mixlu_potrf_async(mixlu_ctx_t ctx, int prec, int n, const double *A, int lda, void *work,
+                      size_t lwork, const mixlu_opts *o, mixlu_factor *F, int *d_info) {
+    if (!ctx) return -1;
+    ProfCall pc_(ctx);
+    return factor_entry(ctx, MIXLU_OP_POSV, prec, n, A, lda, work, lwork, o, F, nullptr, d_info);
+}
+
 int mixlu_getrs(mixlu_ctx_t ctx, const mixlu_factor *F, int trans, const int nrhs,
                 const double *B, int ldb, double *X, int ldx) {
     if (!ctx) return -1;
@@ -1643,6 +1668,14 @@ int mixlu_refine(mixlu_ctx_t ctx, mixlu_factor *F, int trans, int nrhs, const do
     int st[ST_COUNT];
     double nrm[2];
     RETCK(read_status(ctx, L, F->work, st, nrm));
+    if (F->lowp_status == MIXLU_FACTOR_PENDING) {
+        // outcome of an asynchronous factorization, known from here on
+        if (st[ST_TIMEOUT]) return MIXLU_ERR_DEVICE_TIMEOUT;
+        const int brk = breakdown_of(L, st);
+        if (F->prec == MIXLU_FP64) F->lowp_status = brk != INT_MAX ? -1 : 0;
+        else F->lowp_status = st[ST_OVERFLOW] ? -2 : (brk != INT_MAX ? -3 : 0);
+        if (F->prec == MIXLU_FP64 && brk != INT_MAX) rep->info = brk;
+    }
     // ||M^T||_inf = ||M||_1 when the solve is with the transposed matrix
     const double anorm = tr ? nrm[1] : nrm[0];
     rep->anorm = anorm;

@@ -272,6 +272,7 @@ size_t plan_layout(Layout &L, int op, int prec, int n, int nrhs, const mixlu_opt
 // -------------------------------------------------------- kernel launchers
 // Every launcher enqueues on `s` and returns hipGetLastError().
 hipError_t launch_fill_u32(unsigned *p, unsigned v, size_t count, hipStream_t s);
+hipError_t launch_factor_info(const int *status, int chol, int fp64, int *info, hipStream_t s);
 
 // a1/a2: norms, equilibration, conversion (k_convert.hip).  The n x n input
 // is always read as the row-major matrix M (a column-major A is M = A^T).

@@ -19,6 +19,28 @@ __global__ void k_fill_u32(unsigned *p, unsigned v, size_t count) {
     for (; i < count; i += stride) p[i] = v;
 }
 
+// Outcome of a factorization from its status words, for callers that do
+// not synchronize: 0; k + 1 for an exact zero pivot in column k of an FP64
+// factor; -2 (overflow or non-finite value on conversion) or -3 (zero,
+// non-finite or non-positive pivot) for a low-precision factor; -100 when a
+// bounded cross-workgroup wait gave up.
+__global__ void k_factor_info(const int *__restrict__ status, int chol, int fp64,
+                              int *__restrict__ info) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int brk = chol ? status[ST_CHOL] : status[ST_BREAKDOWN];
+    int v = 0;
+    if (status[ST_TIMEOUT]) v = -100;
+    else if (fp64) v = brk == INT_MAX ? 0 : brk;
+    else if (status[ST_OVERFLOW]) v = -2;
+    else if (brk != INT_MAX) v = -3;
+    *info = v;
+}
+
+hipError_t launch_factor_info(const int *status, int chol, int fp64, int *info, hipStream_t s) {
+    k_factor_info<<<dim3(1), dim3(64), 0, s>>>(status, chol, fp64, info);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_u32(unsigned *p, unsigned v, size_t count, hipStream_t s) {
     if (count == 0) return hipSuccess;
     size_t blocks = (count + 255) / 256;

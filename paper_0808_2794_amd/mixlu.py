@@ -83,7 +83,8 @@ EXPORTS = ("mixlu_status_string", "mixlu_default_opts", "mixlu_create", "mixlu_d
            "mixlu_dxgesv_batched", "mixlu_dxgesv_batched_noalloc", "mixlu_profile_enable",
            "mixlu_profile_read", "mixlu_sgesv", "mixlu_report_read", "mixlu_batched_tune", "mixlu_batched_get_tiles",
            "mixlu_batched_set_tiles", "mixlu_condest", "mixlu_sparse_workspace_size",
-           "mixlu_sparse_fgmres", "mixlu_gemm_update", "mixlu_refine_history")
+           "mixlu_sparse_fgmres", "mixlu_gemm_update", "mixlu_refine_history",
+           "mixlu_getrf_async", "mixlu_potrf_async")
 
 _lib = None
 
@@ -106,6 +107,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "mixlu_workspace_size": ([P, I, I, I, I, P, P], I),
         "mixlu_getrf": ([P, I, I, P, I, P, S, P, P, P], I),
         "mixlu_potrf": ([P, I, I, P, I, P, S, P, P, P], I),
+        "mixlu_getrf_async": ([P, I, I, P, I, P, S, P, P, P], I),
+        "mixlu_potrf_async": ([P, I, I, P, I, P, S, P, P, P], I),
         "mixlu_getrs": ([P, P, I, I, P, I, P, I], I),
         "mixlu_refine": ([P, P, I, I, P, I, P, I, P, I, P, P], I),
         "mixlu_dxgesv": ([P, I, I, I, P, I, P, I, P, I, P, S, P, P], I),
@@ -284,6 +287,28 @@ def mixlu_getrf(ctx, prec: int, A, work, opts=None):
 
 def mixlu_potrf(ctx, prec: int, A, work, opts=None):
     return _factor("mixlu_potrf", ctx, prec, A, work, opts)
+
+
+FACTOR_PENDING = 1
+
+
+def _factor_async(name, ctx, prec: int, A, work, d_info, opts=None) -> mixlu_factor:
+    F = mixlu_factor()
+    n = A.shape[0]
+    check(getattr(load(), name)(ctx, prec, n, _p(A), _ld(A, _cm(opts)), _p(work),
+                                work.numel() * work.element_size(),
+                                None if opts is None else ctypes.byref(opts), ctypes.byref(F),
+                                _p(d_info)), name)
+    return F
+
+
+def mixlu_getrf_async(ctx, prec: int, A, work, d_info, opts=None) -> mixlu_factor:
+    """Stream-ordered factorization; the outcome lands in d_info (device int32)."""
+    return _factor_async("mixlu_getrf_async", ctx, prec, A, work, d_info, opts)
+
+
+def mixlu_potrf_async(ctx, prec: int, A, work, d_info, opts=None) -> mixlu_factor:
+    return _factor_async("mixlu_potrf_async", ctx, prec, A, work, d_info, opts)
 
 
 def mixlu_getrs(ctx, F: mixlu_factor, B, X, trans: int = 0) -> None:
