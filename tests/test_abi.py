@@ -80,6 +80,28 @@ def test_host_only_new_entry_points():
     assert o.condest == 0 and o.refine == mixlu.REFINE_CLASSIC
 
 
+def test_host_only_async_and_history():
+    """The stream-ordered factorizations and the residual history refuse a
+    NULL context before any device work; the restart option sits after
+    condest, 0 by default (30 steps); the pending-outcome code is the
+    header's."""
+    import ctypes
+
+    from paper_0808_2794_amd import mixlu
+
+    lib = mixlu.load()
+    F = mixlu.mixlu_factor()
+    for name in ("mixlu_getrf_async", "mixlu_potrf_async"):
+        assert getattr(lib, name)(None, mixlu.FP32, 4, None, 4, None, 0, None, ctypes.byref(F),
+                                  None) == -1
+    cnt = ctypes.c_int()
+    assert lib.mixlu_refine_history(None, None, 0, ctypes.byref(cnt)) == -1
+    assert mixlu.mixlu_opts.restart.offset == mixlu.mixlu_opts.condest.offset + 4
+    assert mixlu.default_opts().restart == 0
+    hdr = open(HEADER).read()
+    assert "#define MIXLU_FACTOR_PENDING 1" in hdr and mixlu.FACTOR_PENDING == 1
+
+
 def test_sweep_datta_bound():
     """The bound the experiment prints: ceil(ln eps_d / (ln eps_s + ln kappa)),
     finite only while kappa eps_s < 1 (worked by hand for FP32: kappa = 10
