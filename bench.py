@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--seed", type=int, default=None)
     ap.add_argument("--refine", default="classic", choices=["classic", "fgmres"],
                     help="refinement after the low-precision factor (dense workload)")
+    ap.add_argument("--restart", type=int, default=0,
+                    help="FGMRES restart length (0: the library's default, 30; at most 128)")
     ap.add_argument("--matrix", default="prescribed", choices=["prescribed", "uniform"],
                     help="dense workload input: U diag(sigma) V^T (default) or iid U[-1,1] "
                          "entries (no QR; for counter runs, whose traffic depends on the "
@@ -272,9 +274,11 @@ def run_dense(args, prec):
     solver = mixlu.Solver()
     refine = mixlu.REFINE_FGMRES if args.refine == "fgmres" else mixlu.REFINE_CLASSIC
     for _ in range(args.warmup):
-        solver.dxgesv(A, b, prec, refine=refine)
+        solver.dxgesv(A, b, prec, refine=refine, restart=args.restart)
     mixlu.mixlu_profile_enable(solver.ctx, True)
-    ms, res = time_calls(lambda: solver.dxgesv(A, b, prec, refine=refine), args.steps)
+    ms, res = time_calls(lambda: solver.dxgesv(A, b, prec, refine=refine, restart=args.restart),
+                         args.steps)
+    history = mixlu.mixlu_refine_history(solver.ctx)
     kst = mixlu.mixlu_profile_read(solver.ctx)
     mixlu.mixlu_profile_enable(solver.ctx, False)
     x = res.x.double().cpu().numpy()
@@ -296,9 +300,11 @@ def run_dense(args, prec):
         "config": {"workload": (f"dense_nonsym_prescribed_cond_n{n}_kappa{kappa:g}_nrhs1"
                                 if args.matrix == "prescribed" else f"dense_nonsym_uniform_n{n}_nrhs1"),
                    "n": n, "kappa": kappa, "nrhs": 1, "seed": seed, "factor_precision": prec,
-                   "refinement": "fp64 " + args.refine},
+                   "refinement": "fp64 " + args.refine
+                   + (f" restart {args.restart}" if args.refine == "fgmres" and args.restart else "")},
         "solve": {"iter": rep["iter"], "prec_used": rep["prec"], "converged": rep["converged"],
-                  "berr": rep["berr"], "fwd_err_vs_x_true": fwd}}
+                  "berr": rep["berr"], "fwd_err_vs_x_true": fwd,
+                  "residual_history": [float(f"{v:.3e}") for v in history[:40]]}}
 
 
 def run_spd(args, prec):
@@ -554,6 +560,7 @@ def run_adjoint(args, prec):
         if args.cpu_seconds > 0 else None
     solver.close()
     return ms, kst, cpu, comp, {
+        "columns": n,
         "config": {"workload": f"differentiable_solve_n{n}_nrhs{nrhs}_kappa{kappa:g}", "n": n,
                    "nrhs": nrhs, "kappa": kappa, "seed": seed, "factor_precision": prec,
                    "refinement": "fp64", "passes": "forward+adjoint"},
