@@ -395,12 +395,19 @@ __device__ __noinline__ void sys_getrs(const T *__restrict__ W, int n, BShared &
         if (tid < kBDiag) {
             const int i = b0 + lane;
             T yl = i < n ? y[i] : (T)0;
+            // each lane divides its row of the block and its right-hand side
+            // by its own pivot first, so the chain below has a unit diagonal:
+            // one broadcast and one multiply-add per step
+            if (i < n) {
+                const T d = sd[lane * DP + lane];
+                yl /= d;
+                for (int c = lane + 1; c < kBDiag; ++c) sd[lane * DP + c] /= d;
+            }
 #pragma unroll 4
             for (int q = kBDiag - 1; q >= 0; --q) {
                 if (b0 + q < n) {
-                    const T yq = readlane_t(yl, q) / sd[q * DP + q];
-                    if (lane == q) yl = yq;
-                    else if (lane < q) yl -= sd[lane * DP + q] * yq;
+                    const T yq = readlane_t(yl, q);
+                    if (lane < q) yl -= sd[lane * DP + q] * yq;
                 }
             }
             if (i < n) y[i] = yl;

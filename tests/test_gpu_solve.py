@@ -176,6 +176,24 @@ def test_multiple_rhs(solver):
         _check(A, b, r.x.cpu().numpy(), 1e3, ref.x)
 
 
+@pytest.mark.parametrize("nb,prec", [(1024, "fp32"), (1024, "fp16"), (256, "fp32"), (64, "fp64")])
+def test_outer_block_widths(solver, nb, prec):
+    """Outer blocks other than the default 512: 1024 (wide interchange lists,
+    the largest the move lists hold), 256, and 64 (interchanges applied by the
+    fused kernel). n = 2100 spans several outer blocks with a ragged tail, so
+    the look-ahead streams and all three packed-operand sets take part."""
+    from paper_0808_2794_amd import mixlu
+
+    n, kappa = 2100, 1e2
+    A, b, _ = gen.prescribed_cond_system(n, kappa, 2400 + nb)
+    _say(f"dxgesv n={n} nb={nb} prec={prec}")
+    Ad, bd = _to_dev(A, b)
+    r = solver.dxgesv(Ad, bd, prec, mixlu.default_opts(nb=nb))
+    assert r.report["converged"] and r.report["prec"] == prec, r.report
+    ref = O.gesv_ir(A, b)
+    _check(A, b, r.x.cpu().numpy(), kappa, ref.x)
+
+
 def test_factor_is_partial_pivoting(solver):
     """Factors read back from the workspace: P A = L U to FP32 accuracy and
     every multiplier |l_ij| <= 1 (the partial-pivoting property: each pivot was
