@@ -956,7 +956,8 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const T *__re
 // registers while the current one is multiplied out of LDS, and stored into
 // the second LDS buffer (one barrier per K slab).  LDS pitches
 // make the MFMA operand reads conflict-free: A is kept [m][k] with pitch
-// BK + 4, B [k][n] with pitch 128 + 16.
+// BK + 4, B [k][n] with pitch 128 + 16.  The accumulators start from C and
+// A is negated on its way into LDS, so the epilogue only stores.
 template <typename T, int BK>
 __global__ __launch_bounds__(256) void k_gemm_big(int M, int N, int K, const T *__restrict__ A,
                                                   int lda, const T *__restrict__ Bm, int ldb,
@@ -978,11 +979,20 @@ __global__ __launch_bounds__(256) void k_gemm_big(int M, int N, int K, const T *
     if (lower && n0 > m0 + BM - 1) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
+    // the accumulators start from the C tile (requested before the first K
+    // slab, so its latency overlaps the operand loads) and the MFMAs add
+    // (-A) B: the epilogue is a plain store, no read-modify-write of C
     acc_t acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = m0 + wm * 64 + i * 16 + Mfma<T>::row(lane, v);
+                const int col = n0 + wn * 64 + j * 16 + (lane & 15);
+                acc[i][j][v] = (row < M && col < N) ? C[(size_t)row * ldc + col] : (T)0;
+            }
     vec_t ra[NLA], rb[NLB];
     auto load = [&](int k0) {
 #pragma unroll
@@ -1019,7 +1029,7 @@ __global__ __launch_bounds__(256) void k_gemm_big(int M, int N, int K, const T *
         for (int q = 0; q < NLA; ++q) {
             const int e = tid + q * 256;
             const int r = e / (BK / V), kv = (e % (BK / V)) * V;
-            *reinterpret_cast<vec_t *>(&sA[r * PA + kv]) = ra[q];
+            *reinterpret_cast<vec_t *>(&sA[r * PA + kv]) = -ra[q];
         }
 #pragma unroll
         for (int q = 0; q < NLB; ++q) {
@@ -1065,7 +1075,7 @@ __global__ __launch_bounds__(256) void k_gemm_big(int M, int N, int K, const T *
             for (int v = 0; v < 4; ++v) {
                 const int row = m0 + wm * 64 + i * 16 + Mfma<T>::row(lane, v);
                 const int col = n0 + wn * 64 + j * 16 + (lane & 15);
-                if (row < M && col < N) C[(size_t)row * ldc + col] -= acc[i][j][v];
+                if (row < M && col < N) C[(size_t)row * ldc + col] = acc[i][j][v];
             }
 }
 
