@@ -1268,25 +1268,48 @@ __global__ __launch_bounds__(256) void k_gemm_lowp(int M, int N, int K, const H 
     if (lower && n0 > m0 + BM - 1) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
+    // the accumulators start from the C tile and A enters LDS negated (the
+    // sign bit of each 16-bit value flipped), so the epilogue only stores;
+    // the next K slab is loaded into registers while the current one is
+    // multiplied
     f32x4 acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = m0 + wm * 64 + i * 16 + (lane >> 4) * 4 + v;
+                const int col = n0 + wn * 64 + j * 16 + (lane & 15);
+                acc[i][j][v] = (row < M && col < N) ? C[(size_t)row * ldc + col] : 0.0f;
+            }
+    uint4 pa[4], pb[4];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = tid + q * 256;
+            const int row = e >> 3, seg = e & 7;
+            pa[q] = make_uint4(0, 0, 0, 0);
+            pb[q] = make_uint4(0, 0, 0, 0);
+            if (m0 + row < M)
+                pa[q] = *reinterpret_cast<const uint4 *>(Ap + (size_t)(m0 + row) * K + k0 + seg * 8);
+            if (n0 + row < N)
+                pb[q] = *reinterpret_cast<const uint4 *>(Bp + (size_t)(n0 + row) * K + k0 + seg * 8);
+        }
+    };
+    load(0);
     for (int k0 = 0; k0 < K; k0 += BK) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int e = tid + q * 256;
             const int row = e >> 3, seg = e & 7;
-            uint4 va = make_uint4(0, 0, 0, 0), vb = make_uint4(0, 0, 0, 0);
-            if (m0 + row < M)
-                va = *reinterpret_cast<const uint4 *>(Ap + (size_t)(m0 + row) * K + k0 + seg * 8);
-            if (n0 + row < N)
-                vb = *reinterpret_cast<const uint4 *>(Bp + (size_t)(n0 + row) * K + k0 + seg * 8);
-            *reinterpret_cast<uint4 *>(&sA[row * PITCH + seg * 8]) = va;
-            *reinterpret_cast<uint4 *>(&sB[row * PITCH + seg * 8]) = vb;
+            constexpr unsigned kSign = 0x80008000u;
+            *reinterpret_cast<uint4 *>(&sA[row * PITCH + seg * 8]) =
+                make_uint4(pa[q].x ^ kSign, pa[q].y ^ kSign, pa[q].z ^ kSign, pa[q].w ^ kSign);
+            *reinterpret_cast<uint4 *>(&sB[row * PITCH + seg * 8]) = pb[q];
         }
         __syncthreads();
+        if (k0 + BK < K) load(k0 + BK);
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 32) {
             vec_t av[4], bv[4];
@@ -1312,7 +1335,7 @@ __global__ __launch_bounds__(256) void k_gemm_lowp(int M, int N, int K, const H 
             for (int v = 0; v < 4; ++v) {
                 const int row = m0 + wm * 64 + i * 16 + (lane >> 4) * 4 + v;
                 const int col = n0 + wn * 64 + j * 16 + (lane & 15);
-                if (row < M && col < N) C[(size_t)row * ldc + col] -= acc[i][j][v];
+                if (row < M && col < N) C[(size_t)row * ldc + col] = acc[i][j][v];
             }
 }
 
@@ -1434,11 +1457,19 @@ __global__ __launch_bounds__(256) void k_gemm_fp8(int M, int N, int K,
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const int kb = K / 32;
+    // accumulators from the C tile, A's codes negated (sign bit of each
+    // E4M3 byte flipped): the epilogue only stores
     f32x4 acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = m0 + wm * 64 + i * 16 + (lane >> 4) * 4 + v;
+                const int col = n0 + wn * 64 + j * 16 + (lane & 15);
+                acc[i][j][v] = (row < M && col < N) ? C[(size_t)row * ldc + col] : 0.0f;
+            }
     for (int k0 = 0; k0 < K; k0 += BK) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -1447,7 +1478,9 @@ __global__ __launch_bounds__(256) void k_gemm_fp8(int M, int N, int K,
             uint4 va = make_uint4(0, 0, 0, 0), vb = make_uint4(0, 0, 0, 0);
             if (m0 + row < M) va = *reinterpret_cast<const uint4 *>(Ac + (size_t)(m0 + row) * K + k0 + seg * 16);
             if (n0 + row < N) vb = *reinterpret_cast<const uint4 *>(Bc + (size_t)(n0 + row) * K + k0 + seg * 16);
-            *reinterpret_cast<uint4 *>(&sA[row * PITCH + seg * 16]) = va;
+            constexpr unsigned kSign = 0x80808080u;
+            *reinterpret_cast<uint4 *>(&sA[row * PITCH + seg * 16]) =
+                make_uint4(va.x ^ kSign, va.y ^ kSign, va.z ^ kSign, va.w ^ kSign);
             *reinterpret_cast<uint4 *>(&sB[row * PITCH + seg * 16]) = vb;
         }
         for (int e = tid; e < BM * 4; e += 256) {
@@ -1493,7 +1526,7 @@ __global__ __launch_bounds__(256) void k_gemm_fp8(int M, int N, int K,
             for (int v = 0; v < 4; ++v) {
                 const int row = m0 + wm * 64 + i * 16 + (lane >> 4) * 4 + v;
                 const int col = n0 + wn * 64 + j * 16 + (lane & 15);
-                if (row < M && col < N) C[(size_t)row * ldc + col] -= acc[i][j][v];
+                if (row < M && col < N) C[(size_t)row * ldc + col] = acc[i][j][v];
             }
 }
 
