@@ -118,25 +118,31 @@ template hipError_t launch_tri_inv<double>(const double *, int, int, double *, h
 // diagonal of W), forward; upper = 1 with U (on and above the diagonal),
 // backward.  TRANS = true solves with the transposed factors: upper = 0
 // with U^T (lower, non-unit), forward; upper = 1 with L^T (upper, unit),
-// backward.  Workgroup b (in ticket order) accumulates the products of its
-// block row with the solved blocks as they are published, then applies the
-// inverse of its diagonal block (from k_tri_inv: dinv, 2 npad x 64) as a
-// 64 x 64 product instead of 64 dependent substitution steps.  yx holds the
-// published solution words ((row * NRT + c) * PWV + word), zeroed before the
-// launch together with the ticket counter at yx[npad * NRT * PWV].
+// backward.  Workgroup o (in ticket order) takes the blocks at chain
+// positions 2o and 2o + 1, one per half (256 threads each): both halves
+// accumulate the products of their block rows with the solved blocks as
+// they are published (tile rows requested a few steps ahead), then the first
+// block is finished by applying the inverse of its diagonal block (from
+// k_tri_inv: dinv, 2 npad x 64) as a 64 x 64 product, and the second takes
+// the first's solution from LDS instead of waiting for its publication, so
+// one cross-workgroup hand-off serves two blocks.  yx holds the published
+// solution words ((row * NRT + c) * PWV + word), zeroed before the launch
+// together with the ticket counter at yx[npad * NRT * PWV].
 template <typename T, int NRT, bool TRANS>
-__global__ __launch_bounds__(256) void k_trsv(int upper, const T *__restrict__ W, int ldw,
+__global__ __launch_bounds__(512) void k_trsv(int upper, const T *__restrict__ W, int ldw,
                                               const T *__restrict__ dinv, int nblk,
                                               T *__restrict__ Y, int ldy, int nrhs,
                                               unsigned long long *__restrict__ yx,
                                               int *__restrict__ status) {
     constexpr int BS = kTrsvBS, PWV = Words<T>::n;
     constexpr int NWMAX = BS * NRT * PWV;          // words of one solution block
-    constexpr int WPT = (NWMAX + 255) / 256;       // words per thread
+    constexpr int WPT = (NWMAX + 511) / 512;       // words per thread
     __shared__ unsigned swords[2][NWMAX];
-    __shared__ T sy[BS][NRT];
+    __shared__ T sy[2][BS][NRT];                   // each half's right-hand side
+    __shared__ T sfirst[BS][NRT];                  // the first block's solution
     __shared__ int s_b, s_bad;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, h = tid >> 8, t = tid & 255;
+    const int npairs = (nblk + 1) / 2;
     int *ticket = reinterpret_cast<int *>(yx + (size_t)nblk * BS * NRT * PWV);
     if (tid == 0) {
         s_b = atomicAdd(ticket, 1);
@@ -144,10 +150,14 @@ __global__ __launch_bounds__(256) void k_trsv(int upper, const T *__restrict__ W
     }
     __syncthreads();
     const int order = s_b;
-    if (order >= nblk) return;
-    const int b = upper ? nblk - 1 - order : order;
-    const int r = tid >> 2, q = tid & 3;  // row of the block, quarter of the k range
-    const int wblk = BS * nrhs * PWV;      // words of one solution block
+    if (order >= npairs) return;
+    const int i0 = 2 * order, i1 = i0 + 1;  // chain positions of the pair
+    const bool has1 = i1 < nblk;
+    const bool mine = h == 0 || has1;       // this half has a block (uniform per wave)
+    const int cpos = h == 0 ? i0 : (has1 ? i1 : i0);
+    const int b = upper ? nblk - 1 - cpos : cpos;
+    const int r = t >> 2, q = t & 3;  // row of the block, quarter of the k range
+    const int wblk = BS * nrhs * PWV;  // words of one solution block
 
     T acc[NRT];
 #pragma unroll
@@ -169,15 +179,25 @@ __global__ __launch_bounds__(256) void k_trsv(int upper, const T *__restrict__ W
         for (int e = 0; e < 16; ++e)
             dg[e] = TRANS ? dblk[(q * 16 + e) * BS + r] : dblk[r * BS + q * 16 + e];
     }
+    // the second block's tile against the first (on the pair's own critical
+    // path), requested now as well
+    T lx[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) lx[e] = (T)0;
+    if (h == 1 && has1) {
+        const T *lrow = tile_ptr(upper ? nblk - 1 - i0 : i0);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) lx[e] = TRANS ? lrow[e * estride] : lrow[e];
+    }
 
-    const int nsteps = upper ? nblk - 1 - b : b;
+    const int nsteps = i0;  // blocks before the pair, in chain order
     // tile rows of the next PF steps are requested ahead (they depend on
     // nothing), so a step costs the wait for its solution block, not a
     // memory latency of its own
-    constexpr int PF = kTrsvPrefetch;
+    constexpr int PF = sizeof(T) == 4 ? kTrsvPrefetch : 2;
     T lv[PF][16];
     auto request = [&](int st, T(&dst)[16]) {
-        if (st < nsteps) {
+        if (mine && st < nsteps) {
             const T *lrow = tile_ptr(upper ? nblk - 1 - st : st);
 #pragma unroll
             for (int e = 0; e < 16; ++e) dst[e] = TRANS ? lrow[e * estride] : lrow[e];
@@ -196,10 +216,10 @@ __global__ __launch_bounds__(256) void k_trsv(int upper, const T *__restrict__ W
             unsigned long long wv[WPT];
 #pragma unroll
             for (int p = 0; p < WPT; ++p) {
-                const int t = tid + p * 256;
+                const int tt = tid + p * 512;
                 wv[p] = 0ull;
-                if (t < wblk) {
-                    const int i = t / (nrhs * PWV), rr = t - i * (nrhs * PWV);
+                if (tt < wblk) {
+                    const int i = tt / (nrhs * PWV), rr = tt - i * (nrhs * PWV);
                     wv[p] = xload(yx + ((size_t)(j * BS + i) * NRT) * PWV + rr);
                 }
             }
@@ -210,15 +230,15 @@ __global__ __launch_bounds__(256) void k_trsv(int upper, const T *__restrict__ W
             bool bad = false;
 #pragma unroll
             for (int p = 0; p < WPT; ++p) {
-                const int t = tid + p * 256;
-                if (t < wblk) {
+                const int tt = tid + p * 512;
+                if (tt < wblk) {
                     unsigned v = (unsigned)wv[p];
                     if ((unsigned)(wv[p] >> 32) != 1u && !bad) {
-                        const int i = t / (nrhs * PWV), rr = t - i * (nrhs * PWV);
+                        const int i = tt / (nrhs * PWV), rr = tt - i * (nrhs * PWV);
                         v = spin_tag(yx + ((size_t)(j * BS + i) * NRT) * PWV + rr, 1u,
                                      &status[ST_TIMEOUT], bad);
                     }
-                    swords[par][t] = v;
+                    swords[par][tt] = v;
                 }
             }
             if (bad) s_bad = 1;
@@ -227,53 +247,82 @@ __global__ __launch_bounds__(256) void k_trsv(int upper, const T *__restrict__ W
                 stop = true;
                 return;
             }
+            if (mine) {
 #pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const int i = q * 16 + e;
+                for (int e = 0; e < 16; ++e) {
+                    const int i = q * 16 + e;
 #pragma unroll
-                for (int c = 0; c < NRT; ++c)
-                    if (c < nrhs) acc[c] += cur[e] * Words<T>::make(&swords[par][(i * nrhs + c) * PWV]);
+                    for (int c = 0; c < NRT; ++c)
+                        if (c < nrhs) acc[c] += cur[e] * Words<T>::make(&swords[par][(i * nrhs + c) * PWV]);
+                }
             }
             par ^= 1;
         });
         if (stop) return;
     }
-    // combine the four k-quarters of each row
+    // y = inv(M_bb) (rhs_b - sum_j M_bj y_j) for this half's block: 16
+    // products per thread, then the four quarters of each row; q == 0
+    // writes Y, publishes the words and (first block) keeps y in LDS
+    auto finish = [&](int hh) {
+        T yv[NRT];
 #pragma unroll
-    for (int c = 0; c < NRT; ++c) {
-        acc[c] += __shfl_xor(acc[c], 1);
-        acc[c] += __shfl_xor(acc[c], 2);
-    }
-    if (q == 0) {
+        for (int c = 0; c < NRT; ++c) {
+            T v = (T)0;
 #pragma unroll
-        for (int c = 0; c < NRT; ++c)
-            if (c < nrhs) sy[r][c] = Y[(size_t)(b * BS + r) * ldy + c] - acc[c];
+            for (int e = 0; e < 16; ++e) v += dg[e] * sy[hh][q * 16 + e][c];
+            v += __shfl_xor(v, 1);
+            v += __shfl_xor(v, 2);
+            yv[c] = v;
+        }
+        if (q == 0) {
+            const int row = b * BS + r;
+#pragma unroll
+            for (int c = 0; c < NRT; ++c) {
+                if (c < nrhs) {
+                    Y[(size_t)row * ldy + c] = yv[c];
+                    if (hh == 0) sfirst[r][c] = yv[c];
+#pragma unroll
+                    for (int wv = 0; wv < PWV; ++wv)
+                        xstore(yx + ((size_t)row * NRT + c) * PWV + wv, 1u, Words<T>::get(yv[c], wv));
+                }
+            }
+        }
+    };
+    // the first block: combine the four k-quarters of each row
+    if (h == 0) {
+#pragma unroll
+        for (int c = 0; c < NRT; ++c) {
+            acc[c] += __shfl_xor(acc[c], 1);
+            acc[c] += __shfl_xor(acc[c], 2);
+        }
+        if (q == 0) {
+#pragma unroll
+            for (int c = 0; c < NRT; ++c)
+                if (c < nrhs) sy[0][r][c] = Y[(size_t)(b * BS + r) * ldy + c] - acc[c];
+        }
     }
     __syncthreads();
-    // y_b = inv(M_bb) (rhs_b - sum_j M_bj y_j): 16 products per thread, then
-    // the four quarters of each row
-    T yv[NRT];
-#pragma unroll
-    for (int c = 0; c < NRT; ++c) {
-        T v = (T)0;
-#pragma unroll
-        for (int e = 0; e < 16; ++e) v += dg[e] * sy[q * 16 + e][c];
-        v += __shfl_xor(v, 1);
-        v += __shfl_xor(v, 2);
-        yv[c] = v;
-    }
-    if (q == 0) {
-        const int row = b * BS + r;
+    if (h == 0) finish(0);
+    __syncthreads();
+    // the second block: its product with the first block's solution, from LDS
+    if (h == 1 && has1) {
 #pragma unroll
         for (int c = 0; c < NRT; ++c) {
             if (c < nrhs) {
-                Y[(size_t)row * ldy + c] = yv[c];
 #pragma unroll
-                for (int wv = 0; wv < PWV; ++wv)
-                    xstore(yx + ((size_t)row * NRT + c) * PWV + wv, 1u, Words<T>::get(yv[c], wv));
+                for (int e = 0; e < 16; ++e) acc[c] += lx[e] * sfirst[q * 16 + e][c];
             }
+            acc[c] += __shfl_xor(acc[c], 1);
+            acc[c] += __shfl_xor(acc[c], 2);
+        }
+        if (q == 0) {
+#pragma unroll
+            for (int c = 0; c < NRT; ++c)
+                if (c < nrhs) sy[1][r][c] = Y[(size_t)(b * BS + r) * ldy + c] - acc[c];
         }
     }
+    __syncthreads();
+    if (h == 1 && has1) finish(1);
 }
 
 template <typename Tw, bool TRANS>
@@ -288,12 +337,13 @@ hipError_t launch_trsv_t(int upper, const Tw *W, int ldw, const Tw *dinv, int np
                                    ((size_t)npad * kTrsvNRT * PWV + 1) * 2, s);
     if (e != hipSuccess) return e;
     // each instantiation lays its words (and ticket) out inside the zeroed region
+    const int npairs = (nblk + 1) / 2;  // two blocks per workgroup
     if (nrhs == 1)
-        k_trsv<Tw, 1, TRANS><<<dim3(nblk), dim3(256), 0, s>>>(upper, W, ldw, dinv, nblk, Y, ldy,
-                                                              nrhs, ybuf, status);
+        k_trsv<Tw, 1, TRANS><<<dim3(npairs), dim3(512), 0, s>>>(upper, W, ldw, dinv, nblk, Y, ldy,
+                                                                nrhs, ybuf, status);
     else
-        k_trsv<Tw, kTrsvNRT, TRANS><<<dim3(nblk), dim3(256), 0, s>>>(upper, W, ldw, dinv, nblk, Y,
-                                                                     ldy, nrhs, ybuf, status);
+        k_trsv<Tw, kTrsvNRT, TRANS><<<dim3(npairs), dim3(512), 0, s>>>(upper, W, ldw, dinv, nblk, Y,
+                                                                       ldy, nrhs, ybuf, status);
     return hipGetLastError();
 }
 
