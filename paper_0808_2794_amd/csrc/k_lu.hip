@@ -465,6 +465,7 @@ template hipError_t launch_panel<double>(double *, int, int, int, int *, unsigne
 // row whose content ends at row k0 + i), then moves the rows of its CW
 // columns of [c0, c1) minus [skip0, skip1) (staged in LDS, so the moves may
 // form cycles).  Workgroup 0 also applies the moves to perm (when given).
+constexpr int kSwapRegs = 8;  // moved values held in registers per thread (128 moves x 16 columns)
 template <typename T, int CW>
 __global__ __launch_bounds__(256) void k_row_swaps(const int *__restrict__ ipiv, int k0, int cnt,
                                                    int npad, int *__restrict__ perm,
@@ -507,7 +508,43 @@ __global__ __launch_bounds__(256) void k_row_swaps(const int *__restrict__ ipiv,
     }
     __syncthreads();
     const int count = s_count;
-    if (perm && blockIdx.x == 0) {
+    // the moved values of this workgroup's columns and (workgroup 0) of perm
+    // are read in one round, all before any is written (so moves may form
+    // cycles): one memory round trip instead of one per array
+    const int lc0 = blockIdx.x * CW;
+    const bool do_perm = perm && blockIdx.x == 0;
+    if (count * CW <= kSwapRegs * 256) {
+        T v[kSwapRegs];
+        int keep[kSwapRegs / 2];
+#pragma unroll
+        for (int u = 0; u < kSwapRegs; ++u) {
+            const int e = threadIdx.x + u * 256;
+            const int q = e / CW, lc = lc0 + e % CW;
+            v[u] = (T)0;
+            if (e < count * CW && lc < ncols)
+                v[u] = W[(size_t)mv[2 * q + 1] * ldw + c0 + lc + (lc >= nleft ? gap : 0)];
+        }
+#pragma unroll
+        for (int u = 0; u < kSwapRegs / 2; ++u) {
+            const int q = threadIdx.x + u * 256;
+            keep[u] = (do_perm && q < count) ? perm[mv[2 * q + 1]] : 0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kSwapRegs; ++u) {
+            const int e = threadIdx.x + u * 256;
+            const int q = e / CW, lc = lc0 + e % CW;
+            if (e < count * CW && lc < ncols)
+                W[(size_t)mv[2 * q] * ldw + c0 + lc + (lc >= nleft ? gap : 0)] = v[u];
+        }
+#pragma unroll
+        for (int u = 0; u < kSwapRegs / 2; ++u) {
+            const int q = threadIdx.x + u * 256;
+            if (do_perm && q < count) perm[mv[2 * q]] = keep[u];
+        }
+        return;
+    }
+    if (do_perm) {
         int keep[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
@@ -521,7 +558,6 @@ __global__ __launch_bounds__(256) void k_row_swaps(const int *__restrict__ ipiv,
             if (q < count) perm[mv[2 * q]] = keep[u];
         }
     }
-    const int lc0 = blockIdx.x * CW;
     for (int e = threadIdx.x; e < count * CW; e += 256) {
         const int q = e / CW, cc = e % CW;
         const int lc = lc0 + cc;
