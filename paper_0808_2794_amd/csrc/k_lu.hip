@@ -916,19 +916,30 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const T *__re
     if (lower && n0 > m0 + BM - 1) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
+    // slice 0 starts its accumulators from C, the others from zero; A is
+    // negated on its way into LDS, so the epilogue only stores (C, or the
+    // slice's -A_z B_z into P); the next K slab is read into registers while
+    // the current one is multiplied
     acc_t acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
-    for (int k0 = kb; k0 < ke; k0 += BK) {
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = m0 + wm * 32 + i * 16 + Mfma<T>::row(lane, v);
+                const int col = n0 + wn * 32 + j * 16 + (lane & 15);
+                acc[i][j][v] = (z == 0 && row < M && col < N) ? C[(size_t)row * ldc + col] : (T)0;
+            }
+    T ra[4], rb[4];
+    auto load = [&](int k0) {
         if constexpr (TA) {
             const int kk = tid >> 4, r = (tid & 15) * 4;
             const int gk = k0 + kk;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int gr = m0 + r + q;
-                sA[kk][r + q] = (gk < ke && gr < M) ? A[(size_t)gk * lda + gr] : (T)0;
+                ra[q] = (gk < ke && gr < M) ? A[(size_t)gk * lda + gr] : (T)0;
             }
         } else {
             const int r = tid >> 2, kk = (tid & 3) * 4;
@@ -936,7 +947,7 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const T *__re
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int gk = k0 + kk + q;
-                sA[kk + q][r] = (gr < M && gk < ke) ? A[(size_t)gr * lda + gk] : (T)0;
+                ra[q] = (gr < M && gk < ke) ? A[(size_t)gr * lda + gk] : (T)0;
             }
         }
         if constexpr (TB) {
@@ -945,7 +956,7 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const T *__re
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int gk = k0 + kk + q;
-                sB[kk + q][c] = (gc < N && gk < ke) ? Bm[(size_t)gc * ldb + gk] : (T)0;
+                rb[q] = (gc < N && gk < ke) ? Bm[(size_t)gc * ldb + gk] : (T)0;
             }
         } else {
             const int kk = tid >> 4, c = (tid & 15) * 4;
@@ -953,10 +964,32 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const T *__re
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int gc = n0 + c + q;
-                sB[kk][c + q] = (gk < ke && gc < N) ? Bm[(size_t)gk * ldb + gc] : (T)0;
+                rb[q] = (gk < ke && gc < N) ? Bm[(size_t)gk * ldb + gc] : (T)0;
             }
         }
+    };
+    if (kb < ke) load(kb);
+    for (int k0 = kb; k0 < ke; k0 += BK) {
+        if constexpr (TA) {
+            const int kk = tid >> 4, r = (tid & 15) * 4;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) sA[kk][r + q] = -ra[q];
+        } else {
+            const int r = tid >> 2, kk = (tid & 3) * 4;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) sA[kk + q][r] = -ra[q];
+        }
+        if constexpr (TB) {
+            const int c = tid >> 2, kk = (tid & 3) * 4;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) sB[kk + q][c] = rb[q];
+        } else {
+            const int kk = tid >> 4, c = (tid & 15) * 4;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) sB[kk][c + q] = rb[q];
+        }
         __syncthreads();
+        if (k0 + BK < ke) load(k0 + BK);
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
             const int kr = kk + (lane >> 4);
@@ -980,8 +1013,8 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const T *__re
                 const int row = m0 + wm * 32 + i * 16 + Mfma<T>::row(lane, v);
                 const int col = n0 + wn * 32 + j * 16 + (lane & 15);
                 if (row < M && col < N) {
-                    if (z == 0) C[(size_t)row * ldc + col] -= acc[i][j][v];
-                    else P[(size_t)(z - 1) * pstride + (size_t)row * ldc + col] = -acc[i][j][v];
+                    if (z == 0) C[(size_t)row * ldc + col] = acc[i][j][v];
+                    else P[(size_t)(z - 1) * pstride + (size_t)row * ldc + col] = acc[i][j][v];
                 }
             }
 }
