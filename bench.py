@@ -39,7 +39,7 @@ PEAK_HBM_GBS = 8000.0
 PEAK_MFMA_TFS = {"fp16": 2500.0, "bf16": 2500.0, "fp8": 5000.0, "fp32": 157.3, "fp64": 78.6}
 PEAK_VALU_TFS = {"fp32": 78.6, "fp64": 78.6}
 METRIC = "time to FP64-accurate solve, mixed vs FP64 LU on 1 GPU; MFMA util"
-DTYPE = {"fp32": "f32", "fp16": "f16", "bf16": "bf16", "fp64": "f64"}
+DTYPE = {"fp32": "f32", "fp16": "f16", "bf16": "bf16", "fp8": "e4m3", "fp64": "f64"}
 DEFAULT_PREC = {"dense": "fp32", "spd": "fp16", "batched": "fp32", "adjoint": "fp32",
                 "sparse": "fp32"}
 
@@ -51,7 +51,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="dense",
                     choices=["dense", "spd", "batched", "adjoint", "sparse"])
-    ap.add_argument("--prec", default=None, choices=["fp32", "fp16", "bf16", "fp64"])
+    ap.add_argument("--prec", default=None, choices=["fp32", "fp16", "bf16", "fp8", "fp64"])
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--kappa", type=float, default=None)
     ap.add_argument("--seed", type=int, default=None)
@@ -565,7 +565,8 @@ def run_adjoint(args, prec):
                    "nrhs": nrhs, "kappa": kappa, "seed": seed, "factor_precision": prec,
                    "refinement": "fp64", "passes": "forward+adjoint"},
         "solve": {k: ({"iter": v["iter"], "prec_used": v["prec"], "converged": v["converged"],
-                       "berr": v["berr"]} if v else None) for k, v in reports.items()}}
+                       "fallback_iter": v["fallback_iter"], "berr": v["berr"]} if v else None)
+                  for k, v in reports.items()}}
 
 
 def main():
