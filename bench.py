@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--seed", type=int, default=None)
     ap.add_argument("--refine", default="classic", choices=["classic", "fgmres"],
                     help="refinement after the low-precision factor (dense workload)")
+    ap.add_argument("--nb", type=int, default=0,
+                    help="outer block width of the dense factorization (0: the library's choice)")
     ap.add_argument("--restart", type=int, default=0,
                     help="FGMRES restart length (0: the library's default, 30; at most 128)")
     ap.add_argument("--matrix", default="prescribed", choices=["prescribed", "uniform"],
@@ -273,11 +275,11 @@ def run_dense(args, prec):
     sync()
     solver = mixlu.Solver()
     refine = mixlu.REFINE_FGMRES if args.refine == "fgmres" else mixlu.REFINE_CLASSIC
+    kw = dict(refine=refine, restart=args.restart, nb=args.nb)
     for _ in range(args.warmup):
-        solver.dxgesv(A, b, prec, refine=refine, restart=args.restart)
+        solver.dxgesv(A, b, prec, **kw)
     mixlu.mixlu_profile_enable(solver.ctx, True)
-    ms, res = time_calls(lambda: solver.dxgesv(A, b, prec, refine=refine, restart=args.restart),
-                         args.steps)
+    ms, res = time_calls(lambda: solver.dxgesv(A, b, prec, **kw), args.steps)
     history = mixlu.mixlu_refine_history(solver.ctx)
     kst = mixlu.mixlu_profile_read(solver.ctx)
     mixlu.mixlu_profile_enable(solver.ctx, False)
@@ -301,7 +303,8 @@ def run_dense(args, prec):
                                 if args.matrix == "prescribed" else f"dense_nonsym_uniform_n{n}_nrhs1"),
                    "n": n, "kappa": kappa, "nrhs": 1, "seed": seed, "factor_precision": prec,
                    "refinement": "fp64 " + args.refine
-                   + (f" restart {args.restart}" if args.refine == "fgmres" and args.restart else "")},
+                   + (f" restart {args.restart}" if args.refine == "fgmres" and args.restart else ""),
+                   **({"nb": args.nb} if args.nb else {})},
         "solve": {"iter": rep["iter"], "prec_used": rep["prec"], "converged": rep["converged"],
                   "berr": rep["berr"], "fwd_err_vs_x_true": fwd,
                   "residual_history": [float(f"{v:.3e}") for v in history[:40]]}}
