@@ -1210,6 +1210,7 @@ struct SparseLayout {
     size_t y;       // least-squares solution staged for the basis update (doubles)
     size_t part;    // partial sums of the dot products
     size_t norms;   // ||r||_inf, ||x||_inf
+    size_t gm;      // inner GMRES least-squares state (doubles), then its two status ints
     size_t total;
 };
 
@@ -1234,6 +1235,7 @@ size_t plan_sparse(SparseLayout &S, int inner_prec, int n, int nnz, int m_out, i
     S.y = take((size_t)mh * 8);
     S.part = take((size_t)mh * kVdotsChunks * 8);
     S.norms = take(4 * 8);
+    S.gm = take(gmres_state_doubles(m_in > 0 ? m_in : 1) * 8 + 16);
     S.total = off;
     return off;
 }
@@ -1296,61 +1298,49 @@ int arnoldi_orth(mixlu_ctx_s *ctx, int n, int k, const T *V, T *w, T *hdev, T *p
 }
 
 // One GMRES(m) cycle from z = 0 for A z = v in precision T (values vals_t),
-// v given in FP64 (v64); z (FP64) = V y.  Returns the steps taken in *steps.
+// v given in FP64 (v64); z (FP64) = V y.  Everything stays on the device:
+// the Arnoldi vectors, the Givens rotations and the stopping test (the
+// rotated residual against eps_rel ||v||) in k_gmres_col, and the back
+// substitution, so the cycle is enqueued without a host round trip; the
+// steps after an early stop still run but touch only vectors the update
+// leaves out (it uses the steps taken, from the device).
 template <typename T>
 int inner_gmres(mixlu_ctx_s *ctx, const SparseLayout &S, void *work, int n, int nnz,
                 const int *rowptr, const int *colind, const T *vals_t, const double *v64,
-                double *z64, int m, int *steps) {
+                double *z64, int m) {
     hipStream_t s = ctx->stream;
     const size_t nn = (size_t)n;
     T *Vi = at<T>(work, S.Vi), *w = at<T>(work, S.wi);
     T *hdev = at<T>(work, S.h);
+    T *part = at<T>(work, S.part);
     double *ydev = at<double>(work, S.y);
+    double *G = at<double>(work, S.gm);
+    int *st = reinterpret_cast<int *>(G + gmres_state_doubles(m));
     const double eps_rel = sizeof(T) == 4 ? 0x1p-24 : 0x1p-53;
-    *steps = 0;
     // V_0 = v / ||v||
     HIPCK((launch_convert_vec<double, T>(nn, v64, w, s)));
-    std::vector<double> col(m + 1), H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1, 0.0),
-        y(m);
-    double beta = 0.0;
-    {
-        T *hn = hdev;
-        HIPCK(launch_vdots<T>(n, 1, w, nn, w, hn, at<T>(work, S.part), s));
-        T *hb = reinterpret_cast<T *>(ctx->hbuf);
-        HIPCK(hipMemcpyAsync(hb, hn, sizeof(T), hipMemcpyDeviceToHost, s));
-        HIPCK(hipStreamSynchronize(s));
-        beta = std::sqrt((double)hb[0]);
-        if (!(beta > 0.0)) {
-            HIPCK(launch_fill_f64(z64, 0.0, nn, s));
-            return MIXLU_OK;
-        }
-        HIPCK(launch_vscale<T>(n, w, hn, Vi, s));
-    }
-    g[0] = beta;
-    int k = 0;
+    HIPCK(launch_vdots<T>(n, 1, w, nn, w, hdev, part, s));
+    HIPCK(launch_gmres_init<T>(hdev, G, m, st, s));
+    HIPCK(launch_vscale<T>(n, w, hdev, Vi, s));
     for (int j = 0; j < m; ++j) {
         {
             ProfScope ps(PC_SPMV, 2.0 * nnz, (double)nnz * (sizeof(T) + 4) + 2.0 * nn * sizeof(T), s);
             HIPCK(launch_csr_spmv<T>(n, rowptr, colind, vals_t, Vi + (size_t)j * nn, w, s));
         }
-        double wn = 0.0;
-        RETCK(arnoldi_orth<T>(ctx, n, j + 1, Vi, w, hdev, at<T>(work, S.part), col, wn));
-        for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = col[i];
-        H[(size_t)(j + 1) * m + j] = wn;
-        givens_column(H, m, j, cs, sn, g);
-        k = j + 1;
-        if (!(wn > 0.0) || std::fabs(g[j + 1]) <= eps_rel * beta) break;
-        if (j + 1 < m)
-            HIPCK(launch_vscale<T>(n, w, hdev + 2 * (j + 1), Vi + (size_t)(j + 1) * nn, s));
+        // Gram-Schmidt twice against V_0..V_j, then ||w||^2
+        const int k = j + 1;
+        T *h1 = hdev, *h2 = hdev + k, *hn = hdev + 2 * k;
+        HIPCK(launch_vdots<T>(n, k, Vi, nn, w, h1, part, s));
+        HIPCK(launch_vcombine<T>(n, k, Vi, nn, h1, w, s));
+        HIPCK(launch_vdots<T>(n, k, Vi, nn, w, h2, part, s));
+        HIPCK(launch_vcombine<T>(n, k, Vi, nn, h2, w, s));
+        HIPCK(launch_vdots<T>(n, 1, w, nn, w, hn, part, s));
+        HIPCK(launch_gmres_col<T>(hdev, G, m, j, eps_rel, st, s));
+        if (j + 1 < m) HIPCK(launch_vscale<T>(n, w, hn, Vi + (size_t)(j + 1) * nn, s));
     }
-    back_substitute(H, m, k, g, y);
-    double *hy = ctx->hbuf + 2048;  // staging well past the words read back above
-    for (int i = 0; i < k; ++i) hy[i] = y[i];
-    HIPCK(hipMemcpyAsync(ydev, hy, (size_t)k * 8, hipMemcpyHostToDevice, s));
+    HIPCK(launch_gmres_backsub(G, m, st, ydev, s));
     HIPCK(launch_fill_f64(z64, 0.0, nn, s));
-    HIPCK((launch_vaxpy_basis<T, double>(n, k, Vi, nn, ydev, z64, s)));
-    HIPCK(hipStreamSynchronize(s));  // hy is reused by the next call
-    *steps = k;
+    HIPCK((launch_vaxpy_basis<T, double>(n, m, Vi, nn, ydev, z64, s, st)));
     return MIXLU_OK;
 }
 
@@ -1427,9 +1417,8 @@ int sparse_solve(mixlu_ctx_s *ctx, const SparseLayout &S, void *work, int n, int
         HIPCK(launch_vscale<double>(n, r, hdev, Vo, s));
         int k = 0;
         for (int j = 0; j < m_out; ++j) {
-            int st = 0;
             RETCK(inner_gmres<T>(ctx, S, work, n, nnz, rowptr, colind, vals_t,
-                                 Vo + (size_t)j * nn, Zo + (size_t)j * nn, m_in, &st));
+                                 Vo + (size_t)j * nn, Zo + (size_t)j * nn, m_in));
             ++inner_calls;
             {
                 ProfScope ps(PC_SPMV, 2.0 * nnz, (double)nnz * 12 + 2.0 * nn * 8, s);

@@ -382,7 +382,16 @@ template <typename T>
 hipError_t launch_vscale(int n, const T *x, const T *den, T *y, hipStream_t s);
 template <typename TZ, typename TX>
 hipError_t launch_vaxpy_basis(int n, int k, const TZ *Z, size_t ldz, const double *y, TX *x,
-                              hipStream_t s);
+                              hipStream_t s, const int *kdev = nullptr);
+// inner GMRES least squares on the device: G holds H ((m + 1) x m), cs, sn,
+// g and beta; st[0] = running, st[1] = steps taken
+constexpr size_t gmres_state_doubles(int m) { return (size_t)(m + 1) * m + 3 * (size_t)m + 2; }
+template <typename T>
+hipError_t launch_gmres_init(const T *hn, double *G, int m, int *st, hipStream_t s);
+template <typename T>
+hipError_t launch_gmres_col(const T *h, double *G, int m, int j, double eps_rel, int *st,
+                            hipStream_t s);
+hipError_t launch_gmres_backsub(const double *G, int m, const int *st, double *y, hipStream_t s);
 
 // kappa_1 estimate (k_condest.hip)
 hipError_t launch_cond_start(double *x, int n, int alt, hipStream_t s);

@@ -13,6 +13,9 @@
 //   k_vcombine      w -= sum_j h[j] V_j  (one pass of Gram-Schmidt)
 //   k_vscale        y = x / ||w||_2 (the squared norm from device memory)
 //   k_vaxpy_basis   x += sum_j y[j] Z_j (the FGMRES update, FP64)
+//   k_gmres_*       the small least-squares part of an inner GMRES cycle
+//                   on the device (Givens rotations, stopping test, back
+//                   substitution), so the cycle runs without the host
 #include "common.h"
 
 namespace mixlu {
@@ -134,16 +137,86 @@ __global__ __launch_bounds__(256) void k_vscale(int n, const T *__restrict__ x,
     if (i < n) y[i] = x[i] / sqrt(sq[0]);
 }
 
-// x += sum_{j < k} y[j] Z_j, y from host-written device memory
+// x += sum_{j < k} y[j] Z_j, y in device memory; kdev (optional): the
+// number of terms is min(k, kdev[1]) (the steps an inner cycle took)
 template <typename TZ, typename TX>
 __global__ __launch_bounds__(256) void k_vaxpy_basis(int n, int k, const TZ *__restrict__ Z,
                                                      size_t ldz, const double *__restrict__ y,
-                                                     TX *__restrict__ x) {
+                                                     TX *__restrict__ x,
+                                                     const int *__restrict__ kdev) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
+    const int kk = kdev && kdev[1] < k ? kdev[1] : k;
     double s = 0.0;
-    for (int j = 0; j < k; ++j) s += y[j] * (double)Z[(size_t)j * ldz + i];
+    for (int j = 0; j < kk; ++j) s += y[j] * (double)Z[(size_t)j * ldz + i];
     x[i] = (TX)((double)x[i] + s);
+}
+
+// Inner GMRES(m) least-squares state in G (doubles): H ((m + 1) x m,
+// row-major), cs[m], sn[m], g[m + 1], beta; st[0] = 1 while the cycle
+// runs, st[1] = steps taken.  One thread does the O(m) work of a step.
+__device__ __forceinline__ double *gm_H(double *G) { return G; }
+__device__ __forceinline__ size_t gm_cs(int m) { return (size_t)(m + 1) * m; }
+template <typename T>
+__global__ void k_gmres_init(const T *__restrict__ hn, double *__restrict__ G, int m,
+                             int *__restrict__ st) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double beta = sqrt((double)hn[0]);
+    const size_t cs = gm_cs(m), sn = cs + m, g = sn + m, b = g + m + 1;
+    for (size_t i = 0; i < b; ++i) G[i] = 0.0;
+    G[g] = beta;
+    G[b] = beta;
+    st[0] = beta > 0.0 ? 1 : 0;
+    st[1] = 0;
+}
+// step j: column j of H from the two Gram-Schmidt passes h[0..j] and
+// h[j+1..2j+1] and the squared norm h[2j+2] of the new vector; the earlier
+// rotations, a new one, g; the cycle ends when the new vector vanishes or
+// the rotated residual |g[j+1]| falls to eps_rel beta
+template <typename T>
+__global__ void k_gmres_col(const T *__restrict__ h, double *__restrict__ G, int m, int j,
+                            double eps_rel, int *__restrict__ st) {
+    if (threadIdx.x != 0 || blockIdx.x != 0 || st[0] == 0) return;
+    const int k = j + 1;
+    double *H = gm_H(G);
+    double *cs = G + gm_cs(m), *sn = cs + m, *g = sn + m;
+    const double beta = g[m + 1];
+    for (int i = 0; i < k; ++i) H[(size_t)i * m + j] = (double)h[i] + (double)h[k + i];
+    const double wn = sqrt((double)h[2 * k]);
+    H[(size_t)k * m + j] = wn;
+    for (int i = 0; i < j; ++i) {
+        const double a = H[(size_t)i * m + j], b2 = H[(size_t)(i + 1) * m + j];
+        H[(size_t)i * m + j] = cs[i] * a + sn[i] * b2;
+        H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * b2;
+    }
+    const double a = H[(size_t)j * m + j], b2 = H[(size_t)k * m + j];
+    double c = 1.0, sv = 0.0;
+    if (b2 != 0.0) {
+        const double r = hypot(a, b2);
+        c = a / r;
+        sv = b2 / r;
+    }
+    cs[j] = c;
+    sn[j] = sv;
+    H[(size_t)j * m + j] = c * a + sv * b2;
+    H[(size_t)k * m + j] = 0.0;
+    g[k] = -sv * g[j];
+    g[j] = c * g[j];
+    st[1] = k;
+    if (!(wn > 0.0) || fabs(g[k]) <= eps_rel * beta || k == m) st[0] = 0;
+}
+// y solving the st[1] x st[1] upper triangle of the rotated H against g
+__global__ void k_gmres_backsub(const double *__restrict__ G, int m, const int *__restrict__ st,
+                                double *__restrict__ y) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double *H = G;
+    const double *g = G + gm_cs(m) + 2 * (size_t)m;
+    const int k = st[1];
+    for (int i = k - 1; i >= 0; --i) {
+        double sacc = g[i];
+        for (int q = i + 1; q < k; ++q) sacc -= H[(size_t)i * m + q] * y[q];
+        y[i] = sacc / H[(size_t)i * m + i];
+    }
 }
 
 // ------------------------------------------------------------ launchers
@@ -204,11 +277,32 @@ hipError_t launch_vscale(int n, const T *x, const T *den, T *y, hipStream_t s) {
 }
 template <typename TZ, typename TX>
 hipError_t launch_vaxpy_basis(int n, int k, const TZ *Z, size_t ldz, const double *y, TX *x,
-                              hipStream_t s) {
+                              hipStream_t s, const int *kdev) {
     if (n <= 0 || k <= 0) return hipSuccess;
-    k_vaxpy_basis<TZ, TX><<<blocks_of(n), 256, 0, s>>>(n, k, Z, ldz, y, x);
+    k_vaxpy_basis<TZ, TX><<<blocks_of(n), 256, 0, s>>>(n, k, Z, ldz, y, x, kdev);
     return hipGetLastError();
 }
+template <typename T>
+hipError_t launch_gmres_init(const T *hn, double *G, int m, int *st, hipStream_t s) {
+    k_gmres_init<T><<<1, 64, 0, s>>>(hn, G, m, st);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_gmres_col(const T *h, double *G, int m, int j, double eps_rel, int *st,
+                            hipStream_t s) {
+    k_gmres_col<T><<<1, 64, 0, s>>>(h, G, m, j, eps_rel, st);
+    return hipGetLastError();
+}
+hipError_t launch_gmres_backsub(const double *G, int m, const int *st, double *y, hipStream_t s) {
+    k_gmres_backsub<<<1, 64, 0, s>>>(G, m, st, y);
+    return hipGetLastError();
+}
+template hipError_t launch_gmres_init<float>(const float *, double *, int, int *, hipStream_t);
+template hipError_t launch_gmres_init<double>(const double *, double *, int, int *, hipStream_t);
+template hipError_t launch_gmres_col<float>(const float *, double *, int, int, double, int *,
+                                            hipStream_t);
+template hipError_t launch_gmres_col<double>(const double *, double *, int, int, double, int *,
+                                             hipStream_t);
 
 template hipError_t launch_csr_spmv<float>(int, const int *, const int *, const float *,
                                            const float *, float *, hipStream_t);
@@ -230,8 +324,10 @@ template hipError_t launch_vscale<float>(int, const float *, const float *, floa
 template hipError_t launch_vscale<double>(int, const double *, const double *, double *,
                                           hipStream_t);
 template hipError_t launch_vaxpy_basis<float, double>(int, int, const float *, size_t,
-                                                      const double *, double *, hipStream_t);
+                                                      const double *, double *, hipStream_t,
+                                                      const int *);
 template hipError_t launch_vaxpy_basis<double, double>(int, int, const double *, size_t,
-                                                       const double *, double *, hipStream_t);
+                                                       const double *, double *, hipStream_t,
+                                                       const int *);
 
 }  // namespace mixlu
