@@ -388,10 +388,8 @@ int factor_lu(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t woff, int tr
                 double fl = 0.0;
                 for (int j = 0; j < B; ++j) fl += (m - j - 1) * (1.0 + 2.0 * (B - j - 1));
                 ProfScope ps(PC_PANEL, fl, 2.0 * m * B * sizeof(T), s);
-                HIPCK(launch_panel<T>(W, np, k, np - k, ipiv, xbuf, status, s));
+                HIPCK(launch_panel<T>(W, np, k, np - k, ipiv, xbuf, status, s, perm, K0, kend));
             }
-            HIPCK(launch_row_swaps<T>(ipiv, k, B, np, perm, W, np, K0, kend, k, k + B, nullptr,
-                                      s));
             if (k + B < kend) {
                 HIPCK(launch_trsm_diag<T>(Wp(k, k), np, Wp(k, k + B), np, kend - k - B, s));
                 HIPCK(launch_gemm<T>(np - k - B, kend - k - B, B, Wp(k + B, k), np, Wp(k, k + B),

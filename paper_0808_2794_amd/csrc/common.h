@@ -294,9 +294,13 @@ hipError_t launch_convert_stats(const double *A, int lda, int n, int npad, Tw *W
                                 hipStream_t s);
 
 // a3: factorization kernels (k_lu.hip)
+// GEPP of the B columns at (k0, k0) over m rows; with perm or sc1 > sc0 its
+// interchanges are also applied to the columns [sc0, sc1) outside the panel
+// (sc0 <= k0, sc1 >= k0 + B) and to perm
 template <typename T>
 hipError_t launch_panel(T *W, int ldw, int k0, int m, int *ipiv, unsigned long long *xb,
-                        int *status, hipStream_t s);
+                        int *status, hipStream_t s, int *perm = nullptr, int sc0 = 0,
+                        int sc1 = 0);
 // pivots ipiv[k0 .. k0+cnt-1] applied to the columns [c0, c1) minus
 // [skip0, skip1) of W, and to perm when given, in one launch
 template <typename T>

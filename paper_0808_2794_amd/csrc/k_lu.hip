@@ -6,6 +6,8 @@
 //                 per column: argmax (first index on ties), the candidate
 //                 rows published as tagged words and gathered by one wave,
 //                 swap, scale; the rank-1 update overlaps the exchange.
+//                 The panel's own interchanges on the other columns of its
+//                 block (and on perm) run at the end of the same launch.
 //   k_row_swaps   applies a block of pivots to the columns outside the panel
 //   k_swaps_compose, k_rows_apply: the same for wide blocks, in two launches
 //   k_trsm_diag   X = L^{-1} X with a unit lower diagonal block in LDS
@@ -134,7 +136,8 @@ template <typename T, int B>
 __global__ __launch_bounds__(kPanelTPB) void k_panel(T *__restrict__ W, int ldw, int k0, int m,
                                                      int *__restrict__ ipiv,
                                                      unsigned long long *__restrict__ xb,
-                                                     int *__restrict__ status, int P, int stride) {
+                                                     int *__restrict__ status, int P, int stride,
+                                                     int *__restrict__ perm, int sc0, int sc1) {
     if (blockIdx.x % stride) return;
     const int w = blockIdx.x / stride;
     if (w >= P) return;
@@ -180,6 +183,82 @@ __global__ __launch_bounds__(kPanelTPB) void k_panel(T *__restrict__ W, int ldw,
                 for (int e = 0; e < V; ++e) a[b][q * V + e] = v[e];
             }
     }
+    // The panel's interchanges on the columns [sc0, sc1) outside it and on
+    // perm are applied at the end from LDS: the words of this workgroup's
+    // slice of those columns (nd <= 64, one per lane) of every row that moves
+    // are read while the pivots are chosen.  Slot i < B holds row i of the
+    // panel, slot B + j the pivot row of column j when it lies below row B.
+    // Nothing writes these columns during the launch, so every read sees the
+    // rows as they were before the interchanges.  The waves that do not poll
+    // take turns: a pivot row read into a register is written to LDS at that
+    // wave's next turn, long after it has arrived.
+    const bool swp = perm != nullptr || sc1 > sc0;
+    const int ncols = sc1 > sc0 ? sc1 - sc0 - B : 0;
+    const int cpw = (ncols + P - 1) / P;
+    const int lc0 = w * cpw;
+    const int nd = max(0, min(cpw, ncols - lc0)) * PWV;
+    const int nleft = k0 - sc0;
+    __shared__ __attribute__((aligned(16))) unsigned s_rows[2 * B][64];
+    __shared__ int s_pm[2 * B];
+    const unsigned *Wd = reinterpret_cast<const unsigned *>(W);
+    int lword = 0;  // this lane's word of a row of the slice
+    if (lane < nd) {
+        const int c = lc0 + lane / PWV;
+        lword = (sc0 + c + (c >= nleft ? B : 0)) * PWV + lane % PWV;
+    }
+    const bool fetcher = swp && wave < GW;
+    const bool pfetch = perm != nullptr && w == 0;
+    constexpr int TR = (B + GW - 1) / GW;  // top rows per fetching wave
+    unsigned rtop[TR];
+    int ptop = 0;
+    if (fetcher) {
+#pragma unroll
+        for (int i = 0; i < TR; ++i) {
+            const int r = wave + GW * i;
+            rtop[i] = (r < B && lane < nd) ? Wd[(size_t)(k0 + r) * ldw * PWV + lword] : 0u;
+        }
+    }
+    if (pfetch && tid < B) ptop = perm[k0 + tid];
+    if (fetcher) {
+#pragma unroll
+        for (int i = 0; i < TR; ++i) {
+            const int r = wave + GW * i;
+            if (r < B) s_rows[r][lane] = rtop[i];
+        }
+    }
+    if (pfetch && tid < B) s_pm[tid] = ptop;
+    unsigned rpiv = 0u;  // this wave's last pivot row word, bound for slot spend
+    int ppiv = 0, spend = -1;
+    // Wave 0 composes the swaps into moves (position <- slot) one column
+    // behind, while it waits for the gather: position i < B is lane i of ca,
+    // position cpos[t] >= B (t the first column whose pivot row it is) lane t
+    // of cb; each holds the slot whose row ends there.
+    int ca = lane, cb = B + lane, cpos = -1;
+    int jprev = -1, pprev = 0;  // the last column and its pivot row
+    auto compose = [&](int t, int qt) __attribute__((always_inline)) {
+        if (qt == t) return;
+        int sl = qt;
+        if (qt >= B) {
+            const unsigned long long hit = __ballot(cpos == qt);
+            if (hit) {
+                sl = B + __ffsll((long long)hit) - 1;
+            } else {
+                sl = B + t;
+                if (lane == t) cpos = qt;
+            }
+        }
+        // selects only (a branch on which register to write makes the
+        // compiler put the pair in scratch)
+        const bool low = sl < B;
+        const int ls = low ? sl : sl - B;
+        const int at = __builtin_amdgcn_readlane(ca, t);
+        const int va = __builtin_amdgcn_readlane(ca, ls), vb = __builtin_amdgcn_readlane(cb, ls);
+        const int aq = low ? va : vb;
+        ca = lane == t ? aq : ca;
+        ca = (low && lane == ls) ? at : ca;
+        cb = (!low && lane == ls) ? at : cb;
+    };
+
     T lp = (T)0;      // pending multiplier of the previous pivot row
     T nu[NG];         // that row negated, lane-replicated: nu[b] = -u[16 (g + b) + lane % 16]
 #pragma unroll
@@ -285,6 +364,7 @@ __global__ __launch_bounds__(kPanelTPB) void k_panel(T *__restrict__ W, int ldw,
                     if (b < NG - g) BcastFma<T>::block(a[b], nu[b], lp);
             }
             lp = (T)0;
+            if (swp && wave == 0 && jprev >= 0) compose(jprev, pprev);
             // --- 4. gather (last wave): headers and row j, then the winner's row
             if (P > 1 && wave == GW) {
                 bool bad = false;
@@ -370,6 +450,17 @@ __global__ __launch_bounds__(kPanelTPB) void k_panel(T *__restrict__ W, int ldw,
                 piv = drow[j];
                 rcp = (T)1 / piv;
             }
+            jprev = j;
+            pprev = p;
+            if (fetcher && p >= B && wave == j % GW) {
+                if (spend >= 0) {
+                    s_rows[spend][lane] = rpiv;
+                    if (pfetch && lane == 0) s_pm[spend] = ppiv;
+                }
+                rpiv = lane < nd ? Wd[(size_t)(k0 + p) * ldw * PWV + lword] : 0u;
+                if (pfetch && lane == 0) ppiv = perm[k0 + p];
+                spend = B + j;
+            }
             const bool normal = fabs(piv) >= tiny && isfinite(piv);
             // no global stores inside the loop: the pivots are kept in LDS
             if (tid == 0) s_piv[j] = (!(piv != (T)0) || !isfinite(piv)) ? -(p + 1) : p;
@@ -413,6 +504,10 @@ __global__ __launch_bounds__(kPanelTPB) void k_panel(T *__restrict__ W, int ldw,
         nu[NG - 1] = n0;
     }
     if (dead) return;  // uniform: every thread saw the same gather result
+    if (spend >= 0) {
+        s_rows[spend][lane] = rpiv;
+        if (pfetch && lane == 0) s_pm[spend] = ppiv;
+    }
     if (live) {
         using vq = typename Vq<T>::type;
         constexpr int V = Vq<T>::V;
@@ -433,6 +528,38 @@ __global__ __launch_bounds__(kPanelTPB) void k_panel(T *__restrict__ W, int ldw,
         ipiv[k0 + tid] = k0 + (v < 0 ? -v - 1 : v);
         if (v < 0) atomicMin(&status[ST_BREAKDOWN], k0 + tid + 1);
     }
+    if (!swp) return;
+    __shared__ int s_mv[4 * B];
+    __shared__ int s_nmv;
+    if (wave == 0) {
+        if (jprev >= 0) compose(jprev, pprev);
+        const bool ma = lane < B && ca != lane;
+        const bool mb = cpos >= 0 && cb != B + lane;
+        const unsigned long long ba = __ballot(ma), bb = __ballot(mb);
+        const unsigned long long below = (1ull << lane) - 1ull;
+        const int na = __popcll(ba);
+        if (ma) {
+            const int i = __popcll(ba & below);
+            s_mv[2 * i] = k0 + lane;
+            s_mv[2 * i + 1] = ca;
+        }
+        if (mb) {
+            const int i = na + __popcll(bb & below);
+            s_mv[2 * i] = k0 + cpos;
+            s_mv[2 * i + 1] = cb;
+        }
+        if (lane == 0) s_nmv = na + __popcll(bb);
+    }
+    __syncthreads();
+    const int count = s_nmv;
+    if (perm && w == 0 && tid < count) perm[s_mv[2 * tid]] = s_pm[s_mv[2 * tid + 1]];
+    for (int e = tid; e < count * nd; e += TPB) {
+        const int mq = e / nd, d = e % nd;
+        const int c = lc0 + d / PWV;
+        const int col = sc0 + c + (c >= nleft ? B : 0);
+        reinterpret_cast<unsigned *>(W + (size_t)s_mv[2 * mq] * ldw + col)[d % PWV] =
+            s_rows[s_mv[2 * mq + 1]][d];
+    }
 }
 
 template <typename T> struct PanelWidth;
@@ -441,21 +568,30 @@ template <> struct PanelWidth<double> { static constexpr int v = kPanelBD; };
 
 template <typename T>
 hipError_t launch_panel(T *W, int ldw, int k0, int m, int *ipiv, unsigned long long *xb,
-                        int *status, hipStream_t s) {
+                        int *status, hipStream_t s, int *perm, int sc0, int sc1) {
     constexpr int B = PanelWidth<T>::v;
     const int P = (m + kPanelRowsPerWG - 1) / kPanelRowsPerWG;
     if (P < 1 || P > kPanelMaxWG || m < B) return hipErrorInvalidValue;
+    const bool swaps = perm != nullptr || sc1 > sc0;
+    if (swaps && (sc0 > k0 || sc1 < k0 + B)) return hipErrorInvalidValue;
     // workers are dealt round-robin over the 8 XCDs: with stride 8 all of them
     // land on one XCD (32 CUs) and exchange through its L2
     const int stride = P == 1 ? 1 : (P <= 32 ? kXcdStride : kXcdStride / 2);
-    k_panel<T, B><<<dim3(P * stride), dim3(kPanelTPB), 0, s>>>(W, ldw, k0, m, ipiv, xb, status,
-                                                               P, stride);
-    return hipGetLastError();
+    // the interchanges ride in the panel launch when each workgroup's slice
+    // is at most 64 words wide; otherwise they get a launch of their own
+    const bool fuse = swaps && (sc1 - sc0 - B + P - 1) / P * (int)(sizeof(T) / 4) <= 64;
+    k_panel<T, B><<<dim3(P * stride), dim3(kPanelTPB), 0, s>>>(
+        W, ldw, k0, m, ipiv, xb, status, P, stride, fuse ? perm : nullptr, fuse ? sc0 : 0,
+        fuse ? sc1 : 0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !swaps || fuse) return e;
+    return launch_row_swaps<T>(ipiv, k0, B, k0 + m, perm, W, ldw, sc0, sc1, k0, k0 + B, nullptr,
+                               s);
 }
 template hipError_t launch_panel<float>(float *, int, int, int, int *, unsigned long long *,
-                                        int *, hipStream_t);
+                                        int *, hipStream_t, int *, int, int);
 template hipError_t launch_panel<double>(double *, int, int, int, int *, unsigned long long *,
-                                         int *, hipStream_t);
+                                         int *, hipStream_t, int *, int, int);
 
 // ======================================================================
 // Row interchanges outside the panel

@@ -2,7 +2,8 @@
 configuration the benchmark times (default options, one solve call).
 
 * dense nonsymmetric n = 8192, A = U diag(sigma) V^T: FP32 factor at
-  kappa = 1e4 and FP16 trailing-update operands at kappa = 1e2, each against
+  kappa = 1e4, FP16 trailing-update operands at kappa = 1e2 and the FP64
+  factor at kappa = 1e4, each against
   the oracle's FP64 refinement (G2: forward error <= 1e-12 kappa) and the
   stopping test of Section 3 with the residual recomputed on the CPU in
   extended precision (G1);
@@ -51,7 +52,8 @@ def _g1_g2(A, b, x, kappa, x_ref=None, x_true=None):
     return m
 
 
-@pytest.mark.parametrize("prec,kappa,seed", [("fp32", 1e4, 212), ("fp16", 1e2, 211)])
+@pytest.mark.parametrize("prec,kappa,seed", [("fp32", 1e4, 212), ("fp16", 1e2, 211),
+                                             ("fp64", 1e4, 213)])
 def test_dense_n8192(solver, prec, kappa, seed):
     import torch
 

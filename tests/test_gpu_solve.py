@@ -194,19 +194,22 @@ def test_outer_block_widths(solver, nb, prec):
     _check(A, b, r.x.cpu().numpy(), kappa, ref.x)
 
 
-def test_factor_is_partial_pivoting(solver):
+@pytest.mark.parametrize("n,nb", [(1200, 512), (4100, 512), (2100, 256)])
+def test_factor_is_partial_pivoting(solver, n, nb):
     """Factors read back from the workspace: P A = L U to FP32 accuracy and
     every multiplier |l_ij| <= 1 (the partial-pivoting property: each pivot was
-    the largest entry of its column), including multi-workgroup panels."""
+    the largest entry of its column), including multi-workgroup panels.  The
+    sizes take the panel's interchanges on the rest of its outer block both
+    ways: in a launch of their own (few panel workgroups, wide slices) and
+    inside the panel launch."""
     import torch
 
     from paper_0808_2794_amd import mixlu
 
-    n = 1200
     A, _, _ = gen.uniform_system(n, 55)
-    _say("getrf fp32 n=1200 readback")
+    _say(f"getrf fp32 n={n} nb={nb} readback")
     (Ad,) = _to_dev(A)
-    o = mixlu.default_opts(equilibrate=0)
+    o = mixlu.default_opts(equilibrate=0, nb=nb)
     work = solver.workspace(mixlu.OP_GESV, mixlu.FP32, n, 1, o)
     F, info = mixlu.mixlu_getrf(solver.ctx, mixlu.FP32, Ad, work, o)
     assert info == 0 and F.lowp_status == 0
