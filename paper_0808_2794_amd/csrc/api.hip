@@ -207,7 +207,7 @@ size_t mixlu::plan_layout(Layout &L, int op, int prec, int n, int nrhs, const mi
     L.vec_z = L.nrhs > 1 ? take(np * L.nrhs * 8) : L.vec_y;
     L.xbuf = take((size_t)kXbufWords * 8);
     L.ybuf = take((np * kTrsvNRT * 2 + 64) * 8);
-    L.moves = take((size_t)2 * kMovesInts * 4);
+    L.moves = take((size_t)(2 * kMovesInts + kPanelListInts) * 4);  // + the panels' lists
     L.tmp = take((size_t)(2 * kColChunks + 2) * np * 8);
     L.status = take(ST_COUNT * 4);
     L.norms = take((size_t)(4 + 3 * L.nrhs) * 8);
@@ -304,6 +304,7 @@ int factor_lu(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t woff, int tr
     // row-move lists of the wide (outer) pivot blocks, one per parity: the
     // side stream may still apply block K's while block K+1 composes
     int *moves2[2] = {at<int>(work, L.moves), at<int>(work, L.moves) + kMovesInts};
+    int *plist = at<int>(work, L.moves) + 2 * kMovesInts;  // this block's panels' move lists
     if (nb % B || nb % 64 || nb > kMaxOuterBlock) return MIXLU_ERR_NOT_IMPLEMENTED;
     RETCK(ensure_side(ctx));
     hipStream_t s2 = ctx->side;
@@ -388,7 +389,8 @@ int factor_lu(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t woff, int tr
                 double fl = 0.0;
                 for (int j = 0; j < B; ++j) fl += (m - j - 1) * (1.0 + 2.0 * (B - j - 1));
                 ProfScope ps(PC_PANEL, fl, 2.0 * m * B * sizeof(T), s);
-                HIPCK(launch_panel<T>(W, np, k, np - k, ipiv, xbuf, status, s, perm, K0, kend));
+                HIPCK(launch_panel<T>(W, np, k, np - k, ipiv, xbuf, status, s, perm, K0, kend,
+                                      wide ? plist + (k - K0) / B * kPanelMovesInts : nullptr));
             }
             if (k + B < kend) {
                 HIPCK(launch_trsm_diag<T>(Wp(k, k), np, Wp(k, k + B), np, kend - k - B, s));
@@ -402,13 +404,13 @@ int factor_lu(mixlu_ctx_s *ctx, void *work, const Layout &L, size_t woff, int tr
             // the side stream has finished
             if (side_used) HIPCK(hipStreamWaitEvent(s, ctx->ev_join, 0));
             side_used = false;
-            if (wide) HIPCK(launch_swaps_compose(ipiv, K0, nb, np, nullptr, moves2[par], s));
+            if (wide) HIPCK(launch_swaps_merge(plist, nb / B, kPanelMovesInts, K0, np, moves2[par], s));
             RETCK(swaps(K0, 0, K0, K0, K0, s));
             break;
         }
         const int nx = nr < nb ? nr : nb;  // the next block's columns
         const int rest = nr - nx;
-        if (wide) HIPCK(launch_swaps_compose(ipiv, K0, nb, np, nullptr, moves2[par], s));
+        if (wide) HIPCK(launch_swaps_merge(plist, nb / B, kPanelMovesInts, K0, np, moves2[par], s));
         if (lowp) {
             if constexpr (sizeof(T) == 4) {
                 auto *Ap = at<unsigned char>(work, L.Ap) + pset * pk * 2;

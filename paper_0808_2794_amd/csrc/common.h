@@ -30,6 +30,11 @@ constexpr int kKrylov = 30;         // default flexible GMRES restart length
 constexpr int kKrylovMax = 128;     // longest restart (the Krylov area's capacity)
 constexpr int kMaxOuterBlock = 1024;  // widest outer block (pivots per wide row interchange)
 constexpr int kMovesInts = 4 + 4 * kMaxOuterBlock;  // one composed row-move list
+// one panel's composed interchanges: count, then (destination row, source
+// row) pairs, at most 2 per pivot
+constexpr int kPanelMovesInts = 4 + 4 * kPanelBF;
+// the lists of one outer block's panels (the narrowest panel is kPanelBD)
+constexpr int kPanelListInts = kMaxOuterBlock / kPanelBD * kPanelMovesInts;
 constexpr int kBatchedNmax = 512;   // largest order of a batched system
 constexpr int kBatchedSlots = 512;  // workgroups (and workspace slots) of a batched launch
 
@@ -296,11 +301,12 @@ hipError_t launch_convert_stats(const double *A, int lda, int n, int npad, Tw *W
 // a3: factorization kernels (k_lu.hip)
 // GEPP of the B columns at (k0, k0) over m rows; with perm or sc1 > sc0 its
 // interchanges are also applied to the columns [sc0, sc1) outside the panel
-// (sc0 <= k0, sc1 >= k0 + B) and to perm
+// (sc0 <= k0, sc1 >= k0 + B) and to perm; with pmoves they are also written
+// there as a composed move list (kPanelMovesInts ints)
 template <typename T>
 hipError_t launch_panel(T *W, int ldw, int k0, int m, int *ipiv, unsigned long long *xb,
                         int *status, hipStream_t s, int *perm = nullptr, int sc0 = 0,
-                        int sc1 = 0);
+                        int sc1 = 0, int *pmoves = nullptr);
 // pivots ipiv[k0 .. k0+cnt-1] applied to the columns [c0, c1) minus
 // [skip0, skip1) of W, and to perm when given, in one launch
 template <typename T>
@@ -315,6 +321,11 @@ constexpr int kSwapsFused = 64;
 // the rows of [c0, c1) minus [skip0, skip1) moved by that list.
 hipError_t launch_swaps_compose(const int *ipiv, int k0, int cnt, int npad, int *perm, int *moves,
                                 hipStream_t s);
+// The same composition from the np panels' move lists (plist, stride ints
+// apart, as the panel writes them) of the block whose first row is k0: the
+// lists are applied in order, each in one parallel round.
+hipError_t launch_swaps_merge(const int *plist, int np, int stride, int k0, int npad,
+                              int *moves, hipStream_t s);
 template <typename T>
 hipError_t launch_swaps_apply(T *W, int ldw, const int *moves, int cnt, int c0, int c1, int skip0,
                               int skip1, hipStream_t s);

@@ -137,7 +137,8 @@ __global__ __launch_bounds__(kPanelTPB) void k_panel(T *__restrict__ W, int ldw,
                                                      int *__restrict__ ipiv,
                                                      unsigned long long *__restrict__ xb,
                                                      int *__restrict__ status, int P, int stride,
-                                                     int *__restrict__ perm, int sc0, int sc1) {
+                                                     int *__restrict__ perm, int sc0, int sc1,
+                                                     int *__restrict__ pmv) {
     if (blockIdx.x % stride) return;
     const int w = blockIdx.x / stride;
     if (w >= P) return;
@@ -193,6 +194,7 @@ __global__ __launch_bounds__(kPanelTPB) void k_panel(T *__restrict__ W, int ldw,
     // take turns: a pivot row read into a register is written to LDS at that
     // wave's next turn, long after it has arrived.
     const bool swp = perm != nullptr || sc1 > sc0;
+    const bool cmp = swp || pmv != nullptr;  // compose the swaps
     const int ncols = sc1 > sc0 ? sc1 - sc0 - B : 0;
     const int cpw = (ncols + P - 1) / P;
     const int lc0 = w * cpw;
@@ -364,7 +366,7 @@ __global__ __launch_bounds__(kPanelTPB) void k_panel(T *__restrict__ W, int ldw,
                     if (b < NG - g) BcastFma<T>::block(a[b], nu[b], lp);
             }
             lp = (T)0;
-            if (swp && wave == 0 && jprev >= 0) compose(jprev, pprev);
+            if (cmp && wave == 0 && jprev >= 0) compose(jprev, pprev);
             // --- 4. gather (last wave): headers and row j, then the winner's row
             if (P > 1 && wave == GW) {
                 bool bad = false;
@@ -528,7 +530,7 @@ __global__ __launch_bounds__(kPanelTPB) void k_panel(T *__restrict__ W, int ldw,
         ipiv[k0 + tid] = k0 + (v < 0 ? -v - 1 : v);
         if (v < 0) atomicMin(&status[ST_BREAKDOWN], k0 + tid + 1);
     }
-    if (!swp) return;
+    if (!cmp) return;
     __shared__ int s_mv[4 * B];
     __shared__ int s_nmv;
     if (wave == 0) {
@@ -537,19 +539,34 @@ __global__ __launch_bounds__(kPanelTPB) void k_panel(T *__restrict__ W, int ldw,
         const bool mb = cpos >= 0 && cb != B + lane;
         const unsigned long long ba = __ballot(ma), bb = __ballot(mb);
         const unsigned long long below = (1ull << lane) - 1ull;
-        const int na = __popcll(ba);
+        const int na = __popcll(ba), nm = na + __popcll(bb);
+        // the rows the slots stand for, for the move list
+        const int qa = __shfl(cpos, (ca - B) & 63), qb = __shfl(cpos, (cb - B) & 63);
+        const bool lst = pmv != nullptr && w == 0;
         if (ma) {
             const int i = __popcll(ba & below);
             s_mv[2 * i] = k0 + lane;
             s_mv[2 * i + 1] = ca;
+            if (lst) {
+                pmv[1 + 2 * i] = k0 + lane;
+                pmv[2 + 2 * i] = k0 + (ca < B ? ca : qa);
+            }
         }
         if (mb) {
             const int i = na + __popcll(bb & below);
             s_mv[2 * i] = k0 + cpos;
             s_mv[2 * i + 1] = cb;
+            if (lst) {
+                pmv[1 + 2 * i] = k0 + cpos;
+                pmv[2 + 2 * i] = k0 + (cb < B ? cb : qb);
+            }
         }
-        if (lane == 0) s_nmv = na + __popcll(bb);
+        if (lane == 0) {
+            s_nmv = nm;
+            if (lst) pmv[0] = nm;
+        }
     }
+    if (!swp) return;
     __syncthreads();
     const int count = s_nmv;
     if (perm && w == 0 && tid < count) perm[s_mv[2 * tid]] = s_pm[s_mv[2 * tid + 1]];
@@ -568,7 +585,7 @@ template <> struct PanelWidth<double> { static constexpr int v = kPanelBD; };
 
 template <typename T>
 hipError_t launch_panel(T *W, int ldw, int k0, int m, int *ipiv, unsigned long long *xb,
-                        int *status, hipStream_t s, int *perm, int sc0, int sc1) {
+                        int *status, hipStream_t s, int *perm, int sc0, int sc1, int *pmoves) {
     constexpr int B = PanelWidth<T>::v;
     const int P = (m + kPanelRowsPerWG - 1) / kPanelRowsPerWG;
     if (P < 1 || P > kPanelMaxWG || m < B) return hipErrorInvalidValue;
@@ -582,16 +599,16 @@ hipError_t launch_panel(T *W, int ldw, int k0, int m, int *ipiv, unsigned long l
     const bool fuse = swaps && (sc1 - sc0 - B + P - 1) / P * (int)(sizeof(T) / 4) <= 64;
     k_panel<T, B><<<dim3(P * stride), dim3(kPanelTPB), 0, s>>>(
         W, ldw, k0, m, ipiv, xb, status, P, stride, fuse ? perm : nullptr, fuse ? sc0 : 0,
-        fuse ? sc1 : 0);
+        fuse ? sc1 : 0, pmoves);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !swaps || fuse) return e;
     return launch_row_swaps<T>(ipiv, k0, B, k0 + m, perm, W, ldw, sc0, sc1, k0, k0 + B, nullptr,
                                s);
 }
 template hipError_t launch_panel<float>(float *, int, int, int, int *, unsigned long long *,
-                                        int *, hipStream_t, int *, int, int);
+                                        int *, hipStream_t, int *, int, int, int *);
 template hipError_t launch_panel<double>(double *, int, int, int, int *, unsigned long long *,
-                                         int *, hipStream_t, int *, int, int);
+                                         int *, hipStream_t, int *, int, int, int *);
 
 // ======================================================================
 // Row interchanges outside the panel
@@ -868,6 +885,66 @@ hipError_t launch_swaps_compose(const int *ipiv, int k0, int cnt, int npad, int 
         attr_done = true;
     }
     k_swaps_compose<<<dim3(1), dim3(1024), lds_c, s>>>(ipiv, k0, cnt, npad, perm, moves);
+    return hipGetLastError();
+}
+
+// The composition of a block's interchanges from its panels' move lists:
+// cur[i] = the row whose content ends at row k0 + i, one parallel round per
+// list (all sources read before any destination is written), then the moved
+// rows gathered into one list as k_swaps_compose writes it.
+__global__ __launch_bounds__(1024) void k_swaps_merge(const int *__restrict__ plist, int np,
+                                                      int stride, int k0, int npad,
+                                                      int *__restrict__ moves) {
+    extern __shared__ int cur[];
+    __shared__ int s_count;
+    const int m = npad - k0;
+    for (int i = threadIdx.x; i < m; i += blockDim.x) cur[i] = i;
+    if (threadIdx.x == 0) s_count = 0;
+    __syncthreads();
+    for (int r = 0; r < np; ++r) {
+        const int *L = plist + (size_t)r * stride;
+        const int cnt = L[0];
+        int d = -1, v = 0;
+        if (threadIdx.x < cnt && threadIdx.x < 2 * kPanelBF) {
+            const int dd = L[1 + 2 * threadIdx.x] - k0, ss = L[2 + 2 * threadIdx.x] - k0;
+            if (dd >= 0 && dd < m && ss >= 0 && ss < m) {  // never index outside [k0, npad)
+                d = dd;
+                v = cur[ss];
+            }
+        }
+        __syncthreads();
+        if (d >= 0) cur[d] = v;
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+        const int src = cur[i];
+        if (src != i) {
+            const int q = atomicAdd(&s_count, 1);
+            if (q < 2 * kMaxOuterBlock) {
+                moves[2 + 2 * q] = k0 + i;
+                moves[3 + 2 * q] = k0 + src;
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) moves[0] = min(s_count, 2 * kMaxOuterBlock);
+}
+
+hipError_t launch_swaps_merge(const int *plist, int np, int stride, int k0, int npad, int *moves,
+                              hipStream_t s) {
+    constexpr size_t kMaxLds = 152 * 1024;
+    if (np < 0 || k0 < 0 || k0 > npad || stride < kPanelMovesInts) return hipErrorInvalidValue;
+    const size_t lds_c = (size_t)(npad - k0) * sizeof(int);
+    if (lds_c > kMaxLds - 24 * 1024) return hipErrorInvalidValue;
+    static bool attr_done = false;
+    if (!attr_done) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_swaps_merge),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)(kMaxLds - 24 * 1024));
+        if (e != hipSuccess) return e;
+        attr_done = true;
+    }
+    k_swaps_merge<<<dim3(1), dim3(1024), lds_c, s>>>(plist, np, stride, k0, npad, moves);
     return hipGetLastError();
 }
 
