@@ -948,19 +948,10 @@ hipError_t launch_swaps_merge(const int *plist, int np, int stride, int k0, int 
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_swaps_apply(T *W, int ldw, const int *moves, int cnt, int c0, int c1, int skip0,
-                              int skip1, hipStream_t s) {
-    constexpr int CW = sizeof(T) == 4 ? 16 : 8;
+template <typename T, int CW>
+hipError_t rows_apply(T *W, int ldw, const int *moves, int cnt, int c0, int nleft, int gap,
+                      int ncols, hipStream_t s) {
     constexpr size_t kMaxLds = 152 * 1024;
-    if (cnt > kMaxOuterBlock || cnt < 0) return hipErrorInvalidValue;
-    if (skip0 < c0) skip0 = c0;
-    if (skip1 > c1) skip1 = c1;
-    if (skip1 < skip0) skip1 = skip0;
-    const int nleft = skip0 - c0;
-    const int gap = skip1 - skip0;
-    const int ncols = (c1 - c0) - gap;
-    if (ncols <= 0) return hipSuccess;
     const size_t lds_a = (size_t)2 * cnt * CW * sizeof(T);
     if (lds_a > kMaxLds) return hipErrorInvalidValue;
     static bool attr_done = false;
@@ -973,6 +964,24 @@ hipError_t launch_swaps_apply(T *W, int ldw, const int *moves, int cnt, int c0, 
     k_rows_apply<T, CW><<<dim3((ncols + CW - 1) / CW), dim3(256), lds_a, s>>>(W, ldw, moves, c0,
                                                                             nleft, gap, ncols);
     return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_swaps_apply(T *W, int ldw, const int *moves, int cnt, int c0, int c1, int skip0,
+                              int skip1, hipStream_t s) {
+    constexpr int CW = sizeof(T) == 4 ? 16 : 8;
+    if (cnt > kMaxOuterBlock || cnt < 0) return hipErrorInvalidValue;
+    if (skip0 < c0) skip0 = c0;
+    if (skip1 > c1) skip1 = c1;
+    if (skip1 < skip0) skip1 = skip0;
+    const int nleft = skip0 - c0;
+    const int gap = skip1 - skip0;
+    const int ncols = (c1 - c0) - gap;
+    if (ncols <= 0) return hipSuccess;
+    // a narrow range (the next block's columns, on the critical path) in
+    // slices of a quarter the width, so that it spreads over more compute units
+    if (ncols <= 2048) return rows_apply<T, CW / 4>(W, ldw, moves, cnt, c0, nleft, gap, ncols, s);
+    return rows_apply<T, CW>(W, ldw, moves, cnt, c0, nleft, gap, ncols, s);
 }
 template hipError_t launch_swaps_apply<float>(float *, int, const int *, int, int, int, int, int,
                                               hipStream_t);
