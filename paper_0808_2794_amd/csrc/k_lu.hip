@@ -794,27 +794,37 @@ __global__ __launch_bounds__(1024) void k_swaps_compose(const int *__restrict__ 
 template <typename T, int CW>
 __global__ __launch_bounds__(256) void k_rows_apply(T *__restrict__ W, int ldw,
                                                     const int *__restrict__ moves, int c0,
-                                                    int nleft, int gap, int ncols) {
+                                                    int nleft, int gap, int ncols, int mvmax) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    T *buf = reinterpret_cast<T *>(smem);
-    const int count = moves[0];
+    T *buf = reinterpret_cast<T *>(smem);                             // mvmax * CW values
+    int *smv = reinterpret_cast<int *>(buf + (size_t)mvmax * CW);    // the move list
+    const int count = min(moves[0], mvmax);
+    for (int i = threadIdx.x; i < 2 * count; i += 256) smv[i] = moves[2 + i];
+    __syncthreads();
     const int lc0 = blockIdx.x * CW;
-    for (int e = threadIdx.x; e < count * CW; e += 256) {
-        const int q = e / CW, cc = e % CW;
-        const int lc = lc0 + cc;
-        if (lc < ncols) {
-            const int col = c0 + lc + (lc >= nleft ? gap : 0);
-            buf[e] = W[(size_t)moves[3 + 2 * q] * ldw + col];
+    // U loads in flight per thread before their LDS writes (one at a time
+    // would put a memory latency per element on the chain)
+    constexpr int U = 8;
+    for (int e0 = threadIdx.x; e0 < count * CW; e0 += 256 * U) {
+        T v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * 256;
+            const int q = e / CW, lc = lc0 + e % CW;
+            v[u] = (T)0;
+            if (e < count * CW && lc < ncols)
+                v[u] = W[(size_t)smv[2 * q + 1] * ldw + c0 + lc + (lc >= nleft ? gap : 0)];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * 256;
+            if (e < count * CW) buf[e] = v[u];
         }
     }
     __syncthreads();
     for (int e = threadIdx.x; e < count * CW; e += 256) {
-        const int q = e / CW, cc = e % CW;
-        const int lc = lc0 + cc;
-        if (lc < ncols) {
-            const int col = c0 + lc + (lc >= nleft ? gap : 0);
-            W[(size_t)moves[2 + 2 * q] * ldw + col] = buf[e];
-        }
+        const int q = e / CW, lc = lc0 + e % CW;
+        if (lc < ncols) W[(size_t)smv[2 * q] * ldw + c0 + lc + (lc >= nleft ? gap : 0)] = buf[e];
     }
 }
 
@@ -834,7 +844,7 @@ hipError_t launch_row_swaps(const int *ipiv, int k0, int cnt, int npad, int *per
     if (cnt > kSwapsFused && moves) {
         // compose once, then apply in a second launch
         const size_t lds_c = (size_t)m * sizeof(int);
-        const size_t lds_a = (size_t)2 * cnt * CW * sizeof(T);
+        const size_t lds_a = (size_t)2 * cnt * (CW * sizeof(T) + 2 * sizeof(int));
         if (lds_c > kMaxLds - 24 * 1024 || lds_a > kMaxLds) return hipErrorInvalidValue;
         static bool attr2_done = false;
         if (!attr2_done) {
@@ -851,7 +861,7 @@ hipError_t launch_row_swaps(const int *ipiv, int k0, int cnt, int npad, int *per
         hipError_t e = hipGetLastError();
         if (e != hipSuccess || ncols <= 0) return e;
         k_rows_apply<T, CW><<<dim3((ncols + CW - 1) / CW), dim3(256), lds_a, s>>>(
-            W, ldw, moves, c0, nleft, gap, ncols);
+            W, ldw, moves, c0, nleft, gap, ncols, 2 * cnt);
         return hipGetLastError();
     }
     const size_t lds = align_up((size_t)(m + 4 * cnt + 4) * 4, 16) + (size_t)2 * cnt * CW * sizeof(T);
@@ -952,7 +962,7 @@ template <typename T, int CW>
 hipError_t rows_apply(T *W, int ldw, const int *moves, int cnt, int c0, int nleft, int gap,
                       int ncols, hipStream_t s) {
     constexpr size_t kMaxLds = 152 * 1024;
-    const size_t lds_a = (size_t)2 * cnt * CW * sizeof(T);
+    const size_t lds_a = (size_t)2 * cnt * (CW * sizeof(T) + 2 * sizeof(int));
     if (lds_a > kMaxLds) return hipErrorInvalidValue;
     static bool attr_done = false;
     if (!attr_done) {
@@ -961,8 +971,8 @@ hipError_t rows_apply(T *W, int ldw, const int *moves, int cnt, int c0, int nlef
         if (e != hipSuccess) return e;
         attr_done = true;
     }
-    k_rows_apply<T, CW><<<dim3((ncols + CW - 1) / CW), dim3(256), lds_a, s>>>(W, ldw, moves, c0,
-                                                                            nleft, gap, ncols);
+    k_rows_apply<T, CW><<<dim3((ncols + CW - 1) / CW), dim3(256), lds_a, s>>>(
+        W, ldw, moves, c0, nleft, gap, ncols, 2 * cnt);
     return hipGetLastError();
 }
 
@@ -1029,14 +1039,15 @@ __global__ __launch_bounds__(64) void k_trsm_diag_wide(const T *__restrict__ L, 
                                                        T *__restrict__ X, int ldx, int ncols) {
     __shared__ T sL[DB][DB + 1];
     const int t = threadIdx.x;
+    const int col = blockIdx.x * 64 + t;
+    // the column is requested before L is staged, so the two loads overlap
+    T x[DB];
+#pragma unroll
+    for (int i = 0; i < DB; ++i) x[i] = col < ncols ? X[(size_t)i * ldx + col] : (T)0;
     for (int i = 0; i < DB; ++i)
         for (int c = t; c < DB; c += 64) sL[i][c] = L[(size_t)i * ldl + c];
     __syncthreads();
-    const int col = blockIdx.x * 64 + t;
     if (col >= ncols) return;
-    T x[DB];
-#pragma unroll
-    for (int i = 0; i < DB; ++i) x[i] = X[(size_t)i * ldx + col];
 #pragma unroll
     for (int k = 0; k < DB; ++k) {
 #pragma unroll
